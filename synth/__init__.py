@@ -1,0 +1,149 @@
+"""Seeded synthetic inputs for the RI-PNOF7 hot path.
+
+This module draws random numbers and lays them out; it holds none of the
+method's arithmetic (no transform, no J/K build, no energy).  Both the HIP
+path (through the binding) and the CPU oracle consume what it returns.
+
+Workloads (shapes mimic the paper's cc-pVTZ-class molecules; the paper's own
+molecules, basis sets and integrals are not available, so these synthetic
+inputs stand in for them):
+
+  name     n_bf  n_aux  pairs  ncwo  n_omega  n_mo
+  tiny       48    192      5     1       10    48   (oracle-sized)
+  c6h12     348   1044     24     4      120   348   (cyclohexane-like)
+  c10h20    580   1740     40     4      200   580   (cyclodecane-like)
+  batch64   U{60..400}, 3*n_bf, n_bf//12, 2          (64 uneven molecules)
+  large    1000   3000     60     6      420  1000
+
+Recipe (draw order b -> C -> H -> ON, numpy ``default_rng(seed)``):
+  b[P] = (G_P + G_P^T)/2 * exp(-3P/n_aux),  G_P ~ N(0, 1/n_bf) i.i.d.
+  C    = Q of the QR factorisation of an n_bf x n_mo standard-normal matrix
+  H    = symmetric: upper triangle N(0,1), mirrored
+  ON   : per pair, strong ON ~ U(0.9, 0.99); each of the ncwo weak orbitals
+         of the pair gets (1 - strong)/ncwo, so every pair sums to exactly 1.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+__all__ = [
+    "Instance", "WORKLOADS", "default_pair_map", "make_instance", "make_b",
+    "rotation_sequence", "batch_sizes", "make_batch",
+]
+
+# name -> (n_bf, n_aux, n_pairs, n_cwo, seed)
+WORKLOADS = {
+    "tiny": (48, 192, 5, 1, 0),
+    "c6h12": (348, 1044, 24, 4, 1),
+    "c10h20": (580, 1740, 40, 4, 2),
+    "large": (1000, 3000, 60, 6, 4),
+}
+
+
+@dataclasses.dataclass
+class Instance:
+    """One molecule's worth of inputs.  All arrays are C-ordered float64/int32."""
+    n_bf: int
+    n_aux: int
+    n_pairs: int
+    n_cwo: int
+    n_mo: int
+    b: np.ndarray        # [n_aux][n_bf][n_bf], each slab symmetric
+    C: np.ndarray        # [n_bf][n_mo], orthonormal columns
+    H: np.ndarray        # [n_bf][n_bf], symmetric
+    occ: np.ndarray      # [n_omega]
+    pair_of: np.ndarray  # [n_omega] int32: pair index of each orbital in Omega
+    seed: int = 0
+
+    @property
+    def n_omega(self) -> int:
+        return self.n_pairs * (1 + self.n_cwo)
+
+
+def default_pair_map(n_pairs: int, n_cwo: int) -> np.ndarray:
+    """Orbital -> pair map of the electron-pairing scheme.
+
+    Orbitals 0..n_pairs-1 are the strong (doubly occupied in the HF limit)
+    orbitals; orbital g is the strong orbital of pair g.  The weak orbitals
+    of pair g are n_pairs + n_cwo*(n_pairs-1-g) + k, k = 0..n_cwo-1, so the
+    highest strong orbital couples to the lowest weak ones.
+    """
+    W = n_pairs * (1 + n_cwo)
+    pm = np.empty(W, dtype=np.int32)
+    pm[:n_pairs] = np.arange(n_pairs)
+    for g in range(n_pairs):
+        for k in range(n_cwo):
+            pm[n_pairs + n_cwo * (n_pairs - 1 - g) + k] = g
+    return pm
+
+
+def make_b(rng: np.random.Generator, n_bf: int, n_aux: int, out=None) -> np.ndarray:
+    """Three-index factors, drawn slab by slab to bound host memory."""
+    b = np.empty((n_aux, n_bf, n_bf), dtype=np.float64) if out is None else out
+    s = 1.0 / math.sqrt(n_bf)
+    for P in range(n_aux):
+        G = rng.standard_normal((n_bf, n_bf))
+        G *= s
+        np.add(G, G.T, out=b[P])
+        b[P] *= 0.5 * math.exp(-3.0 * P / n_aux)
+    return b
+
+
+def make_instance(n_bf: int, n_aux: int, n_pairs: int, n_cwo: int, seed: int,
+                  n_mo: int | None = None, strong_range=(0.9, 0.99)) -> Instance:
+    n_mo = n_bf if n_mo is None else n_mo
+    W = n_pairs * (1 + n_cwo)
+    if W > n_mo or n_mo > n_bf:
+        raise ValueError("need n_omega <= n_mo <= n_bf")
+    rng = np.random.default_rng(seed)
+    b = make_b(rng, n_bf, n_aux)
+    X = rng.standard_normal((n_bf, n_mo))
+    C, _ = np.linalg.qr(X)
+    C = np.ascontiguousarray(C)
+    Hx = rng.standard_normal((n_bf, n_bf))
+    H = np.triu(Hx) + np.triu(Hx, 1).T
+    strong = rng.uniform(strong_range[0], strong_range[1], size=n_pairs)
+    pair_of = default_pair_map(n_pairs, n_cwo)
+    occ = np.empty(W, dtype=np.float64)
+    occ[:n_pairs] = strong
+    for i in range(n_pairs, W):
+        occ[i] = (1.0 - strong[pair_of[i]]) / n_cwo
+    return Instance(n_bf, n_aux, n_pairs, n_cwo, n_mo, b, C, np.ascontiguousarray(H),
+                    occ, pair_of, seed)
+
+
+def workload(name: str) -> Instance:
+    n_bf, n_aux, n_pairs, n_cwo, seed = WORKLOADS[name]
+    return make_instance(n_bf, n_aux, n_pairs, n_cwo, seed)
+
+
+def rotation_sequence(C0: np.ndarray, n_iter: int, base_seed: int = 1000,
+                      scale: float = 0.01) -> list:
+    """Orbitals of a fixed-rotation sequence: C_{it+1} = C_it expm(kappa_it),
+    kappa_it = scale*(X - X^T)/2 with X ~ N(0,1) from seed base_seed+it.
+    Returns [C_0, C_1, ..., C_{n_iter-1}] (C_0 is the input)."""
+    from scipy.linalg import expm
+    n = C0.shape[1]
+    out = [np.ascontiguousarray(C0)]
+    C = C0
+    for it in range(n_iter - 1):
+        X = np.random.default_rng(base_seed + it).standard_normal((n, n))
+        kappa = scale * 0.5 * (X - X.T)
+        C = np.ascontiguousarray(C @ expm(kappa))
+        out.append(C)
+    return out
+
+
+def batch_sizes(n_inst: int = 64, seed: int = 3, lo: int = 60, hi: int = 400) -> np.ndarray:
+    """n_bf of each molecule of the uneven batch, uniform on {lo..hi}."""
+    return np.random.default_rng(seed).integers(lo, hi + 1, size=n_inst)
+
+
+def make_batch(n_inst: int = 64, seed: int = 3, base: int = 3000, n_cwo: int = 2,
+               lo: int = 60, hi: int = 400) -> list:
+    """Uneven batch: n_aux = 3 n_bf, pairs = n_bf // 12, per-instance seed base+i."""
+    return [make_instance(int(nb), 3 * int(nb), int(nb) // 12, n_cwo, base + i)
+            for i, nb in enumerate(batch_sizes(n_inst, seed, lo, hi))]
