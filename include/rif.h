@@ -1,0 +1,154 @@
+/*
+ * rif.h -- C ABI of the RI-PNOF7 hot-path library (librif.so) for MI355X (gfx950).
+ *
+ * The library implements the per-iteration density-fitted tensor work of
+ * PNOF7 with the resolution-of-the-identity (RI) approximation: the AO->MO
+ * transforms of the three-index factors b^l_{mu nu} (Eqs. (12)-(13)), the MO
+ * Coulomb and exchange matrices J_pq, K_pq (Eqs. (10)-(11), Table 2 step 4),
+ * the per-MO AO Coulomb and exchange matrices J^q, K^q (Table 3 steps 3-4),
+ * and the PNOF energy (Eq. (2)) with the orbital Lagrangian and gradient
+ * needed by the orbital optimisation (Sec. II, "Orbital Optimization with RI").
+ *
+ * Conventions shared by every entry point
+ *   - Arrays are row-major (C order).  Index names: l = auxiliary function
+ *     (n_aux), mu/nu = AO (n_bf), p/q/r = orbital of the pairing scheme Omega
+ *     (n_omega), a = any MO (n_mo).  Omega is the first n_omega columns of C.
+ *   - Every array argument is a DEVICE pointer owned by the caller.  The
+ *     library never frees caller memory; its own scratch lives in the context.
+ *   - Calls are asynchronous on the context's stream; the caller synchronises
+ *     (rif_sync or its own stream sync) before reading results on the host.
+ *   - Errors are returned as status codes; nothing aborts and no exception
+ *     crosses the ABI.  rif_last_error() returns the message of the last
+ *     failing call on that context.  Shape and pointer checks happen on the
+ *     host before any launch; checks that need device data (occupation
+ *     numbers) run on the device and are reported by the next rif_sync().
+ *   - One context per host thread.  b is assumed symmetric in (mu, nu) for
+ *     every l (Eq. (9) produces such a factor); this is not checked.
+ *   - Precision: RIF_FP64 computes everything in FP64.  The other modes run the
+ *     GEMM-shaped contractions on lower-precision MFMA (FP32, or BF16/FP16
+ *     pieces split from the FP64 operands) with FP32 accumulation recombined
+ *     in FP64; J_pq/K_pq sums over l, the energy, the Lagrangian and its
+ *     antisymmetrisation stay FP64.  In those modes b_half, b_mo, Jn and Kn
+ *     are FP32 arrays (4 bytes per element) instead of FP64.
+ */
+#ifndef RIF_H
+#define RIF_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rif_ctx rif_ctx;
+
+typedef enum {
+  RIF_OK = 0,
+  RIF_EINVAL = -1,  /* bad shape, NULL pointer, invalid occupations */
+  RIF_ENOMEM = -2,  /* workspace allocation failed or exceeds the cap */
+  RIF_EHIP = -3,    /* a HIP runtime call or kernel launch failed */
+  RIF_ENOTSUP = -4  /* precision or feature not available */
+} rif_status;
+
+typedef enum {
+  RIF_FP64 = 0,
+  RIF_FP32 = 1,
+  RIF_BF16X3 = 2,   /* two bf16 pieces, three products */
+  RIF_BF16X6 = 3,   /* three bf16 pieces, six products */
+  RIF_FP16X3 = 4    /* fp16 high piece + scaled fp16 low piece, three products */
+} rif_prec;
+
+typedef enum { RIF_PNOF7 = 0, RIF_PNOF5 = 1 } rif_functional;
+
+/* Create a context on HIP device `hip_device`.  `hip_stream` is a hipStream_t
+ * to launch on (e.g. the caller's current stream); NULL makes the context
+ * create and own a default-priority stream.  Returns RIF_EINVAL for a bad
+ * device, RIF_EHIP if the runtime fails. */
+rif_status rif_create(rif_ctx **out, int hip_device, void *hip_stream);
+void rif_destroy(rif_ctx *ctx);
+/* Message of the last failing call ("" if none).  Owned by the context. */
+const char *rif_last_error(const rif_ctx *ctx);
+/* Replace the stream later calls launch on (NULL = the context's own). */
+rif_status rif_set_stream(rif_ctx *ctx, void *hip_stream);
+/* Wait for the context's stream, then report any deferred device-side
+ * validation error (RIF_EINVAL with a message) and clear it. */
+rif_status rif_sync(rif_ctx *ctx);
+/* Cap on the context's workspace in bytes (0 = no cap).  A call that would
+ * need more returns RIF_ENOMEM. */
+rif_status rif_set_workspace_limit(rif_ctx *ctx, unsigned long long bytes);
+
+/* Half- and full-MO transforms: Eqs. (12)-(13); Table 2 steps 2-3 and
+ * Table 3 steps 2-3 (Coulomb branch).
+ *   b      [n_aux][n_bf][n_bf]  FP64, each slab symmetric          (in)
+ *   C      [n_bf][n_mo]         FP64 MO coefficients              (in)
+ *   b_half [n_omega][n_aux][n_bf]  b^l_{q nu} = sum_mu C_{mu q} b^l_{mu nu}   (out)
+ *   b_mo   [n_aux][n_omega][n_omega] b^l_{pq} = sum_nu C_{nu q} b^l_{p nu}   (out)
+ *   d      [n_aux][n_omega]     FP64 diagonal d[l][q] = b^l_{qq}   (out)
+ * b_half and b_mo are FP64 for RIF_FP64, FP32 otherwise.
+ * Requires 0 < n_omega <= n_mo <= n_bf, n_aux > 0. */
+rif_status rif_transform(rif_ctx *ctx, int n_bf, int n_aux, int n_omega, int n_mo,
+                         const double *b, const double *C, rif_prec prec,
+                         void *b_half, void *b_mo, double *d);
+
+/* MO Coulomb and exchange matrices: Eqs. (10)-(11); Table 2 step 4.
+ *   b_mo [n_aux][n_omega][n_omega] (FP64 or FP32 as produced by rif_transform)
+ *   d    [n_aux][n_omega] FP64
+ *   J, K [n_omega][n_omega] FP64:  J_pq = sum_l d[l][p] d[l][q],  K_pq = sum_l (b^l_pq)^2
+ * The sums over l are FP64 in every mode and deterministic (fixed order). */
+rif_status rif_jk_mo(rif_ctx *ctx, int n_aux, int n_omega, const void *b_mo, const double *d,
+                     rif_prec prec, double *J, double *K);
+
+/* Per-MO AO Coulomb and exchange matrices: Table 3 steps 3-4.
+ *   b      [n_aux][n_bf][n_bf] FP64          (in)
+ *   b_half [n_omega][n_aux][n_bf]            (in, as produced by rif_transform)
+ *   d      [n_aux][n_omega] FP64             (in)
+ *   Jn     [n_omega][n_bf][n_bf]  J^q_{mu nu} = sum_l b^l_qq b^l_{mu nu}      (out)
+ *   Kn     [n_omega][n_bf][n_bf]  K^q_{mu nu} = sum_l b^l_{q mu} b^l_{q nu}   (out)
+ * Jn and Kn are written in full and are exactly symmetric; FP64 for RIF_FP64,
+ * FP32 otherwise. */
+rif_status rif_jk_ao_per_mo(rif_ctx *ctx, int n_bf, int n_aux, int n_omega,
+                            const double *b, const void *b_half, const double *d,
+                            rif_prec prec, void *Jn, void *Kn);
+
+/* PNOF energy (Eq. (2) with L = K) and orbital Lagrangian / gradient.
+ *   pair_of [n_omega] int32 pair index of each orbital of Omega; orbital g
+ *           (g < n_pairs) must be the strong orbital of pair g and each pair
+ *           must hold exactly 1 + n_cwo orbitals.  NULL selects the default
+ *           map: weak orbitals of pair g are n_pairs + n_cwo*(n_pairs-1-g) + k.
+ *   H  [n_bf][n_bf] FP64 core Hamiltonian; C [n_bf][n_mo]; occ [n_omega] FP64 ONs
+ *   J, K [n_omega][n_omega] FP64 (from rif_jk_mo); Jn, Kn from rif_jk_ao_per_mo
+ *   energy  device FP64 scalar: 2 sum_p n_p H_pp + sum_pq (A_pq J_pq + B_pq K_pq)
+ *   lambda  [n_mo][n_omega] FP64: lambda_aq = c_a^T F^(q) c_q with
+ *           F^(q) = n_q H + sum_r (A_qr J^r + B_qr K^r)
+ *   grad    [n_mo][n_mo] FP64: G = 4 (lambda - lambda^T), lambda zero-padded
+ *           to n_mo columns; G_ab = dE/dtheta along C -> C exp(theta (E_ab - E_ba)).
+ * A and B follow from the functional's Delta and Pi: within a pair A = 0 and
+ * B = Pi (Pi_pp = n_p, +sqrt(n_p n_q) for two weak orbitals, -sqrt(n_p n_q)
+ * with the strong one); between pairs A = 2 n_p n_q and
+ * B = -n_p n_q - Phi_p Phi_q, Phi_p = sqrt(n_p (1 - n_p)) (PNOF7; PNOF5 has no
+ * Phi term).  Host-side checks: n_omega = n_pairs (1 + n_cwo) <= n_mo <= n_bf.
+ * Device-side checks (reported by rif_sync): 0 <= n_p <= 1, per-pair sums
+ * within 1e-12 of 1, a valid pair map. */
+rif_status pnof7_energy_grad(rif_ctx *ctx, int n_bf, int n_mo, int n_pairs, int n_cwo,
+                             const int *pair_of, const double *H, const double *C,
+                             const double *occ, const double *J, const double *K,
+                             const void *Jn, const void *Kn, rif_prec prec,
+                             double *energy, double *lambda, double *grad);
+
+/* Same as pnof7_energy_grad with an explicit functional (RIF_PNOF7 or RIF_PNOF5). */
+rif_status pnof_energy_grad(rif_ctx *ctx, rif_functional functional, int n_bf, int n_mo,
+                            int n_pairs, int n_cwo, const int *pair_of, const double *H,
+                            const double *C, const double *occ, const double *J,
+                            const double *K, const void *Jn, const void *Kn, rif_prec prec,
+                            double *energy, double *lambda, double *grad);
+
+/* Per-kernel timing with HIP events on the context's stream.
+ * rif_profile_enable(ctx, 1) starts recording an event pair around every
+ * kernel launch; rif_profile_report synchronises, folds the pairs into
+ * per-kernel totals and writes "name launches total_ms\n" lines into buf
+ * (truncated to len bytes, NUL-terminated).  Enabling again clears totals. */
+rif_status rif_profile_enable(rif_ctx *ctx, int on);
+rif_status rif_profile_report(rif_ctx *ctx, char *buf, int len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RIF_H */

@@ -1,0 +1,233 @@
+"""RI-PNOF7 hot path on MI355X: Python binding of librif.so.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of librif.so.  PyTorch provides device memory and the stream; there
+is no CPU fallback -- if the library is missing or a tensor is not on the GPU
+the call raises.
+
+    import paper_2012_15662_amd as rif
+    ctx = rif.Context()                       # launches on torch's current stream
+    out = ctx.build(b, C, H, occ, pair_of, n_pairs, n_cwo)   # all steps once
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "Context", "RifError", "load_library", "LIB_PATH", "FP64", "FP32", "BF16X3", "BF16X6",
+    "FP16X3", "PNOF7", "PNOF5", "EXPORTS",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librif.so")
+
+FP64, FP32, BF16X3, BF16X6, FP16X3 = 0, 1, 2, 3, 4
+PNOF7, PNOF5 = 0, 1
+_STATUS = {0: "RIF_OK", -1: "RIF_EINVAL", -2: "RIF_ENOMEM", -3: "RIF_EHIP", -4: "RIF_ENOTSUP"}
+
+_vp, _i, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+# name -> (restype, argtypes); mirrors include/rif.h
+EXPORTS = {
+    "rif_create": (_i, [ctypes.POINTER(_vp), _i, _vp]),
+    "rif_destroy": (None, [_vp]),
+    "rif_last_error": (ctypes.c_char_p, [_vp]),
+    "rif_set_stream": (_i, [_vp, _vp]),
+    "rif_sync": (_i, [_vp]),
+    "rif_set_workspace_limit": (_i, [_vp, ctypes.c_ulonglong]),
+    "rif_transform": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _i, _vp, _vp, _vp]),
+    "rif_jk_mo": (_i, [_vp, _i, _i, _vp, _vp, _i, _vp, _vp]),
+    "rif_jk_ao_per_mo": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _vp]),
+    "pnof7_energy_grad": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i,
+                               _vp, _vp, _vp]),
+    "pnof_energy_grad": (_i, [_vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                              _i, _vp, _vp, _vp]),
+    "rif_profile_enable": (_i, [_vp, _i]),
+    "rif_profile_report": (_i, [_vp, ctypes.c_char_p, _i]),
+}
+
+_lib = None
+
+
+class RifError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def load_library(path: str = LIB_PATH):
+    """Load librif.so and declare its signatures.  Raises if it is not built."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run paper_2012_15662_amd/build.py "
+                          "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+def _ptr(t, name, dtype=None, numel=None):
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor on the GPU")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: tensor must be on the GPU (no CPU path exists)")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous (row-major)")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name}: needs at least {numel} elements, has {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One rif_ctx.  `stream`: a torch.cuda.Stream, a raw hipStream_t int, or
+    None for torch's current stream on `device`."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.lib = load_library()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        raw = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        h = ctypes.c_void_p()
+        st = self.lib.rif_create(ctypes.byref(h), device, ctypes.c_void_p(raw))
+        if st != 0:
+            raise RifError(st, "rif_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rif_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, st):
+        if st != 0:
+            raise RifError(st, self.lib.rif_last_error(self.h).decode())
+
+    # ---- plain ABI calls -------------------------------------------------
+    def sync(self):
+        self._chk(self.lib.rif_sync(self.h))
+
+    def set_workspace_limit(self, nbytes: int):
+        self._chk(self.lib.rif_set_workspace_limit(self.h, nbytes))
+
+    def transform(self, b, C, n_omega, prec=FP64, b_half=None, b_mo=None, d=None):
+        import torch
+        n_aux, n_bf, _ = b.shape
+        n_mo = C.shape[1]
+        dt = torch.float64 if prec == FP64 else torch.float32
+        dev = b.device
+        if b_half is None:
+            b_half = torch.empty((n_omega, n_aux, n_bf), dtype=dt, device=dev)
+        if b_mo is None:
+            b_mo = torch.empty((n_aux, n_omega, n_omega), dtype=dt, device=dev)
+        if d is None:
+            d = torch.empty((n_aux, n_omega), dtype=torch.float64, device=dev)
+        self._chk(self.lib.rif_transform(
+            self.h, n_bf, n_aux, n_omega, n_mo, _ptr(b, "b", torch.float64, n_aux * n_bf * n_bf),
+            _ptr(C, "C", torch.float64, n_bf * n_mo), prec,
+            _ptr(b_half, "b_half", dt, n_omega * n_aux * n_bf),
+            _ptr(b_mo, "b_mo", dt, n_aux * n_omega * n_omega),
+            _ptr(d, "d", torch.float64, n_aux * n_omega)))
+        return b_half, b_mo, d
+
+    def jk_mo(self, b_mo, d, prec=FP64, J=None, K=None):
+        import torch
+        n_aux, n_omega, _ = b_mo.shape
+        dt = torch.float64 if prec == FP64 else torch.float32
+        if J is None:
+            J = torch.empty((n_omega, n_omega), dtype=torch.float64, device=d.device)
+        if K is None:
+            K = torch.empty((n_omega, n_omega), dtype=torch.float64, device=d.device)
+        self._chk(self.lib.rif_jk_mo(
+            self.h, n_aux, n_omega, _ptr(b_mo, "b_mo", dt, n_aux * n_omega * n_omega),
+            _ptr(d, "d", torch.float64, n_aux * n_omega), prec,
+            _ptr(J, "J", torch.float64, n_omega * n_omega),
+            _ptr(K, "K", torch.float64, n_omega * n_omega)))
+        return J, K
+
+    def jk_ao_per_mo(self, b, b_half, d, prec=FP64, Jn=None, Kn=None):
+        import torch
+        n_aux, n_bf, _ = b.shape
+        n_omega = b_half.shape[0]
+        dt = torch.float64 if prec == FP64 else torch.float32
+        if Jn is None:
+            Jn = torch.empty((n_omega, n_bf, n_bf), dtype=dt, device=b.device)
+        if Kn is None:
+            Kn = torch.empty((n_omega, n_bf, n_bf), dtype=dt, device=b.device)
+        self._chk(self.lib.rif_jk_ao_per_mo(
+            self.h, n_bf, n_aux, n_omega, _ptr(b, "b", torch.float64, n_aux * n_bf * n_bf),
+            _ptr(b_half, "b_half", dt, n_omega * n_aux * n_bf),
+            _ptr(d, "d", torch.float64, n_aux * n_omega), prec,
+            _ptr(Jn, "Jn", dt, n_omega * n_bf * n_bf), _ptr(Kn, "Kn", dt, n_omega * n_bf * n_bf)))
+        return Jn, Kn
+
+    def energy_grad(self, H, C, occ, pair_of, n_pairs, n_cwo, J, K, Jn, Kn, prec=FP64,
+                    functional=PNOF7, energy=None, lam=None, grad=None):
+        import torch
+        n_bf, n_mo = C.shape
+        n_omega = n_pairs * (1 + n_cwo)
+        dev = C.device
+        dt = torch.float64 if prec == FP64 else torch.float32
+        if energy is None:
+            energy = torch.empty((1,), dtype=torch.float64, device=dev)
+        if lam is None:
+            lam = torch.empty((n_mo, n_omega), dtype=torch.float64, device=dev)
+        if grad is None:
+            grad = torch.empty((n_mo, n_mo), dtype=torch.float64, device=dev)
+        self._chk(self.lib.pnof_energy_grad(
+            self.h, functional, n_bf, n_mo, n_pairs, n_cwo,
+            _ptr(pair_of, "pair_of", torch.int32, n_omega), _ptr(H, "H", torch.float64, n_bf * n_bf),
+            _ptr(C, "C", torch.float64, n_bf * n_mo), _ptr(occ, "occ", torch.float64, n_omega),
+            _ptr(J, "J", torch.float64, n_omega * n_omega), _ptr(K, "K", torch.float64, n_omega * n_omega),
+            _ptr(Jn, "Jn", dt, n_omega * n_bf * n_bf), _ptr(Kn, "Kn", dt, n_omega * n_bf * n_bf), prec,
+            _ptr(energy, "energy", torch.float64, 1), _ptr(lam, "lambda", torch.float64, n_mo * n_omega),
+            _ptr(grad, "grad", torch.float64, n_mo * n_mo)))
+        return energy, lam, grad
+
+    # ---- one build: every hot-path step once -----------------------------
+    def build(self, b, C, H, occ, pair_of, n_pairs, n_cwo, prec=FP64, functional=PNOF7, out=None):
+        """Transform, J/K (MO), J^q/K^q (AO), energy, Lagrangian and gradient.
+        `out` (a dict from a previous call with the same shapes) is reused to
+        avoid allocations."""
+        n_omega = n_pairs * (1 + n_cwo)
+        o = out if out is not None else {}
+        o["b_half"], o["b_mo"], o["d"] = self.transform(b, C, n_omega, prec, o.get("b_half"),
+                                                        o.get("b_mo"), o.get("d"))
+        o["J"], o["K"] = self.jk_mo(o["b_mo"], o["d"], prec, o.get("J"), o.get("K"))
+        o["Jn"], o["Kn"] = self.jk_ao_per_mo(b, o["b_half"], o["d"], prec, o.get("Jn"), o.get("Kn"))
+        o["energy"], o["lam"], o["grad"] = self.energy_grad(
+            H, C, occ, pair_of, n_pairs, n_cwo, o["J"], o["K"], o["Jn"], o["Kn"], prec, functional,
+            o.get("energy"), o.get("lam"), o.get("grad"))
+        return o
+
+    # ---- per-kernel timing ------------------------------------------------
+    def profile(self, on: bool = True):
+        self._chk(self.lib.rif_profile_enable(self.h, 1 if on else 0))
+
+    def profile_report(self) -> dict:
+        buf = ctypes.create_string_buffer(1 << 16)
+        self._chk(self.lib.rif_profile_report(self.h, buf, len(buf)))
+        out = {}
+        for line in buf.value.decode().splitlines():
+            name, n, ms = line.split()
+            out[name] = (int(n), float(ms))
+        return out

@@ -1,0 +1,251 @@
+// C ABI of librif: context, validation, workspace, profiling, dispatch.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+
+#include "rif_internal.hpp"
+
+namespace rif {
+
+rif_status fail(rif_ctx* c, rif_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+rif_status ws_reserve(rif_ctx* c, size_t bytes) {
+  if (bytes <= c->ws_bytes) return RIF_OK;
+  if (c->ws_limit && bytes > c->ws_limit)
+    return fail(c, RIF_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes exceeds the limit of " +
+                                   std::to_string(c->ws_limit));
+  // the old arena may still be in use by queued kernels
+  if (c->ws) {
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, RIF_EHIP, "hipStreamSynchronize failed");
+    (void)hipFree(c->ws);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  size_t want = std::max(bytes, (size_t)1 << 20);
+  if (hipMalloc(&c->ws, want) != hipSuccess) {
+    (void)hipGetLastError();
+    c->ws = nullptr;
+    return fail(c, RIF_ENOMEM, "hipMalloc of " + std::to_string(want) + " workspace bytes failed");
+  }
+  c->ws_bytes = want;
+  return RIF_OK;
+}
+
+rif_status check_launch(rif_ctx* c, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, RIF_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  return RIF_OK;
+}
+
+ProfScope::ProfScope(rif_ctx* c_, const char* name) : c(c_) {
+  if (!c->prof) return;
+  auto get = [&]() {
+    hipEvent_t e;
+    if (!c->pool.empty()) {
+      e = c->pool.back();
+      c->pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      return (hipEvent_t) nullptr;
+    }
+    return e;
+  };
+  rif_ctx::Ev ev{name, get(), get()};
+  if (!ev.a || !ev.b) return;
+  hipEventRecord(ev.a, c->stream);
+  c->evs.push_back(ev);
+  idx = (int)c->evs.size() - 1;
+}
+
+ProfScope::~ProfScope() {
+  if (idx >= 0) hipEventRecord(c->evs[idx].b, c->stream);
+}
+
+}  // namespace rif
+
+using namespace rif;
+
+static bool dims_ok(long n) { return n > 0 && n < (1L << 30); }
+
+extern "C" {
+
+rif_status rif_create(rif_ctx** out, int dev, void* stream) {
+  if (!out) return RIF_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || dev < 0 || dev >= n) return RIF_EINVAL;
+  if (hipSetDevice(dev) != hipSuccess) return RIF_EHIP;
+  rif_ctx* c = new rif_ctx();
+  c->device = dev;
+  if (stream) {
+    c->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreate(&c->own_stream) != hipSuccess) {
+      delete c;
+      return RIF_EHIP;
+    }
+    c->stream = c->own_stream;
+  }
+  if (hipMalloc(&c->dflag, sizeof(int)) != hipSuccess || hipMemset(c->dflag, 0, sizeof(int)) != hipSuccess) {
+    if (c->own_stream) hipStreamDestroy(c->own_stream);
+    delete c;
+    return RIF_EHIP;
+  }
+  *out = c;
+  return RIF_OK;
+}
+
+void rif_destroy(rif_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  for (auto& e : c->evs) {
+    hipEventDestroy(e.a);
+    hipEventDestroy(e.b);
+  }
+  for (auto e : c->pool) hipEventDestroy(e);
+  if (c->ws) hipFree(c->ws);
+  if (c->dflag) hipFree(c->dflag);
+  if (c->own_stream) hipStreamDestroy(c->own_stream);
+  delete c;
+}
+
+const char* rif_last_error(const rif_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+rif_status rif_set_stream(rif_ctx* c, void* stream) {
+  if (!c) return RIF_EINVAL;
+  c->stream = stream ? (hipStream_t)stream : c->own_stream;
+  if (!c->stream) {
+    if (hipStreamCreate(&c->own_stream) != hipSuccess) return fail(c, RIF_EHIP, "hipStreamCreate failed");
+    c->stream = c->own_stream;
+  }
+  return RIF_OK;
+}
+
+rif_status rif_set_workspace_limit(rif_ctx* c, unsigned long long bytes) {
+  if (!c) return RIF_EINVAL;
+  c->ws_limit = (size_t)bytes;
+  return RIF_OK;
+}
+
+rif_status rif_sync(rif_ctx* c) {
+  if (!c) return RIF_EINVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, RIF_EHIP, "hipStreamSynchronize failed");
+  int flag = 0;
+  if (hipMemcpy(&flag, c->dflag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(c, RIF_EHIP, "reading the status word failed");
+  if (flag) {
+    if (hipMemset(c->dflag, 0, sizeof(int)) != hipSuccess) return fail(c, RIF_EHIP, "hipMemset failed");
+    std::string m = "invalid occupations:";
+    if (flag & kBadOcc) m += " an ON outside [0,1];";
+    if (flag & kBadSum) m += " a pair whose ONs do not sum to 1;";
+    if (flag & kBadMap) m += " a pair map entry out of range or a strong orbital g not in pair g;";
+    if (flag & kBadCount) m += " a pair without exactly 1 + n_cwo orbitals;";
+    return fail(c, RIF_EINVAL, m);
+  }
+  return RIF_OK;
+}
+
+rif_status rif_transform(rif_ctx* c, int nb, int na, int nw, int nmo, const double* b, const double* C,
+                         rif_prec prec, void* bh, void* bmo, double* d) {
+  if (!c) return RIF_EINVAL;
+  if (!dims_ok(nb) || !dims_ok(na) || !dims_ok(nw) || !dims_ok(nmo) || nw > nmo || nmo > nb)
+    return fail(c, RIF_EINVAL, "rif_transform: need 0 < n_omega <= n_mo <= n_bf and n_aux > 0");
+  if (!b || !C || !bh || !bmo || !d) return fail(c, RIF_EINVAL, "rif_transform: NULL pointer");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  if (prec != RIF_FP64) return fail(c, RIF_ENOTSUP, "rif_transform: precision mode not available");
+  rif_status st = f64_half_transform(c, nb, na, nw, nmo, b, C, (double*)bh);
+  if (st) return st;
+  return f64_mo_transform(c, nb, na, nw, nmo, (const double*)bh, C, (double*)bmo, d);
+}
+
+rif_status rif_jk_mo(rif_ctx* c, int na, int nw, const void* bmo, const double* d, rif_prec prec, double* J,
+                     double* K) {
+  if (!c) return RIF_EINVAL;
+  if (!dims_ok(na) || !dims_ok(nw)) return fail(c, RIF_EINVAL, "rif_jk_mo: need n_aux > 0 and n_omega > 0");
+  if (!bmo || !d || !J || !K) return fail(c, RIF_EINVAL, "rif_jk_mo: NULL pointer");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  if (prec != RIF_FP64) return fail(c, RIF_ENOTSUP, "rif_jk_mo: precision mode not available");
+  return f64_jk_mo(c, na, nw, (const double*)bmo, d, J, K);
+}
+
+rif_status rif_jk_ao_per_mo(rif_ctx* c, int nb, int na, int nw, const double* b, const void* bh,
+                            const double* d, rif_prec prec, void* Jn, void* Kn) {
+  if (!c) return RIF_EINVAL;
+  if (!dims_ok(nb) || !dims_ok(na) || !dims_ok(nw) || nw > nb)
+    return fail(c, RIF_EINVAL, "rif_jk_ao_per_mo: need 0 < n_omega <= n_bf and n_aux > 0");
+  if (!b || !bh || !d || !Jn || !Kn) return fail(c, RIF_EINVAL, "rif_jk_ao_per_mo: NULL pointer");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  if (prec != RIF_FP64) return fail(c, RIF_ENOTSUP, "rif_jk_ao_per_mo: precision mode not available");
+  return f64_jk_ao(c, nb, na, nw, b, (const double*)bh, d, (double*)Jn, (double*)Kn);
+}
+
+rif_status pnof_energy_grad(rif_ctx* c, rif_functional fn, int nb, int nmo, int npairs, int ncwo,
+                            const int* pair_of, const double* H, const double* C, const double* occ,
+                            const double* J, const double* K, const void* Jn, const void* Kn, rif_prec prec,
+                            double* energy, double* lambda, double* grad) {
+  if (!c) return RIF_EINVAL;
+  if (fn != RIF_PNOF7 && fn != RIF_PNOF5) return fail(c, RIF_EINVAL, "pnof_energy_grad: unknown functional");
+  if (!dims_ok(nb) || !dims_ok(nmo) || !dims_ok(npairs) || ncwo < 1 || ncwo > (1 << 20))
+    return fail(c, RIF_EINVAL, "pnof_energy_grad: need n_bf, n_mo, n_pairs > 0 and n_cwo >= 1");
+  const long nw = (long)npairs * (1 + ncwo);
+  if (nw > nmo || nmo > nb) return fail(c, RIF_EINVAL, "pnof_energy_grad: need n_pairs (1 + n_cwo) <= n_mo <= n_bf");
+  if (!H || !C || !occ || !J || !K || !Jn || !Kn || !energy || !lambda || !grad)
+    return fail(c, RIF_EINVAL, "pnof_energy_grad: NULL pointer");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  if (prec != RIF_FP64) return fail(c, RIF_ENOTSUP, "pnof_energy_grad: precision mode not available");
+  return f64_energy_grad(c, (int)fn, nb, nmo, npairs, ncwo, pair_of, H, C, occ, J, K, (const double*)Jn,
+                         (const double*)Kn, energy, lambda, grad);
+}
+
+rif_status pnof7_energy_grad(rif_ctx* c, int nb, int nmo, int npairs, int ncwo, const int* pair_of,
+                             const double* H, const double* C, const double* occ, const double* J,
+                             const double* K, const void* Jn, const void* Kn, rif_prec prec, double* energy,
+                             double* lambda, double* grad) {
+  return pnof_energy_grad(c, RIF_PNOF7, nb, nmo, npairs, ncwo, pair_of, H, C, occ, J, K, Jn, Kn, prec, energy,
+                          lambda, grad);
+}
+
+rif_status rif_profile_enable(rif_ctx* c, int on) {
+  if (!c) return RIF_EINVAL;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, RIF_EHIP, "hipStreamSynchronize failed");
+  for (auto& e : c->evs) {
+    c->pool.push_back(e.a);
+    c->pool.push_back(e.b);
+  }
+  c->evs.clear();
+  c->totals.clear();
+  c->prof = on != 0;
+  return RIF_OK;
+}
+
+rif_status rif_profile_report(rif_ctx* c, char* buf, int len) {
+  if (!c || !buf || len <= 0) return RIF_EINVAL;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, RIF_EHIP, "hipStreamSynchronize failed");
+  for (auto& e : c->evs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e.a, e.b) != hipSuccess) ms = 0.f;
+    auto it = std::find_if(c->totals.begin(), c->totals.end(), [&](const rif_ctx::Tot& t) { return t.name == e.name; });
+    if (it == c->totals.end()) c->totals.push_back({e.name, 1, (double)ms});
+    else { it->launches += 1; it->ms += ms; }
+    c->pool.push_back(e.a);
+    c->pool.push_back(e.b);
+  }
+  c->evs.clear();
+  std::string s;
+  char line[160];
+  for (auto& t : c->totals) {
+    snprintf(line, sizeof line, "%s %ld %.6f\n", t.name.c_str(), t.launches, t.ms);
+    s += line;
+  }
+  strncpy(buf, s.c_str(), (size_t)len - 1);
+  buf[len - 1] = 0;
+  return RIF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,76 @@
+// Internal context, workspace arena and launch helpers of librif.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "rif.h"
+
+struct rif_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;
+  std::string err;
+  // workspace arena: one device allocation, grown on demand
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t ws_limit = 0;
+  int* dflag = nullptr;       // device status word for device-side validation
+  // profiling
+  bool prof = false;
+  struct Ev { const char* name; hipEvent_t a, b; };
+  std::vector<Ev> evs;        // recorded pairs, not yet folded
+  std::vector<hipEvent_t> pool;
+  struct Tot { std::string name; long launches; double ms; };
+  std::vector<Tot> totals;
+};
+
+namespace rif {
+
+// Bits of the device status word set by device-side validation.
+enum : int { kBadOcc = 1, kBadSum = 2, kBadMap = 4, kBadCount = 8 };
+
+// Fails the current call with a message.
+rif_status fail(rif_ctx* c, rif_status s, const std::string& msg);
+// Ensures the arena holds at least `bytes`; returns RIF_OK or RIF_ENOMEM/RIF_EHIP.
+rif_status ws_reserve(rif_ctx* c, size_t bytes);
+
+// Carves aligned sub-buffers from the arena.
+struct Carve {
+  size_t off = 0;
+  template <class T>
+  size_t take(size_t n) {
+    size_t o = (off + 255) & ~size_t(255);
+    off = o + n * sizeof(T);
+    return o;
+  }
+};
+
+// Event-pair bracket around a launch when profiling is on.
+struct ProfScope {
+  rif_ctx* c;
+  int idx = -1;
+  ProfScope(rif_ctx* c_, const char* name);
+  ~ProfScope();
+};
+
+rif_status check_launch(rif_ctx* c, const char* what);
+
+// ---- FP64 launchers (kernels_f64.hip) ----
+// All pointers are device pointers; shapes already validated.
+rif_status f64_half_transform(rif_ctx* c, int nb, int na, int nw, int nmo, const double* b,
+                              const double* C, double* bh);
+rif_status f64_mo_transform(rif_ctx* c, int nb, int na, int nw, int nmo, const double* bh,
+                            const double* C, double* bmo, double* d);
+rif_status f64_jk_mo(rif_ctx* c, int na, int nw, const double* bmo, const double* d, double* J,
+                     double* K);
+rif_status f64_jk_ao(rif_ctx* c, int nb, int na, int nw, const double* b, const double* bh,
+                     const double* d, double* Jn, double* Kn);
+rif_status f64_energy_grad(rif_ctx* c, int functional, int nb, int nmo, int npairs, int ncwo,
+                           const int* pair_of, const double* H, const double* C,
+                           const double* occ, const double* J, const double* K,
+                           const double* Jn, const double* Kn, double* energy, double* lambda,
+                           double* grad);
+
+}  // namespace rif
