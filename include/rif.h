@@ -140,6 +140,19 @@ rif_status pnof_energy_grad(rif_ctx *ctx, rif_functional functional, int n_bf, i
                             const double *K, const void *Jn, const void *Kn, rif_prec prec,
                             double *energy, double *lambda, double *grad);
 
+/* Tile-shape selection for the MFMA kernels.  Each GEMM-shaped kernel has up
+ * to four tile variants (0: 128x128, 1: 64x64, 2: 128x64, 3: 64x128 outputs
+ * per workgroup).  mode 0 picks one per shape with a wave-quantisation
+ * model; mode 1 (autotune) times every variant on the first call with a new
+ * shape -- synchronising the stream once -- and reuses the fastest for that
+ * shape afterwards.  Results are identical to FP64 rounding across variants. */
+rif_status rif_autotune(rif_ctx *ctx, int mode);
+/* Force variant v (0..3, clamped to what each kernel has) for every kernel;
+ * -1 returns to automatic selection. */
+rif_status rif_set_tile_variant(rif_ctx *ctx, int v);
+/* "kernel shape... -> variant | ms per variant" lines for every tuned shape. */
+rif_status rif_tune_report(rif_ctx *ctx, char *buf, int len);
+
 /* Per-kernel timing with HIP events on the context's stream.
  * rif_profile_enable(ctx, 1) starts recording an event pair around every
  * kernel launch; rif_profile_report synchronises, folds the pairs into

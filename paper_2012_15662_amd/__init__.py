@@ -42,6 +42,9 @@ EXPORTS = {
                                _vp, _vp, _vp]),
     "pnof_energy_grad": (_i, [_vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                               _i, _vp, _vp, _vp]),
+    "rif_autotune": (_i, [_vp, _i]),
+    "rif_set_tile_variant": (_i, [_vp, _i]),
+    "rif_tune_report": (_i, [_vp, ctypes.c_char_p, _i]),
     "rif_profile_enable": (_i, [_vp, _i]),
     "rif_profile_report": (_i, [_vp, ctypes.c_char_p, _i]),
 }
@@ -218,6 +221,18 @@ class Context:
             H, C, occ, pair_of, n_pairs, n_cwo, o["J"], o["K"], o["Jn"], o["Kn"], prec, functional,
             o.get("energy"), o.get("lam"), o.get("grad"))
         return o
+
+    # ---- tile selection ---------------------------------------------------
+    def autotune(self, on: bool = True):
+        self._chk(self.lib.rif_autotune(self.h, 1 if on else 0))
+
+    def set_tile_variant(self, v: int):
+        self._chk(self.lib.rif_set_tile_variant(self.h, v))
+
+    def tune_report(self) -> str:
+        buf = ctypes.create_string_buffer(1 << 16)
+        self._chk(self.lib.rif_tune_report(self.h, buf, len(buf)))
+        return buf.value.decode()
 
     # ---- per-kernel timing ------------------------------------------------
     def profile(self, on: bool = True):

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(Cfg::NT) void k_half_transform(int nb, long nr, int
   lb.init([&](int x) -> const double* {
     long r = r0 + x;
     return r < nr ? b + r * nb : nullptr;
-  }, nb);
+  }, b, nb);
   Acc<Cfg> acc;
   gemm_mainloop<Cfg>(la, lb, cdiv(nb, Cfg::BK), acc, smem);
   acc.for_each([&](int m, int n, double v) {
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(Cfg::NT) void k_mo_transform(int nb, int na, int nw
     if (s >= ns) return nullptr;
     const long l = s / nw, p = s - l * nw;
     return bh + p * AB + l * nb;
-  }, nb);
+  }, bh, nb);
   XCn<Cfg> lb;
   lb.init(C, nmo, nb, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
   Acc<Cfg> acc;
@@ -145,6 +145,12 @@ __global__ __launch_bounds__(256) void k_jk_mo_reduce(int nw, int nsplit, const 
 // M = q, N = a TMU x TNU block of (mu, nu), K = l.  Only blocks that touch the
 // upper triangle run; each writes (mu<=nu) directly and (mu<nu) mirrored, so
 // every element of the full matrix is written exactly once.
+// First block column of block row bi that holds an element with nu >= mu.
+__host__ __device__ __forceinline__ int jao_first_col(int bi, int tmu, int tnu) {
+  const int t = bi * tmu - (tnu - 1);
+  return t <= 0 ? 0 : (t + tnu - 1) / tnu;
+}
+
 template <class Cfg, int TNU>
 __global__ __launch_bounds__(Cfg::NT) void k_jao(int nb, int na, int nw, const double* __restrict__ b,
                                                  const double* __restrict__ d,
@@ -152,16 +158,23 @@ __global__ __launch_bounds__(Cfg::NT) void k_jao(int nb, int na, int nw, const d
   constexpr int TMU = Cfg::BN / TNU;
   __shared__ double smem[Cfg::SMEM_DOUBLES];
   const int nbj = (nb + TNU - 1) / TNU;
-  const long nbi = (nb + TMU - 1) / TMU;
+  const int nbi = (nb + TMU - 1) / TMU;
   const long nq = (nw + Cfg::BM - 1) / Cfg::BM;
-  // logical tile: q-tile fastest so tiles sharing a b block sit on one XCD
+  // The grid enumerates only blocks that touch the upper triangle, q-tile
+  // fastest, so the XCD remap spreads equal work over the XCDs and q-tiles
+  // that share a b block run on one XCD.
   const long t = xcd_remap(blockIdx.x, (long)gridDim.x);
   const int qt = (int)(t % nq);
-  const long blk = t / nq;
-  const int bi = (int)(blk / nbj), bj = (int)(blk % nbj);
+  long a = t / nq;
+  int bi = 0;
+  for (; bi < nbi; ++bi) {
+    const int n = nbj - jao_first_col(bi, TMU, TNU);
+    if (a < n) break;
+    a -= n;
+  }
   if (bi >= nbi) return;
+  const int bj = jao_first_col(bi, TMU, TNU) + (int)a;
   const int mu0 = bi * TMU, nu0 = bj * TNU;
-  if (nu0 + TNU - 1 < mu0) return;  // strictly lower block: written by its mirror
   const int q0 = qt * Cfg::BM;
   const long B2 = (long)nb * nb;
   XC<Cfg> la;
@@ -245,40 +258,19 @@ __device__ __forceinline__ int pair_index(const int* pair_of, int p, int npairs,
 }
 
 // Coefficients A, B of E = 2 sum n_p H_pp + sum (A J + B K) (Eq. (2), PNOF7 or
-// PNOF5 Delta/Pi), the diagonal H_pp from HC = H C_Omega, the energy (fixed
-// tree order) and the device-side validation of the occupations.
-// One workgroup of 256 threads.
-__global__ __launch_bounds__(256) void k_coef_energy(int functional, int nw, int npairs, int ncwo,
-                                                     int nb, int nmo, const int* __restrict__ pair_of,
-                                                     const double* __restrict__ occ,
-                                                     const double* __restrict__ C,
-                                                     const double* __restrict__ HC,
-                                                     const double* __restrict__ J,
-                                                     const double* __restrict__ K,
-                                                     double* __restrict__ Ac, double* __restrict__ Bc,
-                                                     double* __restrict__ energy, int* __restrict__ flag) {
+// PNOF5 Delta/Pi), with one energy partial per workgroup (fixed order).
+__global__ __launch_bounds__(256) void k_coef(int functional, int nw, int npairs, int ncwo,
+                                              const int* __restrict__ pair_of,
+                                              const double* __restrict__ occ,
+                                              const double* __restrict__ J, const double* __restrict__ K,
+                                              double* __restrict__ Ac, double* __restrict__ Bc,
+                                              double* __restrict__ epart) {
   __shared__ double red[256];
   const int tid = threadIdx.x;
-  int bad = 0;
-  for (int p = tid; p < nw; p += 256) {
-    const double n = occ[p];
-    if (!(n >= 0.0 && n <= 1.0)) bad |= kBadOcc;
-    const int g = pair_index(pair_of, p, npairs, ncwo);
-    if (g < 0 || g >= npairs || (p < npairs && g != p)) bad |= kBadMap;
-  }
-  for (int g = tid; g < npairs; g += 256) {
-    double s = 0.0;
-    int cnt = 0;
-    for (int p = 0; p < nw; ++p)
-      if (pair_index(pair_of, p, npairs, ncwo) == g) { s += occ[p]; ++cnt; }
-    if (!(fabs(s - 1.0) <= 1e-12)) bad |= kBadSum;
-    if (cnt != 1 + ncwo) bad |= kBadCount;
-  }
-  if (bad) atomicOr(flag, bad);
-
-  double e = 0.0;
   const long w2 = (long)nw * nw;
-  for (long idx = tid; idx < w2; idx += 256) {
+  const long idx = (long)blockIdx.x * 256 + tid;
+  double e = 0.0;
+  if (idx < w2) {
     const int p = (int)(idx / nw), q = (int)(idx - (long)p * nw);
     const double np = occ[p], nq = occ[q];
     const int gp = pair_index(pair_of, p, npairs, ncwo), gq = pair_index(pair_of, q, npairs, ncwo);
@@ -295,12 +287,67 @@ __global__ __launch_bounds__(256) void k_coef_energy(int functional, int nw, int
     }
     Ac[idx] = a;
     Bc[idx] = bb;
-    e += a * J[idx] + bb * K[idx];
+    e = a * J[idx] + bb * K[idx];
   }
+  red[tid] = e;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) epart[blockIdx.x] = red[0];
+}
+
+// H_pp = c_p^T H c_p, the energy (coefficient partials + 2 sum n_p H_pp, fixed
+// order) and the device-side validation of the occupations.  One workgroup.
+__global__ __launch_bounds__(256) void k_energy(int nw, int npairs, int ncwo, int nb, int nmo, int nparts,
+                                                const int* __restrict__ pair_of,
+                                                const double* __restrict__ occ,
+                                                const double* __restrict__ C,
+                                                const double* __restrict__ HC,
+                                                const double* __restrict__ epart,
+                                                double* __restrict__ energy, int* __restrict__ flag) {
+  constexpr int kStage = 2048;
+  __shared__ double socc[kStage];
+  __shared__ int spair[kStage];
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  const bool staged = nw <= kStage;
+  if (staged) {
+    for (int p = tid; p < nw; p += 256) {
+      socc[p] = occ[p];
+      spair[p] = pair_index(pair_of, p, npairs, ncwo);
+    }
+  }
+  __syncthreads();
+  int bad = 0;
   for (int p = tid; p < nw; p += 256) {
+    const double n = staged ? socc[p] : occ[p];
+    if (!(n >= 0.0 && n <= 1.0)) bad |= kBadOcc;
+    const int g = staged ? spair[p] : pair_index(pair_of, p, npairs, ncwo);
+    if (g < 0 || g >= npairs || (p < npairs && g != p)) bad |= kBadMap;
+  }
+  for (int g = tid; g < npairs; g += 256) {
+    double s = 0.0;
+    int cnt = 0;
+    for (int p = 0; p < nw; ++p) {
+      const int gp = staged ? spair[p] : pair_index(pair_of, p, npairs, ncwo);
+      if (gp == g) { s += staged ? socc[p] : occ[p]; ++cnt; }
+    }
+    if (!(fabs(s - 1.0) <= 1e-12)) bad |= kBadSum;
+    if (cnt != 1 + ncwo) bad |= kBadCount;
+  }
+  if (bad) atomicOr(flag, bad);
+
+  double e = 0.0;
+  for (int i = tid; i < nparts; i += 256) e += epart[i];
+  // H_pp: one wave per orbital, lanes over mu, fixed-order butterfly
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int p = wave; p < nw; p += 4) {
     double h = 0.0;
-    for (int mu = 0; mu < nb; ++mu) h = fma(C[(long)mu * nmo + p], HC[(long)mu * nw + p], h);
-    e += 2.0 * occ[p] * h;
+    for (int mu = lane; mu < nb; mu += 64) h = fma(C[(long)mu * nmo + p], HC[(long)mu * nw + p], h);
+    for (int off = 32; off > 0; off >>= 1) h += __shfl_xor(h, off, 64);
+    if (lane == 0) e += 2.0 * occ[p] * h;
   }
   red[tid] = e;
   __syncthreads();
@@ -319,6 +366,7 @@ template <class Cfg>
 struct FockA {  // element (mu, nu) of slab t; X_t symmetric so read row nu
   XCLoader<Cfg::BM, Cfg::BK, Cfg::NT> g;
   static constexpr int R = XCLoader<Cfg::BM, Cfg::BK, Cfg::NT>::R;
+  static constexpr int RR = R;
   const double *Jn, *Kn;
   int nb, nw, t0, nchunk, mu;
   bool ok;
@@ -333,10 +381,17 @@ struct FockA {  // element (mu, nu) of slab t; X_t symmetric so read row nu
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       const int nu = nu0 + g.kx + j * g.KSTEP;
-      r[j] = (ok && nu < nb) ? X[(long)nu * nb + mu] : 0.0;
+      r[j] = X[(long)(nu < nb ? nu : nb - 1) * nb + (ok ? mu : 0)];
     }
   }
-  __device__ void stash(double* S, const double (&r)[R]) const { g.stash(S, r); }
+  __device__ void stash(lds_f64* S, const double (&r)[R], int kt) const {
+    const int nu0 = (kt % nchunk) * Cfg::BK;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int nu = nu0 + g.kx + j * g.KSTEP;
+      S[(g.kx + j * g.KSTEP) * (Cfg::BM + kPadF64) + g.x] = (ok && nu < nb) ? r[j] : 0.0;
+    }
+  }
 };
 
 template <class Cfg>
@@ -353,16 +408,26 @@ struct FockB {  // element (q, nu) of slab t: coef_t[q] * C[nu][q]
     g.x = threadIdx.x % Cfg::BN; g.kx = threadIdx.x / Cfg::BN;
     q = q0 + g.x; ok = q < nw;
   }
-  __device__ void fetch(int kt, double (&r)[R]) const {
+  // r[0..R-1] = C elements, r[R] = the slab coefficient for this column
+  static constexpr int RR = R + 1;
+  __device__ void fetch(int kt, double (&r)[R + 1]) const {
     const int t = t0 + kt / nchunk, nu0 = (kt % nchunk) * Cfg::BK;
-    const double cf = ok ? (t < nw ? Ac[(long)q * nw + t] : Bc[(long)q * nw + (t - nw)]) : 0.0;
+    const int qc = ok ? q : 0;
+    r[R] = t < nw ? Ac[(long)qc * nw + t] : Bc[(long)qc * nw + (t - nw)];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       const int nu = nu0 + g.kx + j * g.KSTEP;
-      r[j] = (ok && nu < nb) ? cf * C[(long)nu * nmo + q] : 0.0;
+      r[j] = C[(long)(nu < nb ? nu : nb - 1) * nmo + qc];
     }
   }
-  __device__ void stash(double* S, const double (&r)[R]) const { g.stash(S, r); }
+  __device__ void stash(lds_f64* S, const double (&r)[R + 1], int kt) const {
+    const int nu0 = (kt % nchunk) * Cfg::BK;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int nu = nu0 + g.kx + j * g.KSTEP;
+      S[(g.kx + j * g.KSTEP) * (Cfg::BN + kPadF64) + g.x] = (ok && nu < nb) ? r[R] * r[j] : 0.0;
+    }
+  }
 };
 
 template <class Cfg>
@@ -412,26 +477,104 @@ __global__ __launch_bounds__(256) void k_grad(int nmo, int nw, const double* __r
 }
 
 // ---------------------------------------------------------------------------
-// Launchers
+// Launchers.  Each GEMM-shaped kernel exists in a few tile variants:
+//   0: 128x128 (4 waves of 64x64)   1: 64x64 (4 waves of 32x32)
+//   2: 128x64  (4 waves of 64x32)   3: 64x128 (4 waves of 32x64)
+// pick_variant() chooses one per (kernel, shape): a wave-quantisation
+// heuristic by default, or the fastest measured one when autotuning is on.
+
+using V0 = TileCfg<128, 128, 16, 64, 64>;
+using V1 = TileCfg<64, 64, 16, 32, 32>;
+using V2 = TileCfg<128, 64, 16, 64, 32>;
+using V3 = TileCfg<64, 128, 16, 32, 64>;
+
+// workgroups of each variant that fit on one CU (LDS-limited)
+static const int kWgPerCu[4] = {2, 4, 2, 2};
+static const int kTileM[4] = {128, 64, 128, 64};
+static const int kTileN[4] = {128, 64, 64, 128};
+
+// Relative time of a launch of `nwg` tiles of variant v: whole rounds of
+// 256*k concurrent tiles, each round as long as one tile at 1/k of a CU.
+static double est_cost(int v, long nwg, double useful) {
+  const long slots = 256L * kWgPerCu[v];
+  const long rounds = (nwg + slots - 1) / slots;
+  return (double)rounds * kTileM[v] * kTileN[v] * kWgPerCu[v] / useful;
+}
+
+template <class F>
+static decltype(auto) dispatch(int v, F&& f) {
+  switch (v) {
+    case 0: return f(V0());
+    case 1: return f(V1());
+    case 2: return f(V2());
+    default: return f(V3());
+  }
+}
+
+// ---- half transform
+template <class Cfg>
+static long half_tiles(int nb, int na, int nw) {
+  return (long)cdiv((long)na * nb, Cfg::BN) * cdiv(nw, Cfg::BM);
+}
+template <class Cfg>
+static void launch_half(rif_ctx* c, int nb, int na, int nw, int nmo, const double* b, const double* C,
+                        double* bh) {
+  const long nr = (long)na * nb;
+  dim3 grid(cdiv(nr, Cfg::BN), cdiv(nw, Cfg::BM));
+  hipLaunchKernelGGL(k_half_transform<Cfg>, grid, dim3(Cfg::NT), 0, c->stream, nb, nr, nw, nmo, b, C, bh);
+}
 
 rif_status f64_half_transform(rif_ctx* c, int nb, int na, int nw, int nmo, const double* b,
                               const double* C, double* bh) {
-  using Cfg = CfgL;
-  const long nr = (long)na * nb;
-  dim3 grid(cdiv(nr, Cfg::BN), cdiv(nw, Cfg::BM));
+  auto run = [&](int v) {
+    return dispatch(v, [&](auto cfg) {
+      launch_half<decltype(cfg)>(c, nb, na, nw, nmo, b, C, bh);
+      return check_launch(c, "half_transform");
+    });
+  };
+  double best = 1e300;
+  int hv = 0;
+  for (int v = 0; v < 4; ++v) {
+    const double useful = (double)nw / (cdiv(nw, kTileM[v]) * kTileM[v]);
+    const long n = dispatch(v, [&](auto cfg) { return half_tiles<decltype(cfg)>(nb, na, nw); });
+    const double e = est_cost(v, n, useful);
+    if (e < best) { best = e; hv = v; }
+  }
+  const int v = pick_variant(c, "half_transform", {nb, na, nw, nmo}, 4, hv, run);
+  if (v < 0) return RIF_EHIP;
   ProfScope ps(c, "half_transform");
-  hipLaunchKernelGGL(k_half_transform<Cfg>, grid, dim3(Cfg::NT), 0, c->stream, nb, nr, nw, nmo, b, C, bh);
-  return check_launch(c, "half_transform");
+  return run(v);
+}
+
+// ---- MO transform
+template <class Cfg>
+static void launch_mo(rif_ctx* c, int nb, int na, int nw, int nmo, const double* bh, const double* C,
+                      double* bmo, double* d) {
+  const long ns = (long)na * nw;
+  dim3 grid(cdiv(ns, Cfg::BM), cdiv(nw, Cfg::BN));
+  hipLaunchKernelGGL(k_mo_transform<Cfg>, grid, dim3(Cfg::NT), 0, c->stream, nb, na, nw, nmo, bh, C, bmo, d);
 }
 
 rif_status f64_mo_transform(rif_ctx* c, int nb, int na, int nw, int nmo, const double* bh,
                             const double* C, double* bmo, double* d) {
-  using Cfg = CfgL;
-  const long ns = (long)na * nw;
-  dim3 grid(cdiv(ns, Cfg::BM), cdiv(nw, Cfg::BN));
+  auto run = [&](int v) {
+    return dispatch(v, [&](auto cfg) {
+      launch_mo<decltype(cfg)>(c, nb, na, nw, nmo, bh, C, bmo, d);
+      return check_launch(c, "mo_transform");
+    });
+  };
+  double best = 1e300;
+  int hv = 0;
+  for (int v = 0; v < 4; ++v) {
+    const long n = (long)cdiv((long)na * nw, kTileM[v]) * cdiv(nw, kTileN[v]);
+    const double useful = (double)nw / (cdiv(nw, kTileN[v]) * kTileN[v]);
+    const double e = est_cost(v, n, useful);
+    if (e < best) { best = e; hv = v; }
+  }
+  const int v = pick_variant(c, "mo_transform", {nb, na, nw, nmo}, 4, hv, run);
+  if (v < 0) return RIF_EHIP;
   ProfScope ps(c, "mo_transform");
-  hipLaunchKernelGGL(k_mo_transform<Cfg>, grid, dim3(Cfg::NT), 0, c->stream, nb, na, nw, nmo, bh, C, bmo, d);
-  return check_launch(c, "mo_transform");
+  return run(v);
 }
 
 rif_status f64_jk_mo(rif_ctx* c, int na, int nw, const double* bmo, const double* d, double* J,
@@ -454,27 +597,66 @@ rif_status f64_jk_mo(rif_ctx* c, int na, int nw, const double* bmo, const double
   return check_launch(c, "jk_mo_reduce");
 }
 
+// ---- per-MO AO J and K
+template <class Cfg>
+static long jao_active(int nb, int nw) {  // tiles that touch the upper triangle
+  constexpr int TNU = 16, TMU = Cfg::BN / TNU;
+  long n = 0;
+  for (int bi = 0; bi < cdiv(nb, TMU); ++bi) n += std::max(0, cdiv(nb, TNU) - jao_first_col(bi, TMU, TNU));
+  return n * cdiv(nw, Cfg::BM);
+}
+
 rif_status f64_jk_ao(rif_ctx* c, int nb, int na, int nw, const double* b, const double* bh,
                      const double* d, double* Jn, double* Kn) {
   rif_status st;
+  auto runj = [&](int v) {
+    return dispatch(v, [&](auto cfg) {
+      using Cfg = decltype(cfg);
+      hipLaunchKernelGGL((k_jao<Cfg, 16>), dim3((unsigned)jao_active<Cfg>(nb, nw)), dim3(Cfg::NT), 0, c->stream,
+                         nb, na, nw, b, d, Jn);
+      return check_launch(c, "jao");
+    });
+  };
+  double best = 1e300;
+  int hv = 0;
+  for (int v = 0; v < 4; ++v) {
+    const long n = dispatch(v, [&](auto cfg) { return jao_active<decltype(cfg)>(nb, nw); });
+    const double useful = (double)nw / (cdiv(nw, kTileM[v]) * kTileM[v]);
+    const double e = est_cost(v, n, useful);
+    if (e < best) { best = e; hv = v; }
+  }
+  int v = pick_variant(c, "jao", {nb, na, nw}, 4, hv, runj);
+  if (v < 0) return RIF_EHIP;
   {
-    using Cfg = CfgL;
-    constexpr int TNU = 16;
-    constexpr int TMU = Cfg::BN / TNU;
-    const long nblk = (long)cdiv(nb, TMU) * cdiv(nb, TNU);
-    const long nq = cdiv(nw, Cfg::BM);
     ProfScope ps(c, "jao");
-    hipLaunchKernelGGL((k_jao<Cfg, TNU>), dim3((unsigned)(nblk * nq)), dim3(Cfg::NT), 0, c->stream, nb, na, nw, b, d, Jn);
+    if ((st = runj(v))) return st;
   }
-  if ((st = check_launch(c, "jao"))) return st;
-  {
-    using Cfg = CfgL;
-    const long nbk = cdiv(nb, Cfg::BM);
-    const long nblk = nbk * (nbk + 1) / 2;
-    ProfScope ps(c, "kao");
-    hipLaunchKernelGGL(k_kao<Cfg>, dim3((unsigned)(nblk * nw)), dim3(Cfg::NT), 0, c->stream, nb, na, nw, bh, Kn);
+  // K: square tiles only (variants 0 and 1)
+  auto runk = [&](int v) {
+    return dispatch(v, [&](auto cfg) {
+      using Cfg = decltype(cfg);
+      if constexpr (Cfg::BM == Cfg::BN) {
+        const long nbk = cdiv(nb, Cfg::BM);
+        hipLaunchKernelGGL(k_kao<Cfg>, dim3((unsigned)(nbk * (nbk + 1) / 2 * nw)), dim3(Cfg::NT), 0, c->stream,
+                           nb, na, nw, bh, Kn);
+        return check_launch(c, "kao");
+      } else {
+        return fail(c, RIF_ENOTSUP, "kao: non-square tile variant");
+      }
+    });
+  };
+  best = 1e300;
+  hv = 0;
+  for (int v2 = 0; v2 < 2; ++v2) {
+    const long nbk = cdiv(nb, kTileM[v2]);
+    const double useful = (double)nb * (nb + 1) / 2 / (nbk * (nbk + 1) / 2 * (double)kTileM[v2] * kTileM[v2]);
+    const double e = est_cost(v2, nbk * (nbk + 1) / 2 * nw, useful);
+    if (e < best) { best = e; hv = v2; }
   }
-  return check_launch(c, "kao");
+  v = pick_variant(c, "kao", {nb, na, nw}, 2, hv, runk);
+  if (v < 0) return RIF_EHIP;
+  ProfScope ps(c, "kao");
+  return runk(v);
 }
 
 rif_status f64_energy_grad(rif_ctx* c, int functional, int nb, int nmo, int npairs, int ncwo,
@@ -482,10 +664,10 @@ rif_status f64_energy_grad(rif_ctx* c, int functional, int nb, int nmo, int npai
                            const double* J, const double* K, const double* Jn, const double* Kn,
                            double* energy, double* lambda, double* grad) {
   const int nw = npairs * (1 + ncwo);
-  using CS = CfgS;
-  using CF = CfgS;
-  const int mt = cdiv(nb, CF::BM), nt = cdiv(nw, CF::BN);
+  using CS = V1;
   const int slabs = 2 * nw;
+  // split-K over the stacked slabs; sized so a variant-0/1 launch has >= 1024 tiles
+  const int mt = cdiv(nb, 64), nt = cdiv(nw, 64);
   int nsplit = std::max(1, std::min(slabs, cdiv(1024, (long)mt * nt)));
   const int per = cdiv(slabs, nsplit);
   nsplit = cdiv(slabs, per);
@@ -495,11 +677,13 @@ rif_status f64_energy_grad(rif_ctx* c, int functional, int nb, int nmo, int npai
   const size_t o_b = cv.take<double>((size_t)nw * nw);
   const size_t o_yp = cv.take<double>((size_t)nsplit * nb * nw);
   const size_t o_y = cv.take<double>((size_t)nb * nw);
+  const int nparts = cdiv((long)nw * nw, 256);
+  const size_t o_ep = cv.take<double>((size_t)nparts);
   rif_status st = ws_reserve(c, cv.off);
   if (st) return st;
   char* w = (char*)c->ws;
   double *HC = (double*)(w + o_hc), *Ac = (double*)(w + o_a), *Bc = (double*)(w + o_b);
-  double *Yp = (double*)(w + o_yp), *Y = (double*)(w + o_y);
+  double *Yp = (double*)(w + o_yp), *Y = (double*)(w + o_y), *Ep = (double*)(w + o_ep);
   {
     ProfScope ps(c, "hc_gemm");
     hipLaunchKernelGGL(k_gemm_tn<CS>, dim3(cdiv(nb, CS::BM), cdiv(nw, CS::BN)), dim3(CS::NT), 0, c->stream,
@@ -507,17 +691,39 @@ rif_status f64_energy_grad(rif_ctx* c, int functional, int nb, int nmo, int npai
   }
   if ((st = check_launch(c, "hc_gemm"))) return st;
   {
-    ProfScope ps(c, "coef_energy");
-    hipLaunchKernelGGL(k_coef_energy, dim3(1), dim3(256), 0, c->stream, functional, nw, npairs, ncwo, nb, nmo,
-                       pair_of, occ, C, HC, J, K, Ac, Bc, energy, c->dflag);
+    ProfScope ps(c, "coef");
+    hipLaunchKernelGGL(k_coef, dim3(nparts), dim3(256), 0, c->stream, functional, nw, npairs, ncwo, pair_of, occ,
+                       J, K, Ac, Bc, Ep);
   }
-  if ((st = check_launch(c, "coef_energy"))) return st;
+  if ((st = check_launch(c, "coef"))) return st;
+  {
+    ProfScope ps(c, "energy");
+    hipLaunchKernelGGL(k_energy, dim3(1), dim3(256), 0, c->stream, nw, npairs, ncwo, nb, nmo, nparts, pair_of, occ,
+                       C, HC, Ep, energy, c->dflag);
+  }
+  if ((st = check_launch(c, "energy"))) return st;
+  auto runf = [&](int v) {
+    return dispatch(v, [&](auto cfg) {
+      using Cfg = decltype(cfg);
+      hipLaunchKernelGGL(k_fock<Cfg>, dim3(cdiv(nb, Cfg::BM), cdiv(nw, Cfg::BN), nsplit), dim3(Cfg::NT), 0,
+                         c->stream, nb, nw, nmo, per, Jn, Kn, Ac, Bc, C, Yp);
+      return check_launch(c, "fock");
+    });
+  };
+  double best = 1e300;
+  int hv = 1;
+  for (int v = 0; v < 4; ++v) {
+    const long n = (long)cdiv(nb, kTileM[v]) * cdiv(nw, kTileN[v]) * nsplit;
+    const double useful = (double)nb * nw / (cdiv(nb, kTileM[v]) * kTileM[v] * (double)cdiv(nw, kTileN[v]) * kTileN[v]);
+    const double e = est_cost(v, n, useful);
+    if (e < best) { best = e; hv = v; }
+  }
+  const int v = pick_variant(c, "fock", {nb, nw, nmo, nsplit}, 4, hv, runf);
+  if (v < 0) return RIF_EHIP;
   {
     ProfScope ps(c, "fock");
-    hipLaunchKernelGGL(k_fock<CF>, dim3(mt, nt, nsplit), dim3(CF::NT), 0, c->stream, nb, nw, nmo, per, Jn, Kn,
-                       Ac, Bc, C, Yp);
+    if ((st = runf(v))) return st;
   }
-  if ((st = check_launch(c, "fock"))) return st;
   {
     ProfScope ps(c, "fock_reduce");
     hipLaunchKernelGGL(k_fock_reduce, dim3(cdiv((long)nb * nw, 256)), dim3(256), 0, c->stream, nb, nw, nsplit,

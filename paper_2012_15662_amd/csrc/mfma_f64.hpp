@@ -16,6 +16,9 @@
 namespace rif {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+// LDS pointer type: keeps ds_read/ds_write (a generic pointer would compile to
+// flat accesses, whose waits also drain the in-flight global prefetch).
+typedef __attribute__((address_space(3))) double lds_f64;
 
 constexpr int kPadF64 = 16;   // 128 B row padding: the 4 k-rows of a fragment land in distinct banks
 
@@ -27,6 +30,7 @@ struct XCLoader {
   static constexpr int KSTEP = NT / BX;
   static_assert(BK % KSTEP == 0, "BK must be a multiple of NT/BX");
   static constexpr int R = BK / KSTEP;
+  static constexpr int RR = R;  // registers staged per thread and slice
   const double* base;
   long ld;
   long xoff;
@@ -40,20 +44,27 @@ struct XCLoader {
     x = threadIdx.x % BX; kx = threadIdx.x / BX;
     long o = 0;
     ok = off(x, o);
-    xoff = o;
+    xoff = ok ? o : 0;  // absent columns read a valid element and mask it
   }
   // kt = slice index; this slice covers k in [kt*BK, kt*BK + BK).
   __device__ void fetch(int kt, double (&r)[R]) const {
     const int k0 = kt * BK;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-      int k = k0 + kx + j * KSTEP;
-      r[j] = (ok && k < kmax) ? base[(long)k * ld + xoff] : 0.0;
+      const int k = k0 + kx + j * KSTEP;
+      const int kc = k < kmax ? k : kmax - 1;
+      r[j] = base[(long)kc * ld + xoff];
     }
   }
-  __device__ void stash(double* S, const double (&r)[R]) const {
+  // Masks out-of-range elements while writing to LDS (after the MFMAs of the
+  // current slice), so the prefetch is not waited for any earlier.
+  __device__ void stash(lds_f64* S, const double (&r)[R], int kt) const {
+    const int k0 = kt * BK;
 #pragma unroll
-    for (int j = 0; j < R; ++j) S[(kx + j * KSTEP) * (BX + kPadF64) + x] = r[j];
+    for (int j = 0; j < R; ++j) {
+      const int k = k0 + kx + j * KSTEP;
+      S[(kx + j * KSTEP) * (BX + kPadF64) + x] = (ok && k < kmax) ? r[j] : 0.0;
+    }
   }
 };
 
@@ -66,16 +77,24 @@ struct KCLoader {
   static_assert(NT % TPR == 0 && BX % RSTEP == 0, "bad KC tiling");
   static constexpr int NP = BX / RSTEP;
   static constexpr int R = 2 * NP;
+  static constexpr int RR = R;
   const double* rp[NP];
+  unsigned valid;
   int kk, xr, kmax;
-  // rowptr(x) returns the row base pointer or nullptr if row x is outside the operand.
+  // rowptr(x) returns the row base pointer or nullptr if row x is outside the
+  // operand; `fallback` is any valid row, read in its place and masked.
   template <class RowPtr>
-  __device__ void init(RowPtr rowptr, int K) {
+  __device__ void init(RowPtr rowptr, const double* fallback, int K) {
     kk = 2 * (threadIdx.x % TPR);
     xr = threadIdx.x / TPR;
     kmax = K;
+    valid = 0;
 #pragma unroll
-    for (int p = 0; p < NP; ++p) rp[p] = rowptr(xr + p * RSTEP);
+    for (int p = 0; p < NP; ++p) {
+      const double* q = rowptr(xr + p * RSTEP);
+      valid |= (q != nullptr) << p;
+      rp[p] = q ? q : fallback;
+    }
   }
   __device__ void fetch(int kt, double (&r)[R]) const {
     const int k0 = kt * BK;
@@ -83,16 +102,21 @@ struct KCLoader {
     for (int p = 0; p < NP; ++p) {
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
-        int k = k0 + kk + v;
-        r[2 * p + v] = (rp[p] != nullptr && k < kmax) ? rp[p][k] : 0.0;
+        const int k = k0 + kk + v;
+        const int kc = k < kmax ? k : kmax - 1;
+        r[2 * p + v] = rp[p][kc];
       }
     }
   }
-  __device__ void stash(double* S, const double (&r)[R]) const {
+  __device__ void stash(lds_f64* S, const double (&r)[R], int kt) const {
+    const int k0 = kt * BK;
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
 #pragma unroll
-      for (int v = 0; v < 2; ++v) S[(kk + v) * (BX + kPadF64) + xr + p * RSTEP] = r[2 * p + v];
+      for (int v = 0; v < 2; ++v) {
+        const int k = k0 + kk + v;
+        S[(kk + v) * (BX + kPadF64) + xr + p * RSTEP] = ((valid >> p & 1) && k < kmax) ? r[2 * p + v] : 0.0;
+      }
     }
   }
 };
@@ -139,7 +163,7 @@ struct Acc {
 
 // One BK-deep slice of MFMA work from LDS buffers As[BK][LDA], Bs[BK][LDB].
 template <class Cfg>
-__device__ __forceinline__ void mma_slice(const double* __restrict__ As, const double* __restrict__ Bs,
+__device__ __forceinline__ void mma_slice(const lds_f64* __restrict__ As, const lds_f64* __restrict__ Bs,
                                           Acc<Cfg>& acc) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm0 = (wave / Cfg::WAVES_N) * Cfg::WM, wn0 = (wave % Cfg::WAVES_N) * Cfg::WN;
@@ -163,15 +187,16 @@ __device__ __forceinline__ void mma_slice(const double* __restrict__ As, const d
 // their own k offsets.  smem must hold Cfg::SMEM_DOUBLES doubles.
 template <class Cfg, class LA, class LB>
 __device__ __forceinline__ void gemm_mainloop(LA& la, LB& lb, int nk, Acc<Cfg>& acc, double* smem) {
-  double* As[2] = {smem, smem + Cfg::BK * Cfg::LDA};
-  double* Bs[2] = {smem + 2 * Cfg::BK * Cfg::LDA, smem + 2 * Cfg::BK * Cfg::LDA + Cfg::BK * Cfg::LDB};
-  double ra[LA::R], rb[LB::R];
+  lds_f64* L = (lds_f64*)smem;
+  lds_f64* As[2] = {L, L + Cfg::BK * Cfg::LDA};
+  lds_f64* Bs[2] = {L + 2 * Cfg::BK * Cfg::LDA, L + 2 * Cfg::BK * Cfg::LDA + Cfg::BK * Cfg::LDB};
+  double ra[LA::RR], rb[LB::RR];
   acc.zero();
   if (nk <= 0) return;
   la.fetch(0, ra);
   lb.fetch(0, rb);
-  la.stash(As[0], ra);
-  lb.stash(Bs[0], rb);
+  la.stash(As[0], ra, 0);
+  lb.stash(Bs[0], rb, 0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
@@ -182,8 +207,8 @@ __device__ __forceinline__ void gemm_mainloop(LA& la, LB& lb, int nk, Acc<Cfg>& 
     }
     mma_slice<Cfg>(As[cur], Bs[cur], acc);
     if (more) {
-      la.stash(As[cur ^ 1], ra);
-      lb.stash(Bs[cur ^ 1], rb);
+      la.stash(As[cur ^ 1], ra, kt + 1);
+      lb.stash(Bs[cur ^ 1], rb, kt + 1);
     }
     __syncthreads();
   }

@@ -42,6 +42,40 @@ rif_status check_launch(rif_ctx* c, const char* what) {
   return RIF_OK;
 }
 
+int pick_variant(rif_ctx* c, const char* kernel, std::initializer_list<long> shape, int nvar, int heuristic,
+                 const std::function<rif_status(int)>& run) {
+  if (c->force_variant >= 0) return std::min(c->force_variant, nvar - 1);
+  if (c->tune_mode == 0) return heuristic;
+  std::string key = kernel;
+  for (long v : shape) key += " " + std::to_string(v);
+  for (auto& t : c->tune)
+    if (t.key == key) return t.variant;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return -1;
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return -1; }
+  rif_ctx::Tune t{key, heuristic, std::vector<float>(nvar, -1.f)};
+  float best = 1e30f;
+  const bool prof = c->prof;
+  c->prof = false;
+  for (int v = 0; v < nvar; ++v) {
+    if (run(v) != RIF_OK) continue;  // warm-up; variants a kernel lacks report an error
+    (void)hipEventRecord(e0, c->stream);
+    for (int r = 0; r < 3; ++r) run(v);
+    (void)hipEventRecord(e1, c->stream);
+    if (hipEventSynchronize(e1) != hipSuccess) { c->prof = prof; return -1; }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    t.ms[v] = ms / 3;
+    if (t.ms[v] < best) { best = t.ms[v]; t.variant = v; }
+  }
+  c->prof = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->err.clear();
+  c->tune.push_back(t);
+  return t.variant;
+}
+
 ProfScope::ProfScope(rif_ctx* c_, const char* name) : c(c_) {
   if (!c->prof) return;
   auto get = [&]() {
@@ -209,6 +243,35 @@ rif_status pnof7_energy_grad(rif_ctx* c, int nb, int nmo, int npairs, int ncwo, 
                              double* lambda, double* grad) {
   return pnof_energy_grad(c, RIF_PNOF7, nb, nmo, npairs, ncwo, pair_of, H, C, occ, J, K, Jn, Kn, prec, energy,
                           lambda, grad);
+}
+
+rif_status rif_autotune(rif_ctx* c, int mode) {
+  if (!c || mode < 0 || mode > 1) return RIF_EINVAL;
+  c->tune_mode = mode;
+  return RIF_OK;
+}
+
+rif_status rif_set_tile_variant(rif_ctx* c, int v) {
+  if (!c || v < -1 || v > 3) return RIF_EINVAL;
+  c->force_variant = v;
+  return RIF_OK;
+}
+
+rif_status rif_tune_report(rif_ctx* c, char* buf, int len) {
+  if (!c || !buf || len <= 0) return RIF_EINVAL;
+  std::string s;
+  for (auto& t : c->tune) {
+    s += t.key + " -> " + std::to_string(t.variant) + " |";
+    char x[32];
+    for (float ms : t.ms) {
+      snprintf(x, sizeof x, " %.4f", ms);
+      s += x;
+    }
+    s += "\n";
+  }
+  strncpy(buf, s.c_str(), (size_t)len - 1);
+  buf[len - 1] = 0;
+  return RIF_OK;
 }
 
 rif_status rif_profile_enable(rif_ctx* c, int on) {

@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <functional>
+#include <initializer_list>
 #include <string>
 #include <vector>
 
@@ -24,6 +26,11 @@ struct rif_ctx {
   std::vector<hipEvent_t> pool;
   struct Tot { std::string name; long launches; double ms; };
   std::vector<Tot> totals;
+  // tile-variant selection
+  int tune_mode = 0;          // 0: heuristic, 1: measure every variant on first use of a shape
+  int force_variant = -1;     // >= 0: use this variant everywhere (clamped per kernel)
+  struct Tune { std::string key; int variant; std::vector<float> ms; };
+  std::vector<Tune> tune;
 };
 
 namespace rif {
@@ -56,6 +63,14 @@ struct ProfScope {
 };
 
 rif_status check_launch(rif_ctx* c, const char* what);
+
+// Chooses the tile variant of `kernel` for `shape`.  Forced variant if set;
+// else with autotuning on, the first call for a key times each of the `nvar`
+// variants through run(v) (every kernel overwrites its whole output, so the
+// trial launches are harmless) and caches the fastest; else `heuristic`.
+// Returns -1 if a trial launch failed.
+int pick_variant(rif_ctx* c, const char* kernel, std::initializer_list<long> shape, int nvar, int heuristic,
+                 const std::function<rif_status(int)>& run);
 
 // ---- FP64 launchers (kernels_f64.hip) ----
 // All pointers are device pointers; shapes already validated.

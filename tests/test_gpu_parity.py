@@ -160,3 +160,30 @@ def test_workspace_limit(ctx):
         c2.build(t["b"], t["C"], t["H"], t["occ"], t["pair_of"], inst.n_pairs, inst.n_cwo)
     assert e.value.status == -2
     c2.close()
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_every_tile_variant(ctx, variant):
+    """Each tile shape of every MFMA kernel, on a case with ragged tails in all dims."""
+    ctx.set_tile_variant(variant)
+    try:
+        run_and_compare(ctx, synth.make_instance(139, 157, 9, 3, 30 + variant))
+    finally:
+        ctx.set_tile_variant(-1)
+
+
+def test_autotune_picks_and_matches(ctx):
+    import paper_2012_15662_amd as rif
+    c2 = rif.Context()
+    c2.autotune(True)
+    inst = synth.make_instance(101, 230, 6, 4, 40)
+    t = to_dev(inst)
+    o = c2.build(t["b"], t["C"], t["H"], t["occ"], t["pair_of"], inst.n_pairs, inst.n_cwo)
+    c2.sync()
+    rep = c2.tune_report()
+    for k in ("half_transform", "mo_transform", "jao", "kao", "fock"):
+        assert k in rep, rep
+    ref = ri.build_instance(inst)
+    assert relerr(host(o["grad"]), ref["grad"]) < TOL
+    assert abs(float(host(o["energy"])[0]) - ref["energy"]) < TOL * abs(ref["energy"])
+    c2.close()
