@@ -25,6 +25,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "RI-PNOF7 J/K+gradient builds/s & TFLOP/s; split-prec vs FP64 at 1 µEh"
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0}   # dense MFMA TFLOP/s
+MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
+PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}   # MFMA products per multiply-add
+MODE_PEAK = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16"}
 HBM_GBS = 8000.0
 
 
@@ -66,6 +69,29 @@ def cpu_baseline(inst, Cs, budget_s=20.0):
             "sample": f"{n} full FP64 builds of the same workload (numpy oracle, rotated C), {el:.1f} s"}
 
 
+def time_builds(ctx, b, Cd, H, occ, pm, inst, prec, steps, warmup, profile=False):
+    """Warm up (autotunes tiles on first use), then time `steps` builds."""
+    import torch
+    out = None
+    for i in range(max(warmup, 1)):
+        out = ctx.build(b, Cd[i % len(Cd)], H, occ, pm, inst.n_pairs, inst.n_cwo, prec=prec, out=out)
+    ctx.sync()
+    if profile:
+        ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        out = ctx.build(b, Cd[i % len(Cd)], H, occ, pm, inst.n_pairs, inst.n_cwo, prec=prec, out=out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.sync()
+    prof = None
+    if profile:
+        prof = ctx.profile_report()
+        ctx.profile(False)
+    return el, out, prof
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +101,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-tune", action="store_true", help="heuristic tile shapes instead of autotuning")
+    ap.add_argument("--prec", default="fp64", choices=list(MODES))
+    ap.add_argument("--no-modes", action="store_true", help="skip timing the other precision modes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -98,21 +126,11 @@ def main():
     pm = torch.from_numpy(inst.pair_of.astype(np.int32)).to(dev)
     ctx = rif.Context(0)
     ctx.autotune(not args.no_tune)
-    out = None
-    for i in range(max(args.warmup, 1)):
-        out = ctx.build(b, Cd[i % len(Cd)], H, occ, pm, inst.n_pairs, inst.n_cwo, out=out)
+    el, out, prof = time_builds(ctx, b, Cd, H, occ, pm, inst, MODES[args.prec], args.steps, args.warmup,
+                                profile=True)
+    ref_out = ctx.build(b, Cd[0], H, occ, pm, inst.n_pairs, inst.n_cwo, prec=MODES[args.prec])
     ctx.sync()
-
-    ctx.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        out = ctx.build(b, Cd[i % len(Cd)], H, occ, pm, inst.n_pairs, inst.n_cwo, out=out)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ctx.sync()
-    prof = ctx.profile_report()
-    ctx.profile(False)
+    e_main = float(ref_out["energy"].cpu()[0])   # energy at the unrotated C
 
     kf = kernel_flops(nb, na, nw, nmo)
     per_kernel = {}
@@ -138,20 +156,37 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16"}[args.prec],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: n_bf={nb} n_aux={na} pairs={inst.n_pairs} "
                                f"ncwo={inst.n_cwo} n_omega={nw} n_mo={nmo}, 30 rotated C",
-                   "precision": "fp64"},
+                   "precision": args.prec},
         "tflops": round(flops * builds_s / 1e12, 3),
         "flops_per_build": flops,
         "roofline": {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 3),
-                     "peak": PEAK["f64"], "unit": "TFLOP/s", "frac": round(achieved / PEAK["f64"], 4),
+                     "peak": PEAK[MODE_PEAK[args.prec]], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK[MODE_PEAK[args.prec]], 4),
+                     "mfma_products_per_fma": PRODUCTS[args.prec],
                      "traffic": None},
         "kernels": per_kernel,
         "tiles": ctx.tune_report().strip().splitlines(),
-        "energy": float(out["energy"].cpu()[0]),
+        "energy_at_C0": e_main,
     }
+    if not args.no_modes:
+        # the other arithmetic modes on the same workload: speed-up over this
+        # run and energy difference to it (errors against the oracle are in the tests)
+        modes = {}
+        for name, pv in MODES.items():
+            if name == args.prec:
+                continue
+            n2 = max(5, args.steps // 2)
+            el2, _, _ = time_builds(ctx, b, Cd, H, occ, pm, inst, pv, n2, 2)
+            o2 = ctx.build(b, Cd[0], H, occ, pm, inst.n_pairs, inst.n_cwo, prec=pv)
+            ctx.sync()
+            modes[name] = {"builds_s": round(n2 / el2, 2), "speedup": round((n2 / el2) / builds_s, 3),
+                           "tflops": round(flops * n2 / el2 / 1e12, 2),
+                           "dE_vs_" + args.prec: float(o2["energy"].cpu()[0]) - e_main}
+        line["modes"] = modes
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(inst, Cs, args.cpu_budget)
     ctx.close()

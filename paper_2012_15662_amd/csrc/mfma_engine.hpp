@@ -1,0 +1,451 @@
+// MFMA tile engines for gfx950, one per arithmetic mode, behind one interface.
+//
+// A workgroup owns a BM x BN output tile and walks the reduction index in
+// BK-deep slices.  Operand slices go global -> registers -> LDS (double
+// buffered, one barrier per slice).  Waves are laid out (BM/WM) x (BN/WN); each
+// accumulates WM x WN with 16x16 MFMA blocks.  Kernels describe their operand
+// layouts with source loaders (XCSrc / KCSrc or their own) and read results
+// through Acc::for_each, which always yields FP64 values.
+//
+// Modes
+//   kF64    v_mfma_f64_16x16x4_f64, FP64 operands and accumulation.
+//   kF32    v_mfma_f32_16x16x4_f32 on operands rounded to FP32; FP32 partial
+//           sums are folded into FP64 accumulators every 128 k.
+//   kBF16x3 v_mfma_f32_16x16x32_bf16 on pieces split from each FP64 (or FP32)
+//           operand x = hi + lo (+ lo2) with hi = bf16(x), lo = bf16(x - hi),
+//           lo2 = bf16(x - hi - lo).  x3: hi.hi + (hi.lo + lo.hi);
+//   kBF16x6 x6 adds hi.lo2 + lo.lo + lo2.hi.  The hi.hi products and the cross
+//           products accumulate in separate FP32 registers, folded into FP64
+//           every 128 k.
+//
+// LDS layouts: FP64/FP32 slices are k-major ([k][x], x contiguous), which is
+// what the 16x16x4 fragments read (lane l takes x = l%16, k = l/16).  BF16
+// pieces are x-major with k contiguous ([x][k]), since a 16x16x32 fragment is
+// 8 consecutive k of one row per lane (x = l%16, k = 8*(l/16) .. +7).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rif {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+// LDS pointer types: keep ds_read/ds_write (generic pointers would compile to
+// flat accesses, whose waits also drain the in-flight global prefetch).
+typedef __attribute__((address_space(3))) double lds_f64;
+typedef __attribute__((address_space(3))) float lds_f32;
+typedef __attribute__((address_space(3))) u16x8 lds_u16x8;
+typedef __attribute__((address_space(3))) char lds_char;
+
+enum Prec : int { kF64 = 0, kF32 = 1, kBF16x3 = 2, kBF16x6 = 3 };
+
+template <int BM_, int BN_, int BK_, int WM_, int WN_>
+struct TileCfg {
+  static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
+  static constexpr int WAVES_M = BM / WM, WAVES_N = BN / WN;
+  static constexpr int NWAVES = WAVES_M * WAVES_N;
+  static constexpr int NT = 64 * NWAVES;
+  static constexpr int TM = WM / 16, TN = WN / 16;
+  static_assert(BM % WM == 0 && BN % WN == 0 && WM % 16 == 0 && WN % 16 == 0, "tile");
+};
+
+// ---------------------------------------------------------------------------
+// Source loaders.  A thread holds RR registers per slice: NP groups of KV
+// consecutive k of one column x.  xl(p) / kl(p) give the local coordinates of
+// group p, valid(p, i, kt) whether element i of group p exists, val() the
+// value to stage.  Loads clamp their address into the operand so they never
+// branch; out-of-range elements are zeroed at staging time (after the MFMAs
+// of the current slice), which keeps the prefetch in flight.
+
+// x-contiguous operand: element (x, k) at base[k*ld + off(x)].
+template <class T, int BX, int BK, int NT, int KV>
+struct XCSrc {
+  static constexpr int TPX = NT / BX;   // threads per column
+  static constexpr int NG = BK / KV;    // k-groups per column
+  static_assert(NT % BX == 0 && NG % TPX == 0, "bad XC tiling");
+  static constexpr int NP = NG / TPX;
+  static constexpr int R = NP * KV, RR = R;
+  using type = T;
+  const T* base;
+  long ld, xoff;
+  int kmax, x, kg;
+  bool ok;
+  // off(x, o) sets o = offset of column x and returns whether column x exists.
+  template <class OffFn>
+  __device__ void init(const T* base_, long ld_, int K, OffFn off) {
+    base = base_; ld = ld_; kmax = K;
+    x = threadIdx.x % BX; kg = threadIdx.x / BX;
+    long o = 0;
+    ok = off(x, o);
+    xoff = ok ? o : 0;
+  }
+  __device__ int xl(int) const { return x; }
+  __device__ int kl(int p) const { return (kg + p * TPX) * KV; }
+  __device__ bool valid(int p, int i, int kt) const { return ok && kt * BK + kl(p) + i < kmax; }
+  __device__ void fetch(int kt, T (&r)[RR]) const {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int i = 0; i < KV; ++i) {
+        const int k = kt * BK + kl(p) + i;
+        r[p * KV + i] = base[(long)(k < kmax ? k : kmax - 1) * ld + xoff];
+      }
+  }
+  __device__ double val(const T (&r)[RR], int p, int i) const { return (double)r[p * KV + i]; }
+};
+
+// k-contiguous operand: element (x, k) at row(x)[k].
+template <class T, int BX, int BK, int NT, int KV>
+struct KCSrc {
+  static constexpr int TPR = BK / KV;   // threads per row
+  static constexpr int RSTEP = NT / TPR;
+  static_assert(NT % TPR == 0 && BX % RSTEP == 0, "bad KC tiling");
+  static constexpr int NP = BX / RSTEP;
+  static constexpr int R = NP * KV, RR = R;
+  using type = T;
+  const T* rp[NP];
+  unsigned vmask;
+  int kg, xr, kmax;
+  // rowptr(x) returns row x's base or nullptr if absent; `fallback` is any
+  // valid row, read in its place and masked.
+  template <class RowPtr>
+  __device__ void init(RowPtr rowptr, const T* fallback, int K) {
+    kg = threadIdx.x % TPR;
+    xr = threadIdx.x / TPR;
+    kmax = K;
+    vmask = 0;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const T* q = rowptr(xr + p * RSTEP);
+      vmask |= (unsigned)(q != nullptr) << p;
+      rp[p] = q ? q : fallback;
+    }
+  }
+  __device__ int xl(int p) const { return xr + p * RSTEP; }
+  __device__ int kl(int) const { return kg * KV; }
+  __device__ bool valid(int p, int i, int kt) const { return (vmask >> p & 1) && kt * BK + kg * KV + i < kmax; }
+  __device__ void fetch(int kt, T (&r)[RR]) const {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int i = 0; i < KV; ++i) {
+        const int k = kt * BK + kg * KV + i;
+        r[p * KV + i] = rp[p][k < kmax ? k : kmax - 1];
+      }
+  }
+  __device__ double val(const T (&r)[RR], int p, int i) const { return (double)r[p * KV + i]; }
+};
+
+__device__ __forceinline__ void wave_origin(int WAVES_N, int WM, int WN, int& wm0, int& wn0) {
+  const int wave = threadIdx.x >> 6;
+  wm0 = (wave / WAVES_N) * WM;
+  wn0 = (wave % WAVES_N) * WN;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 engine
+struct EngF64 {
+  static constexpr int BK = 16, KV = 1, PAD = 16, CHUNK = 1 << 30;
+  template <int BX>
+  static constexpr int stage_bytes() { return BK * (BX + PAD) * 8; }
+  template <class Cfg>
+  struct Acc {
+    d4 v[Cfg::TM][Cfg::TN];
+    __device__ void zero() {
+#pragma unroll
+      for (int i = 0; i < Cfg::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < Cfg::TN; ++j) v[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+    __device__ void flush() {}
+    // f64 16x16x4: register r of lane l holds row l/16 + 4r, column l%16.
+    template <class F>
+    __device__ void for_each(F&& f) const {
+      const int lane = threadIdx.x & 63;
+      int wm0, wn0;
+      wave_origin(Cfg::WAVES_N, Cfg::WM, Cfg::WN, wm0, wn0);
+#pragma unroll
+      for (int i = 0; i < Cfg::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < Cfg::TN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            f(wm0 + i * 16 + (lane >> 4) + 4 * r, wn0 + j * 16 + (lane & 15), v[i][j][r]);
+    }
+  };
+  template <int BX, class L>
+  __device__ static void stash(lds_char* S, const L& ld, const typename L::type (&r)[L::RR], int kt) {
+    lds_f64* s = (lds_f64*)S;
+#pragma unroll
+    for (int p = 0; p < L::NP; ++p)
+      s[ld.kl(p) * (BX + PAD) + ld.xl(p)] = ld.valid(p, 0, kt) ? ld.val(r, p, 0) : 0.0;
+  }
+  template <class Cfg>
+  __device__ static void mma(const lds_char* SA, const lds_char* SB, Acc<Cfg>& acc) {
+    const lds_f64* As = (const lds_f64*)SA;
+    const lds_f64* Bs = (const lds_f64*)SB;
+    const int lane = threadIdx.x & 63;
+    int wm0, wn0;
+    wave_origin(Cfg::WAVES_N, Cfg::WM, Cfg::WN, wm0, wn0);
+    const int kr = lane >> 4, xc = lane & 15;
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double a[Cfg::TM], b[Cfg::TN];
+#pragma unroll
+      for (int i = 0; i < Cfg::TM; ++i) a[i] = As[(kk + kr) * (Cfg::BM + PAD) + wm0 + i * 16 + xc];
+#pragma unroll
+      for (int j = 0; j < Cfg::TN; ++j) b[j] = Bs[(kk + kr) * (Cfg::BN + PAD) + wn0 + j * 16 + xc];
+#pragma unroll
+      for (int i = 0; i < Cfg::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < Cfg::TN; ++j)
+          acc.v[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc.v[i][j], 0, 0, 0);
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// FP32 engine (FP64 recombination every CHUNK slices = 128 k)
+struct EngF32 {
+  static constexpr int BK = 16, KV = 1, PAD = 16, CHUNK = 8;
+  template <int BX>
+  static constexpr int stage_bytes() { return BK * (BX + PAD) * 4; }
+  template <class Cfg>
+  struct Acc {
+    f4 s[Cfg::TM][Cfg::TN];
+    d4 v[Cfg::TM][Cfg::TN];
+    __device__ void zero() {
+#pragma unroll
+      for (int i = 0; i < Cfg::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < Cfg::TN; ++j) {
+          s[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+          v[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+        }
+    }
+    __device__ void flush() {
+#pragma unroll
+      for (int i = 0; i < Cfg::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < Cfg::TN; ++j) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v[i][j][r] += (double)s[i][j][r];
+          s[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+    // f32 MFMA layout: register r of lane l holds row 4*(l/16) + r, column l%16.
+    template <class F>
+    __device__ void for_each(F&& f) const {
+      const int lane = threadIdx.x & 63;
+      int wm0, wn0;
+      wave_origin(Cfg::WAVES_N, Cfg::WM, Cfg::WN, wm0, wn0);
+#pragma unroll
+      for (int i = 0; i < Cfg::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < Cfg::TN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            f(wm0 + i * 16 + 4 * (lane >> 4) + r, wn0 + j * 16 + (lane & 15), v[i][j][r]);
+    }
+  };
+  template <int BX, class L>
+  __device__ static void stash(lds_char* S, const L& ld, const typename L::type (&r)[L::RR], int kt) {
+    lds_f32* s = (lds_f32*)S;
+#pragma unroll
+    for (int p = 0; p < L::NP; ++p)
+      s[ld.kl(p) * (BX + PAD) + ld.xl(p)] = ld.valid(p, 0, kt) ? (float)ld.val(r, p, 0) : 0.f;
+  }
+  template <class Cfg>
+  __device__ static void mma(const lds_char* SA, const lds_char* SB, Acc<Cfg>& acc) {
+    const lds_f32* As = (const lds_f32*)SA;
+    const lds_f32* Bs = (const lds_f32*)SB;
+    const int lane = threadIdx.x & 63;
+    int wm0, wn0;
+    wave_origin(Cfg::WAVES_N, Cfg::WM, Cfg::WN, wm0, wn0);
+    const int kr = lane >> 4, xc = lane & 15;
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      float a[Cfg::TM], b[Cfg::TN];
+#pragma unroll
+      for (int i = 0; i < Cfg::TM; ++i) a[i] = As[(kk + kr) * (Cfg::BM + PAD) + wm0 + i * 16 + xc];
+#pragma unroll
+      for (int j = 0; j < Cfg::TN; ++j) b[j] = Bs[(kk + kr) * (Cfg::BN + PAD) + wn0 + j * 16 + xc];
+#pragma unroll
+      for (int i = 0; i < Cfg::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < Cfg::TN; ++j)
+          acc.s[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc.s[i][j], 0, 0, 0);
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Split-BF16 engines.  NPC = pieces per operand (2 for x3, 3 for x6).
+__device__ __forceinline__ unsigned short bf16_bits(float x) {
+  // round to nearest even; operands here are finite
+  unsigned u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ double bf16_value(unsigned short h) {
+  return (double)__uint_as_float((unsigned)h << 16);
+}
+
+template <int NPC>
+struct EngBF16 {
+  static constexpr int BK = 32, KV = 8, PAD = 8, CHUNK = 4;
+  static constexpr int ROW = BK + PAD;  // 16-bit elements per LDS row (80 B)
+  // one piece plane of BX rows; a stage holds NPC planes
+  template <int BX>
+  static constexpr int piece_bytes() { return BX * ROW * 2; }
+  template <int BX>
+  static constexpr int stage_bytes() { return NPC * piece_bytes<BX>(); }
+  template <class Cfg>
+  struct Acc {
+    f4 hh[Cfg::TM][Cfg::TN];
+    f4 xx[Cfg::TM][Cfg::TN];
+    d4 v[Cfg::TM][Cfg::TN];
+    __device__ void zero() {
+#pragma unroll
+      for (int i = 0; i < Cfg::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < Cfg::TN; ++j) {
+          hh[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+          xx[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+          v[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+        }
+    }
+    __device__ void flush() {
+#pragma unroll
+      for (int i = 0; i < Cfg::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < Cfg::TN; ++j) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v[i][j][r] += (double)hh[i][j][r] + (double)xx[i][j][r];
+          hh[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+          xx[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+    template <class F>
+    __device__ void for_each(F&& f) const {
+      const int lane = threadIdx.x & 63;
+      int wm0, wn0;
+      wave_origin(Cfg::WAVES_N, Cfg::WM, Cfg::WN, wm0, wn0);
+#pragma unroll
+      for (int i = 0; i < Cfg::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < Cfg::TN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            f(wm0 + i * 16 + 4 * (lane >> 4) + r, wn0 + j * 16 + (lane & 15), v[i][j][r]);
+    }
+  };
+  // Splits each group of 8 consecutive k into NPC bf16 pieces and writes one
+  // 16-byte vector per piece.
+  template <int BX, class L>
+  __device__ static void stash(lds_char* S, const L& ld, const typename L::type (&r)[L::RR], int kt) {
+    static_assert(L::NP * KV <= L::RR, "groups of 8");
+#pragma unroll
+    for (int p = 0; p < L::NP; ++p) {
+      u16x8 pc[NPC];
+#pragma unroll
+      for (int i = 0; i < KV; ++i) {
+        double x = ld.valid(p, i, kt) ? ld.val(r, p, i) : 0.0;
+#pragma unroll
+        for (int s = 0; s < NPC; ++s) {
+          const unsigned short h = bf16_bits((float)x);
+          pc[s][i] = h;
+          x -= bf16_value(h);
+        }
+      }
+      const int off = ld.xl(p) * ROW + ld.kl(p);
+#pragma unroll
+      for (int s = 0; s < NPC; ++s)
+        *(lds_u16x8*)(S + s * piece_bytes<BX>() + off * 2) = pc[s];
+    }
+  }
+  template <class Cfg>
+  __device__ static void mma(const lds_char* SA, const lds_char* SB, Acc<Cfg>& acc) {
+    const int lane = threadIdx.x & 63;
+    int wm0, wn0;
+    wave_origin(Cfg::WAVES_N, Cfg::WM, Cfg::WN, wm0, wn0);
+    const int xc = lane & 15, k0 = 8 * (lane >> 4);
+    bf16x8 a[NPC][Cfg::TM], b[NPC][Cfg::TN];
+#pragma unroll
+    for (int s = 0; s < NPC; ++s) {
+#pragma unroll
+      for (int i = 0; i < Cfg::TM; ++i)
+        a[s][i] = __builtin_bit_cast(bf16x8, *(const lds_u16x8*)(SA + s * piece_bytes<Cfg::BM>() +
+                                                                  ((wm0 + i * 16 + xc) * ROW + k0) * 2));
+#pragma unroll
+      for (int j = 0; j < Cfg::TN; ++j)
+        b[s][j] = __builtin_bit_cast(bf16x8, *(const lds_u16x8*)(SB + s * piece_bytes<Cfg::BN>() +
+                                                                  ((wn0 + j * 16 + xc) * ROW + k0) * 2));
+    }
+#pragma unroll
+    for (int i = 0; i < Cfg::TM; ++i)
+#pragma unroll
+      for (int j = 0; j < Cfg::TN; ++j) {
+        f4 x = acc.xx[i][j];
+        if constexpr (NPC == 3) {
+          x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], x, 0, 0, 0);
+          x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], x, 0, 0, 0);
+          x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], x, 0, 0, 0);
+        }
+        x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], x, 0, 0, 0);
+        x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], x, 0, 0, 0);
+        acc.xx[i][j] = x;
+        acc.hh[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc.hh[i][j], 0, 0, 0);
+      }
+  }
+};
+
+template <class E, class Cfg>
+constexpr int smem_bytes() { return 2 * (E::template stage_bytes<Cfg::BM>() + E::template stage_bytes<Cfg::BN>()); }
+
+template <int P> struct EngineOf;
+template <> struct EngineOf<kF64> { using type = EngF64; };
+template <> struct EngineOf<kF32> { using type = EngF32; };
+template <> struct EngineOf<kBF16x3> { using type = EngBF16<2>; };
+template <> struct EngineOf<kBF16x6> { using type = EngBF16<3>; };
+
+// Main loop over nk slices.  smem: smem_bytes<E, Cfg>() bytes of LDS, laid
+// out [A stage 0][A stage 1][B stage 0][B stage 1].
+template <class E, class Cfg, class LA, class LB>
+__device__ __forceinline__ void gemm_mainloop(LA& la, LB& lb, int nk, typename E::template Acc<Cfg>& acc,
+                                              char* smem_generic) {
+  constexpr int SA = E::template stage_bytes<Cfg::BM>();
+  constexpr int SB = E::template stage_bytes<Cfg::BN>();
+  lds_char* smem = (lds_char*)smem_generic;
+  lds_char* As[2] = {smem, smem + SA};
+  lds_char* Bs[2] = {smem + 2 * SA, smem + 2 * SA + SB};
+  typename LA::type ra[LA::RR];
+  typename LB::type rb[LB::RR];
+  acc.zero();
+  if (nk <= 0) return;
+  la.fetch(0, ra);
+  lb.fetch(0, rb);
+  E::template stash<Cfg::BM>(As[0], la, ra, 0);
+  E::template stash<Cfg::BN>(Bs[0], lb, rb, 0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) {
+      la.fetch(kt + 1, ra);
+      lb.fetch(kt + 1, rb);
+    }
+    E::template mma<Cfg>(As[cur], Bs[cur], acc);
+    if ((kt + 1) % E::CHUNK == 0) acc.flush();
+    if (more) {
+      E::template stash<Cfg::BM>(As[cur ^ 1], la, ra, kt + 1);
+      E::template stash<Cfg::BN>(Bs[cur ^ 1], lb, rb, kt + 1);
+    }
+    __syncthreads();
+  }
+  acc.flush();
+}
+
+}  // namespace rif

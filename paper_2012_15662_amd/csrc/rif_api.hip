@@ -192,10 +192,7 @@ rif_status rif_transform(rif_ctx* c, int nb, int na, int nw, int nmo, const doub
     return fail(c, RIF_EINVAL, "rif_transform: need 0 < n_omega <= n_mo <= n_bf and n_aux > 0");
   if (!b || !C || !bh || !bmo || !d) return fail(c, RIF_EINVAL, "rif_transform: NULL pointer");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
-  if (prec != RIF_FP64) return fail(c, RIF_ENOTSUP, "rif_transform: precision mode not available");
-  rif_status st = f64_half_transform(c, nb, na, nw, nmo, b, C, (double*)bh);
-  if (st) return st;
-  return f64_mo_transform(c, nb, na, nw, nmo, (const double*)bh, C, (double*)bmo, d);
+  return op_transform(c, (int)prec, nb, na, nw, nmo, b, C, bh, bmo, d);
 }
 
 rif_status rif_jk_mo(rif_ctx* c, int na, int nw, const void* bmo, const double* d, rif_prec prec, double* J,
@@ -204,8 +201,7 @@ rif_status rif_jk_mo(rif_ctx* c, int na, int nw, const void* bmo, const double* 
   if (!dims_ok(na) || !dims_ok(nw)) return fail(c, RIF_EINVAL, "rif_jk_mo: need n_aux > 0 and n_omega > 0");
   if (!bmo || !d || !J || !K) return fail(c, RIF_EINVAL, "rif_jk_mo: NULL pointer");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
-  if (prec != RIF_FP64) return fail(c, RIF_ENOTSUP, "rif_jk_mo: precision mode not available");
-  return f64_jk_mo(c, na, nw, (const double*)bmo, d, J, K);
+  return op_jk_mo(c, (int)prec, na, nw, bmo, d, J, K);
 }
 
 rif_status rif_jk_ao_per_mo(rif_ctx* c, int nb, int na, int nw, const double* b, const void* bh,
@@ -215,8 +211,7 @@ rif_status rif_jk_ao_per_mo(rif_ctx* c, int nb, int na, int nw, const double* b,
     return fail(c, RIF_EINVAL, "rif_jk_ao_per_mo: need 0 < n_omega <= n_bf and n_aux > 0");
   if (!b || !bh || !d || !Jn || !Kn) return fail(c, RIF_EINVAL, "rif_jk_ao_per_mo: NULL pointer");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
-  if (prec != RIF_FP64) return fail(c, RIF_ENOTSUP, "rif_jk_ao_per_mo: precision mode not available");
-  return f64_jk_ao(c, nb, na, nw, b, (const double*)bh, d, (double*)Jn, (double*)Kn);
+  return op_jk_ao(c, (int)prec, nb, na, nw, b, bh, d, Jn, Kn);
 }
 
 rif_status pnof_energy_grad(rif_ctx* c, rif_functional fn, int nb, int nmo, int npairs, int ncwo,
@@ -232,9 +227,8 @@ rif_status pnof_energy_grad(rif_ctx* c, rif_functional fn, int nb, int nmo, int 
   if (!H || !C || !occ || !J || !K || !Jn || !Kn || !energy || !lambda || !grad)
     return fail(c, RIF_EINVAL, "pnof_energy_grad: NULL pointer");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
-  if (prec != RIF_FP64) return fail(c, RIF_ENOTSUP, "pnof_energy_grad: precision mode not available");
-  return f64_energy_grad(c, (int)fn, nb, nmo, npairs, ncwo, pair_of, H, C, occ, J, K, (const double*)Jn,
-                         (const double*)Kn, energy, lambda, grad);
+  return op_energy_grad(c, (int)prec, (int)fn, nb, nmo, npairs, ncwo, pair_of, H, C, occ, J, K, Jn, Kn, energy,
+                        lambda, grad);
 }
 
 rif_status pnof7_energy_grad(rif_ctx* c, int nb, int nmo, int npairs, int ncwo, const int* pair_of,

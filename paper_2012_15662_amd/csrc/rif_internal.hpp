@@ -72,20 +72,17 @@ rif_status check_launch(rif_ctx* c, const char* what);
 int pick_variant(rif_ctx* c, const char* kernel, std::initializer_list<long> shape, int nvar, int heuristic,
                  const std::function<rif_status(int)>& run);
 
-// ---- FP64 launchers (kernels_f64.hip) ----
-// All pointers are device pointers; shapes already validated.
-rif_status f64_half_transform(rif_ctx* c, int nb, int na, int nw, int nmo, const double* b,
-                              const double* C, double* bh);
-rif_status f64_mo_transform(rif_ctx* c, int nb, int na, int nw, int nmo, const double* bh,
-                            const double* C, double* bmo, double* d);
-rif_status f64_jk_mo(rif_ctx* c, int na, int nw, const double* bmo, const double* d, double* J,
-                     double* K);
-rif_status f64_jk_ao(rif_ctx* c, int nb, int na, int nw, const double* b, const double* bh,
-                     const double* d, double* Jn, double* Kn);
-rif_status f64_energy_grad(rif_ctx* c, int functional, int nb, int nmo, int npairs, int ncwo,
-                           const int* pair_of, const double* H, const double* C,
-                           const double* occ, const double* J, const double* K,
-                           const double* Jn, const double* Kn, double* energy, double* lambda,
-                           double* grad);
+// ---- hot-path operations (kernels.hip) ----
+// All pointers are device pointers; shapes already validated.  `prec` is the
+// rif_prec mode; b_half/b_mo/Jn/Kn are double for RIF_FP64, float otherwise.
+rif_status op_transform(rif_ctx* c, int prec, int nb, int na, int nw, int nmo, const double* b, const double* C,
+                        void* bh, void* bmo, double* d);
+rif_status op_jk_mo(rif_ctx* c, int prec, int na, int nw, const void* bmo, const double* d, double* J, double* K);
+rif_status op_jk_ao(rif_ctx* c, int prec, int nb, int na, int nw, const double* b, const void* bh,
+                    const double* d, void* Jn, void* Kn);
+rif_status op_energy_grad(rif_ctx* c, int prec, int functional, int nb, int nmo, int npairs, int ncwo,
+                          const int* pair_of, const double* H, const double* C, const double* occ,
+                          const double* J, const double* K, const void* Jn, const void* Kn, double* energy,
+                          double* lambda, double* grad);
 
 }  // namespace rif

@@ -1,0 +1,73 @@
+"""Reduced-precision modes (FP32 MFMA, split BF16 x3 / x6) vs the FP64 oracle.
+
+Targets: the split path within 1 uEh of the FP64 energy and within 1e-6 in the
+gradient (normwise: max|dG| / max|G|).  FP32 and BF16x6 are held to that bar
+at the cyclohexane-like size; BF16x3 (two pieces, three products) is known not
+to reach it and is only held to 1e-4, with its error printed.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import pnof7_ri as ri
+from tests.gpu_util import host, relerr, to_dev
+
+pytestmark = pytest.mark.gpu
+
+MODES = {"fp32": 1, "bf16x3": 2, "bf16x6": 3}
+# (abs energy error Eh, normwise gradient error, normwise J^q/K^q error)
+TOL = {"fp32": (1e-6, 1e-6, 1e-6), "bf16x6": (1e-6, 1e-6, 1e-6), "bf16x3": (1e-4, 1e-4, 1e-4)}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2012_15662_amd as rif
+    c = rif.Context()
+    yield c
+    c.close()
+
+
+def errors(ctx, inst, prec, C=None, ref=None):
+    t = to_dev(inst, C)
+    out = ctx.build(t["b"], t["C"], t["H"], t["occ"], t["pair_of"], inst.n_pairs, inst.n_cwo, prec=prec)
+    ctx.sync()
+    if ref is None:
+        ref = ri.build_instance(inst, C=C)
+    e = {k: relerr(host(out[k]), ref[k]) for k in ("b_half", "b_mo", "d", "J", "K", "Jn", "Kn", "lam", "grad")}
+    e["dE"] = abs(float(host(out["energy"])[0]) - ref["energy"])
+    return e, out, ref
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("shape", [(48, 192, 5, 1, 0), (139, 157, 9, 3, 31)])
+def test_small_shapes(ctx, mode, shape):
+    nb, na, npair, ncwo, seed = shape
+    inst = synth.make_instance(nb, na, npair, ncwo, seed)
+    e, _, _ = errors(ctx, inst, MODES[mode])
+    print(mode, shape, " ".join(f"{k}={v:.2e}" for k, v in e.items()), flush=True)
+    te, tg, tj = TOL[mode]
+    assert e["dE"] < te and e["grad"] < tg and e["Jn"] < tj and e["Kn"] < tj
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_cyclohexane_like(ctx, mode):
+    inst = synth.workload("c6h12")
+    e, out, ref = errors(ctx, inst, MODES[mode])
+    print(mode, "c6h12", " ".join(f"{k}={v:.2e}" for k, v in e.items()), flush=True)
+    te, tg, tj = TOL[mode]
+    assert e["dE"] < te and e["grad"] < tg
+    # J^q and K^q stay exactly symmetric in every mode
+    Jn = host(out["Jn"])
+    assert np.array_equal(Jn, Jn.transpose(0, 2, 1))
+
+
+def test_fp16x3_not_available(ctx):
+    import paper_2012_15662_amd as rif
+    inst = synth.make_instance(20, 30, 2, 1, 3)
+    t = to_dev(inst)
+    with pytest.raises(rif.RifError) as e:
+        ctx.transform(t["b"], t["C"], inst.n_omega, prec=rif.FP16X3)
+    assert e.value.status == -4
