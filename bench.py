@@ -92,12 +92,78 @@ def time_builds(ctx, b, Cd, H, occ, pm, inst, prec, steps, warmup, profile=False
     return el, out, prof
 
 
+def bench_batch(args):
+    """64 uneven molecules (n_bf ~ U{60..400}, n_aux = 3 n_bf, pairs = n_bf//12,
+    Ncwo = 2): one grouped launch per step, captured in a hipGraph and replayed.
+    Reports aggregate builds/s and the same molecules built one after another."""
+    import numpy as np
+    import torch
+
+    import paper_2012_15662_amd as rif
+    import synth
+
+    prec = MODES[args.prec]
+    insts = synth.make_batch(64)
+    dev = "cuda:0"
+    ctx = rif.Context(0)
+    ctx.autotune(not args.no_tune)
+    items, flops = [], 0.0
+    for inst in insts:
+        inp = {"b": torch.from_numpy(inst.b).to(dev), "C": torch.from_numpy(inst.C).to(dev),
+               "H": torch.from_numpy(inst.H).to(dev), "occ": torch.from_numpy(inst.occ).to(dev),
+               "pair_of": torch.from_numpy(inst.pair_of.astype(np.int32)).to(dev)}
+        inst.b = None   # release host memory as we go
+        items.append((inp, inst.n_pairs, inst.n_cwo, None))
+        flops += build_flops(inst.n_bf, inst.n_aux, inst.n_omega, inst.n_mo)
+    batch = ctx.batch(items, prec=prec)
+    for _ in range(max(args.warmup, 1)):
+        batch.run(use_graph=True)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.run(use_graph=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.sync()
+    # the same molecules one build call after another (no batching, no graph)
+    for inp, npair, ncwo, out in zip([i[0] for i in items], [i[1] for i in items], [i[2] for i in items],
+                                     batch.outs):
+        ctx.build_instance(inp, npair, ncwo, out=out, prec=prec)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for inp, npair, ncwo, out in zip([i[0] for i in items], [i[1] for i in items], [i[2] for i in items],
+                                     batch.outs):
+        ctx.build_instance(inp, npair, ncwo, out=out, prec=prec)
+    torch.cuda.synchronize()
+    el_seq = time.perf_counter() - t1
+    ctx.sync()
+    per = el / args.steps
+    line = {
+        "metric": METRIC, "value": round(64 / per, 2), "unit": "builds/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(per * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": "batch64: 64 molecules, n_bf ~ U{60..400} (seed 3), n_aux = 3 n_bf, "
+                               "pairs = n_bf//12, Ncwo = 2; one step = all 64 builds",
+                   "precision": args.prec},
+        "tflops": round(flops / per / 1e12, 2), "flops_per_step": flops,
+        "sequential_builds_s": round(64 / el_seq, 2), "batch_speedup": round(el_seq / per, 3),
+        "tiles": [t for t in ctx.tune_report().strip().splitlines() if t.startswith("g_")],
+    }
+    batch.close()
+    ctx.close()
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c6h12", choices=["tiny", "c6h12", "c10h20"])
+    ap.add_argument("--workload", default="c6h12", choices=["tiny", "c6h12", "c10h20", "batch64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-tune", action="store_true", help="heuristic tile shapes instead of autotuning")
@@ -108,6 +174,9 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the path would shard over the orbitals of Omega; see the design notes)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch64":
+        return bench_batch(args)
 
     import numpy as np
     import torch

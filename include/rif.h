@@ -140,6 +140,41 @@ rif_status pnof_energy_grad(rif_ctx *ctx, rif_functional functional, int n_bf, i
                             const double *K, const void *Jn, const void *Kn, rif_prec prec,
                             double *energy, double *lambda, double *grad);
 
+/* One molecule's inputs and outputs for rif_build / rif_batch_create.  Every
+ * pointer is a device pointer owned by the caller, with the layouts and
+ * element types of the four calls above (b_half, b_mo, Jn, Kn: double for
+ * RIF_FP64, float otherwise); pair_of may be NULL (default map). */
+typedef struct rif_instance {
+  int n_bf, n_aux, n_pairs, n_cwo, n_mo;
+  const double *b, *C, *H, *occ;
+  const int *pair_of;
+  void *b_half, *b_mo;
+  double *d, *J, *K;
+  void *Jn, *Kn;
+  double *energy, *lambda, *grad;
+} rif_instance;
+
+/* One build: rif_transform, rif_jk_mo, rif_jk_ao_per_mo and pnof_energy_grad
+ * in sequence for one molecule (same checks and errors as those calls). */
+rif_status rif_build(rif_ctx *ctx, const rif_instance *inst, rif_prec prec, rif_functional functional);
+
+/* Batched builds of many molecules of uneven size.  rif_batch_create checks
+ * every instance (as rif_build would), orders them largest first, allocates
+ * the batch's own workspace and uploads a work-list per step; it chooses
+ * each step's tile variant for the batch as a whole (timing the candidates if
+ * autotuning is on).  rif_batch_run enqueues one persistent grouped launch per
+ * step covering all molecules; with use_graph != 0 the first run captures the
+ * sequence in a hipGraph on the context's stream and every run replays it.
+ * The instance pointers are baked into the plan: keep them valid and
+ * unchanged while the batch lives.  Results for each molecule equal
+ * rif_build's with the same tile variants.  `inst` is a HOST array of n_inst
+ * structs (copied). */
+typedef struct rif_batch rif_batch;
+rif_status rif_batch_create(rif_ctx *ctx, int n_inst, const rif_instance *inst, rif_prec prec,
+                            rif_functional functional, rif_batch **out);
+rif_status rif_batch_run(rif_batch *batch, int use_graph);
+void rif_batch_destroy(rif_batch *batch);
+
 /* Tile-shape selection for the MFMA kernels.  Each GEMM-shaped kernel has up
  * to four tile variants (0: 128x128, 1: 64x64, 2: 128x64, 3: 64x128 outputs
  * per workgroup).  mode 0 picks one per shape with a wave-quantisation

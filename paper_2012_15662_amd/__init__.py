@@ -15,7 +15,7 @@ import ctypes
 import os
 
 __all__ = [
-    "Context", "RifError", "load_library", "LIB_PATH", "FP64", "FP32", "BF16X3", "BF16X6",
+    "Context", "Batch", "Instance", "RifError", "load_library", "LIB_PATH", "FP64", "FP32", "BF16X3", "BF16X6",
     "FP16X3", "PNOF7", "PNOF5", "EXPORTS",
 ]
 
@@ -27,6 +27,13 @@ PNOF7, PNOF5 = 0, 1
 _STATUS = {0: "RIF_OK", -1: "RIF_EINVAL", -2: "RIF_ENOMEM", -3: "RIF_EHIP", -4: "RIF_ENOTSUP"}
 
 _vp, _i, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+class Instance(ctypes.Structure):
+    """struct rif_instance (include/rif.h)."""
+    _fields_ = [(n, ctypes.c_int) for n in ("n_bf", "n_aux", "n_pairs", "n_cwo", "n_mo")] + \
+               [(n, ctypes.c_void_p) for n in ("b", "C", "H", "occ", "pair_of", "b_half", "b_mo", "d", "J",
+                                               "K", "Jn", "Kn", "energy", "lambda_", "grad")]
+
+
 # name -> (restype, argtypes); mirrors include/rif.h
 EXPORTS = {
     "rif_create": (_i, [ctypes.POINTER(_vp), _i, _vp]),
@@ -42,6 +49,10 @@ EXPORTS = {
                                _vp, _vp, _vp]),
     "pnof_energy_grad": (_i, [_vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                               _i, _vp, _vp, _vp]),
+    "rif_build": (_i, [_vp, ctypes.POINTER(Instance), _i, _i]),
+    "rif_batch_create": (_i, [_vp, _i, ctypes.POINTER(Instance), _i, _i, ctypes.POINTER(_vp)]),
+    "rif_batch_run": (_i, [_vp, _i]),
+    "rif_batch_destroy": (None, [_vp]),
     "rif_autotune": (_i, [_vp, _i]),
     "rif_set_tile_variant": (_i, [_vp, _i]),
     "rif_tune_report": (_i, [_vp, ctypes.c_char_p, _i]),
@@ -50,6 +61,8 @@ EXPORTS = {
 }
 
 _lib = None
+
+
 
 
 class RifError(RuntimeError):
@@ -222,6 +235,57 @@ class Context:
             o.get("energy"), o.get("lam"), o.get("grad"))
         return o
 
+    # ---- instances and batches ---------------------------------------------
+    def outputs(self, n_bf, n_aux, n_pairs, n_cwo, n_mo, prec=FP64, device="cuda"):
+        """Allocate every output array of one build."""
+        import torch
+        w = n_pairs * (1 + n_cwo)
+        dt = torch.float64 if prec == FP64 else torch.float32
+        f64 = torch.float64
+        return {"b_half": torch.empty((w, n_aux, n_bf), dtype=dt, device=device),
+                "b_mo": torch.empty((n_aux, w, w), dtype=dt, device=device),
+                "d": torch.empty((n_aux, w), dtype=f64, device=device),
+                "J": torch.empty((w, w), dtype=f64, device=device),
+                "K": torch.empty((w, w), dtype=f64, device=device),
+                "Jn": torch.empty((w, n_bf, n_bf), dtype=dt, device=device),
+                "Kn": torch.empty((w, n_bf, n_bf), dtype=dt, device=device),
+                "energy": torch.empty((1,), dtype=f64, device=device),
+                "lam": torch.empty((n_mo, w), dtype=f64, device=device),
+                "grad": torch.empty((n_mo, n_mo), dtype=f64, device=device)}
+
+    @staticmethod
+    def instance(inp, n_pairs, n_cwo, out, prec=FP64):
+        """rif_instance from input tensors (b, C, H, occ, pair_of) and outputs."""
+        import torch
+        n_aux, n_bf, _ = inp["b"].shape
+        n_mo = inp["C"].shape[1]
+        w = n_pairs * (1 + n_cwo)
+        dt = torch.float64 if prec == FP64 else torch.float32
+        f64 = torch.float64
+        return Instance(
+            n_bf, n_aux, n_pairs, n_cwo, n_mo,
+            _ptr(inp["b"], "b", f64, n_aux * n_bf * n_bf), _ptr(inp["C"], "C", f64, n_bf * n_mo),
+            _ptr(inp["H"], "H", f64, n_bf * n_bf), _ptr(inp["occ"], "occ", f64, w),
+            _ptr(inp.get("pair_of"), "pair_of", torch.int32, w),
+            _ptr(out["b_half"], "b_half", dt, w * n_aux * n_bf), _ptr(out["b_mo"], "b_mo", dt, n_aux * w * w),
+            _ptr(out["d"], "d", f64, n_aux * w), _ptr(out["J"], "J", f64, w * w), _ptr(out["K"], "K", f64, w * w),
+            _ptr(out["Jn"], "Jn", dt, w * n_bf * n_bf), _ptr(out["Kn"], "Kn", dt, w * n_bf * n_bf),
+            _ptr(out["energy"], "energy", f64, 1), _ptr(out["lam"], "lambda", f64, n_mo * w),
+            _ptr(out["grad"], "grad", f64, n_mo * n_mo))
+
+    def build_instance(self, inp, n_pairs, n_cwo, out=None, prec=FP64, functional=PNOF7):
+        """One build through rif_build."""
+        n_aux, n_bf, _ = inp["b"].shape
+        if out is None:
+            out = self.outputs(n_bf, n_aux, n_pairs, n_cwo, inp["C"].shape[1], prec, inp["b"].device)
+        inst = self.instance(inp, n_pairs, n_cwo, out, prec)
+        self._chk(self.lib.rif_build(self.h, ctypes.byref(inst), prec, functional))
+        return out
+
+    def batch(self, items, prec=FP64, functional=PNOF7):
+        """items: list of (inputs dict, n_pairs, n_cwo, outputs dict or None)."""
+        return Batch(self, items, prec, functional)
+
     # ---- tile selection ---------------------------------------------------
     def autotune(self, on: bool = True):
         self._chk(self.lib.rif_autotune(self.h, 1 if on else 0))
@@ -246,3 +310,36 @@ class Context:
             name, n, ms = line.split()
             out[name] = (int(n), float(ms))
         return out
+
+
+class Batch:
+    """A rif_batch: many molecules built by one grouped launch per step."""
+
+    def __init__(self, ctx: Context, items, prec=FP64, functional=PNOF7):
+        self.ctx = ctx
+        self.outs, self.inputs = [], []
+        arr = (Instance * len(items))()
+        for i, (inp, n_pairs, n_cwo, out) in enumerate(items):
+            n_aux, n_bf, _ = inp["b"].shape
+            if out is None:
+                out = ctx.outputs(n_bf, n_aux, n_pairs, n_cwo, inp["C"].shape[1], prec, inp["b"].device)
+            self.inputs.append(inp)
+            self.outs.append(out)
+            arr[i] = Context.instance(inp, n_pairs, n_cwo, out, prec)
+        h = ctypes.c_void_p()
+        ctx._chk(ctx.lib.rif_batch_create(ctx.h, len(items), arr, prec, functional, ctypes.byref(h)))
+        self.h = h
+
+    def run(self, use_graph: bool = True):
+        self.ctx._chk(self.ctx.lib.rif_batch_run(self.h, 1 if use_graph else 0))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.rif_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -48,25 +48,66 @@ template <int P, class T, int BX, int NT>
 using KCS = KCSrc<T, BX, EngineOf<P>::type::BK, NT, EngineOf<P>::type::KV>;
 
 // ---------------------------------------------------------------------------
+// Per-step argument blocks.  Each step is written once as a tile function
+// (a tile = one workgroup's share of the step, indexed by a linear id);
+// single-molecule kernels map blockIdx to a tile, grouped kernels walk a
+// work-list of tiles that spans many molecules (rif_batch_*).  The same tile
+// code and tile shape give bitwise-identical results in both.
+
+struct HalfArgs { int nb, nw, nmo; long nr; const double* b; const double* C; void* bh; };
+struct MoArgs { int nb, na, nw, nmo; const void* bh; const double* C; void* bmo; double* d; };
+struct JaoArgs { int nb, na, nw; const double* b; const double* d; void* Jn; };
+struct KaoArgs { int nb, na, nw; const void* bh; void* Kn; };
+struct GemmArgs { int M, N, K; const double* A; long lda; const double* B; long ldb; double* out; long ldo; };
+struct FockArgs {
+  int nb, nw, nmo, per, nsplit;
+  const void *Jn, *Kn;
+  const double *Ac, *Bc, *C;
+  double* Yp;
+};
+struct JkArgs { int na, nw, nsplit; const void* bmo; const double* d; double* part; double* J; double* K; };
+struct CoefArgs {
+  int functional, nw, npairs, ncwo;
+  const int* pair_of;
+  const double *occ, *J, *K;
+  double *Ac, *Bc, *Ep;
+};
+struct EnergyArgs {
+  int nw, npairs, ncwo, nb, nmo, nparts;
+  const int* pair_of;
+  const double *occ, *C, *HC, *Ep;
+  double* energy;
+  int* flag;
+};
+struct FockRedArgs { int nb, nw, nsplit; const double *Yp, *occ, *HC; double* Y; };
+struct GradArgs { int nmo, nw; const double* lam; double* G; };
+
 // Half transform.  Since b[l] is symmetric, b[l][mu][nu] = b[l][nu][mu] and the
 // step is one GEMM: bh[q][r] = sum_mu C[mu][q] bflat[r][mu] with r = l*n_bf + nu.
-// M = q, N = r (stores run along r, contiguous in b_half), K = mu.
+// M = q, N = r (stores run along r, contiguous in b_half), K = mu.  Tiles:
+// q-tile fastest.
 template <int P, class Cfg>
-__global__ __launch_bounds__(Cfg::NT) void k_half_transform(int nb, long nr, int nw, int nmo,
-                                                            const double* __restrict__ b,
-                                                            const double* __restrict__ C,
-                                                            IOT<P>* __restrict__ bh) {
-  ENGINE_TYPES;
-  const int q0 = blockIdx.y * Cfg::BM;
-  const long r0 = (long)blockIdx.x * Cfg::BN;
+__host__ __device__ inline long half_tiles(const HalfArgs& a) {
+  return (long)cdiv(a.nw, Cfg::BM) * cdiv(a.nr, Cfg::BN);
+}
+template <int P, class Cfg>
+__device__ void half_tile(const HalfArgs& a, long t, char* smem) {
+  using E = typename EngineOf<P>::type;
+  const int nqt = cdiv(a.nw, Cfg::BM);
+  const int q0 = (int)(t % nqt) * Cfg::BM;
+  const long r0 = (t / nqt) * Cfg::BN;
+  const int nb = a.nb, nw = a.nw;
+  const long nr = a.nr;
+  const double* b = a.b;
+  IOT<P>* bh = (IOT<P>*)a.bh;
   XCS<P, double, Cfg::BM, Cfg::NT> la;
-  la.init(C, nmo, nb, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
+  la.init(a.C, a.nmo, nb, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
   KCS<P, double, Cfg::BN, Cfg::NT> lb;
   lb.init([&](int x) -> const double* {
     const long r = r0 + x;
     return r < nr ? b + r * nb : nullptr;
   }, b, nb);
-  Acc acc;
+  typename E::template Acc<Cfg> acc;
   gemm_mainloop<E, Cfg>(la, lb, cdiv(nb, E::BK), acc, smem);
   acc.for_each([&](int m, int n, double v) {
     const int q = q0 + m;
@@ -78,16 +119,21 @@ __global__ __launch_bounds__(Cfg::NT) void k_half_transform(int nb, long nr, int
 // MO transform: rows s = l*n_omega + p, bmo[s][q] = sum_nu bh[p][l][nu] C[nu][q];
 // the FP64 diagonal d[l][p] = bmo[l][p][p] comes from the same epilogue.
 template <int P, class Cfg>
-__global__ __launch_bounds__(Cfg::NT) void k_mo_transform(int nb, int na, int nw, int nmo,
-                                                          const IOT<P>* __restrict__ bh,
-                                                          const double* __restrict__ C,
-                                                          IOT<P>* __restrict__ bmo,
-                                                          double* __restrict__ d) {
-  ENGINE_TYPES;
+__host__ __device__ inline long mo_tiles(const MoArgs& a) {
+  return (long)cdiv(a.nw, Cfg::BN) * cdiv((long)a.na * a.nw, Cfg::BM);
+}
+template <int P, class Cfg>
+__device__ void mo_tile(const MoArgs& a, long t, char* smem) {
+  using E = typename EngineOf<P>::type;
+  const int nb = a.nb, na = a.na, nw = a.nw;
+  const int nqt = cdiv(nw, Cfg::BN);
+  const int q0 = (int)(t % nqt) * Cfg::BN;
+  const long s0 = (t / nqt) * Cfg::BM;
   const long ns = (long)na * nw;
-  const long s0 = (long)blockIdx.x * Cfg::BM;
-  const int q0 = blockIdx.y * Cfg::BN;
   const long AB = (long)na * nb;
+  const IOT<P>* bh = (const IOT<P>*)a.bh;
+  IOT<P>* bmo = (IOT<P>*)a.bmo;
+  double* d = a.d;
   KCS<P, IOT<P>, Cfg::BM, Cfg::NT> la;
   la.init([&](int x) -> const IOT<P>* {
     const long s = s0 + x;
@@ -96,8 +142,8 @@ __global__ __launch_bounds__(Cfg::NT) void k_mo_transform(int nb, int na, int nw
     return bh + p * AB + l * nb;
   }, bh, nb);
   XCS<P, double, Cfg::BN, Cfg::NT> lb;
-  lb.init(C, nmo, nb, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
-  Acc acc;
+  lb.init(a.C, a.nmo, nb, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
+  typename E::template Acc<Cfg> acc;
   gemm_mainloop<E, Cfg>(la, lb, cdiv(nb, E::BK), acc, smem);
   acc.for_each([&](int m, int n, double v) {
     const long s = s0 + m;
@@ -114,46 +160,57 @@ __host__ __device__ __forceinline__ int jao_first_col(int bi, int tmu, int tnu) 
   const int t = bi * tmu - (tnu - 1);
   return t <= 0 ? 0 : (t + tnu - 1) / tnu;
 }
+constexpr int kJaoTNU = 16;
+__host__ __device__ inline long jao_active(int nb, int tmu, int tnu) {  // blocks touching the upper triangle
+  long n = 0;
+  const int nbi = cdiv(nb, tmu), nbj = cdiv(nb, tnu);
+  for (int bi = 0; bi < nbi; ++bi) {
+    const int f = jao_first_col(bi, tmu, tnu);
+    n += nbj > f ? nbj - f : 0;
+  }
+  return n;
+}
 
 // Per-MO AO Coulomb: Jn[q][mu][nu] = sum_l d[l][q] b[l][mu][nu].
-// M = q, N = a TMU x TNU block of (mu, nu), K = l.  The grid enumerates only
-// blocks that touch the upper triangle, q-tile fastest, so the XCD remap
-// spreads equal work over the XCDs and q-tiles sharing a b block run on one
-// XCD.  Each block writes (mu <= nu) directly and (mu < nu) mirrored, so every
-// element of the full matrix is written exactly once.
-template <int P, class Cfg, int TNU>
-__global__ __launch_bounds__(Cfg::NT) void k_jao(int nb, int na, int nw, const double* __restrict__ b,
-                                                 const double* __restrict__ d,
-                                                 IOT<P>* __restrict__ Jn) {
-  ENGINE_TYPES;
-  constexpr int TMU = Cfg::BN / TNU;
-  const int nbj = (nb + TNU - 1) / TNU;
-  const int nbi = (nb + TMU - 1) / TMU;
-  const long nq = (nw + Cfg::BM - 1) / Cfg::BM;
-  const long t = xcd_remap(blockIdx.x, (long)gridDim.x);
+// M = q, N = a TMU x TNU block of (mu, nu), K = l.  Tiles enumerate only
+// blocks that touch the upper triangle, q-tile fastest (tiles sharing a b
+// block are adjacent).  Each block writes (mu <= nu) directly and (mu < nu)
+// mirrored, so every element of the full matrix is written exactly once.
+template <int P, class Cfg>
+__host__ __device__ inline long jao_tiles(const JaoArgs& a) {
+  return jao_active(a.nb, Cfg::BN / kJaoTNU, kJaoTNU) * cdiv(a.nw, Cfg::BM);
+}
+template <int P, class Cfg>
+__device__ void jao_tile(const JaoArgs& a, long t, char* smem) {
+  using E = typename EngineOf<P>::type;
+  constexpr int TNU = kJaoTNU, TMU = Cfg::BN / TNU;
+  const int nb = a.nb, na = a.na, nw = a.nw;
+  const int nbj = cdiv(nb, TNU), nbi = cdiv(nb, TMU);
+  const long nq = cdiv(nw, Cfg::BM);
   const int qt = (int)(t % nq);
-  long a = t / nq;
+  long r = t / nq;
   int bi = 0;
   for (; bi < nbi; ++bi) {
     const int n = nbj - jao_first_col(bi, TMU, TNU);
-    if (a < n) break;
-    a -= n;
+    if (r < n) break;
+    r -= n;
   }
   if (bi >= nbi) return;
-  const int bj = jao_first_col(bi, TMU, TNU) + (int)a;
+  const int bj = jao_first_col(bi, TMU, TNU) + (int)r;
   const int mu0 = bi * TMU, nu0 = bj * TNU;
   const int q0 = qt * Cfg::BM;
   const long B2 = (long)nb * nb;
   XCS<P, double, Cfg::BM, Cfg::NT> la;
-  la.init(d, nw, na, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
+  la.init(a.d, nw, na, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
   XCS<P, double, Cfg::BN, Cfg::NT> lb;
-  lb.init(b, B2, na, [&](int x, long& o) {
+  lb.init(a.b, B2, na, [&](int x, long& o) {
     const int mu = mu0 + x / TNU, nu = nu0 + x % TNU;
     o = (long)mu * nb + nu;
     return mu < nb && nu < nb;
   });
-  Acc acc;
+  typename E::template Acc<Cfg> acc;
   gemm_mainloop<E, Cfg>(la, lb, cdiv(na, E::BK), acc, smem);
+  IOT<P>* Jn = (IOT<P>*)a.Jn;
   acc.for_each([&](int m, int n, double v) {
     const int q = q0 + m, mu = mu0 + n / TNU, nu = nu0 + n % TNU;
     if (q < nw && mu < nb && nu < nb) {
@@ -165,31 +222,35 @@ __global__ __launch_bounds__(Cfg::NT) void k_jao(int nb, int na, int nw, const d
 }
 
 // Per-MO AO exchange: Kn[q] = X_q^T X_q with X_q = b_half[q] ([n_aux][n_bf]).
-// Square blocks bi <= bj only, mirrored like k_jao.
+// Square blocks bi <= bj only (the blocks of one q adjacent), mirrored like J.
 template <int P, class Cfg>
-__global__ __launch_bounds__(Cfg::NT) void k_kao(int nb, int na, int nw, const IOT<P>* __restrict__ bh,
-                                                 IOT<P>* __restrict__ Kn) {
+__host__ __device__ inline long kao_tiles(const KaoArgs& a) {
+  const long nbk = cdiv(a.nb, Cfg::BM);
+  return nbk * (nbk + 1) / 2 * a.nw;
+}
+template <int P, class Cfg>
+__device__ void kao_tile(const KaoArgs& a, long t, char* smem) {
   static_assert(Cfg::BM == Cfg::BN, "square blocks");
-  ENGINE_TYPES;
-  const int nbk = (nb + Cfg::BM - 1) / Cfg::BM;
-  const long nblk = (long)nbk * (nbk + 1) / 2;  // upper-triangle blocks per q
-  const long t = xcd_remap(blockIdx.x, (long)gridDim.x);
+  using E = typename EngineOf<P>::type;
+  const int nb = a.nb, na = a.na, nw = a.nw;
+  const int nbk = cdiv(nb, Cfg::BM);
+  const long nblk = (long)nbk * (nbk + 1) / 2;
   const int q = (int)(t / nblk);
   if (q >= nw) return;
   int rem = (int)(t % nblk), bi = 0;
   while (rem >= nbk - bi) { rem -= nbk - bi; ++bi; }
   const int bj = bi + rem;
   const long AB = (long)na * nb;
-  const IOT<P>* X = bh + (long)q * AB;
+  const IOT<P>* X = (const IOT<P>*)a.bh + (long)q * AB;
   const int mu0 = bi * Cfg::BM, nu0 = bj * Cfg::BN;
   XCS<P, IOT<P>, Cfg::BM, Cfg::NT> la;
   la.init(X, nb, na, [&](int x, long& o) { o = mu0 + x; return mu0 + x < nb; });
   XCS<P, IOT<P>, Cfg::BN, Cfg::NT> lb;
   lb.init(X, nb, na, [&](int x, long& o) { o = nu0 + x; return nu0 + x < nb; });
-  Acc acc;
+  typename E::template Acc<Cfg> acc;
   gemm_mainloop<E, Cfg>(la, lb, cdiv(na, E::BK), acc, smem);
   const long B2 = (long)nb * nb;
-  IOT<P>* K = Kn + (long)q * B2;
+  IOT<P>* K = (IOT<P>*)a.Kn + (long)q * B2;
   acc.for_each([&](int m, int n, double v) {
     const int mu = mu0 + m, nu = nu0 + n;
     if (mu < nb && nu < nb) {
@@ -201,21 +262,24 @@ __global__ __launch_bounds__(Cfg::NT) void k_kao(int nb, int na, int nw, const I
 
 // FP64 GEMM out[m][n] = sum_k A[k][m] B[k][n], both operands x-contiguous;
 // used for H C_Omega and lambda = C^T Y.
-template <class Cfg>
-__global__ __launch_bounds__(Cfg::NT) void k_gemm_tn(int M, int N, int K, const double* __restrict__ A,
-                                                     long lda, const double* __restrict__ B, long ldb,
-                                                     double* __restrict__ out, long ldo) {
-  constexpr int P = kF64;
-  ENGINE_TYPES;
-  const int m0 = blockIdx.x * Cfg::BM, n0 = blockIdx.y * Cfg::BN;
+template <int P, class Cfg>
+__host__ __device__ inline long gemm_tiles(const GemmArgs& a) {
+  return (long)cdiv(a.M, Cfg::BM) * cdiv(a.N, Cfg::BN);
+}
+template <int P, class Cfg>
+__device__ void gemm_tile(const GemmArgs& a, long t, char* smem) {
+  using E = typename EngineOf<P>::type;
+  const int nmt = cdiv(a.M, Cfg::BM);
+  const int m0 = (int)(t % nmt) * Cfg::BM, n0 = (int)(t / nmt) * Cfg::BN;
+  const int M = a.M, N = a.N;
   XCS<P, double, Cfg::BM, Cfg::NT> la;
-  la.init(A, lda, K, [&](int x, long& o) { o = m0 + x; return m0 + x < M; });
+  la.init(a.A, a.lda, a.K, [&](int x, long& o) { o = m0 + x; return m0 + x < M; });
   XCS<P, double, Cfg::BN, Cfg::NT> lb;
-  lb.init(B, ldb, K, [&](int x, long& o) { o = n0 + x; return n0 + x < N; });
-  Acc acc;
-  gemm_mainloop<E, Cfg>(la, lb, cdiv(K, E::BK), acc, smem);
+  lb.init(a.B, a.ldb, a.K, [&](int x, long& o) { o = n0 + x; return n0 + x < N; });
+  typename E::template Acc<Cfg> acc;
+  gemm_mainloop<E, Cfg>(la, lb, cdiv(a.K, E::BK), acc, smem);
   acc.for_each([&](int m, int n, double v) {
-    if (m0 + m < M && n0 + n < N) out[(long)(m0 + m) * ldo + n0 + n] = v;
+    if (m0 + m < M && n0 + n < N) a.out[(long)(m0 + m) * a.ldo + n0 + n] = v;
   });
 }
 
@@ -291,62 +355,71 @@ struct FockB {  // element (q, nu) of slab t: coef_t[q] * C[nu][q]; r[R] holds c
 };
 
 template <int P, class Cfg>
-__global__ __launch_bounds__(Cfg::NT) void k_fock(int nb, int nw, int nmo, int per,
-                                                  const IOT<P>* __restrict__ Jn,
-                                                  const IOT<P>* __restrict__ Kn,
-                                                  const double* __restrict__ Ac,
-                                                  const double* __restrict__ Bc,
-                                                  const double* __restrict__ C,
-                                                  double* __restrict__ Ypart) {
-  ENGINE_TYPES;
-  const int mu0 = blockIdx.x * Cfg::BM, q0 = blockIdx.y * Cfg::BN, s = blockIdx.z;
-  const int t0 = s * per, t1 = min(2 * nw, t0 + per);
+__host__ __device__ inline long fock_tiles(const FockArgs& a) {
+  return (long)cdiv(a.nb, Cfg::BM) * cdiv(a.nw, Cfg::BN) * a.nsplit;
+}
+template <int P, class Cfg>
+__device__ void fock_tile(const FockArgs& a, long t, char* smem) {
+  using E = typename EngineOf<P>::type;
+  const int nb = a.nb, nw = a.nw;
+  const int nmt = cdiv(nb, Cfg::BM), nnt = cdiv(nw, Cfg::BN);
+  const int mu0 = (int)(t % nmt) * Cfg::BM;
+  const int q0 = (int)((t / nmt) % nnt) * Cfg::BN;
+  const int s = (int)(t / ((long)nmt * nnt));
+  const int t0 = s * a.per, t1 = min(2 * nw, t0 + a.per);
   FockA<P, Cfg> la;
-  la.init(Jn, Kn, nb, nw, t0, mu0);
+  la.init((const IOT<P>*)a.Jn, (const IOT<P>*)a.Kn, nb, nw, t0, mu0);
   FockB<P, Cfg> lb;
-  lb.init(Ac, Bc, C, nb, nw, nmo, t0, q0);
-  Acc acc;
+  lb.init(a.Ac, a.Bc, a.C, nb, nw, a.nmo, t0, q0);
+  typename E::template Acc<Cfg> acc;
   gemm_mainloop<E, Cfg>(la, lb, (t1 - t0) * la.nchunk, acc, smem);
-  double* Y = Ypart + (long)s * nb * nw;
+  double* Y = a.Yp + (long)s * nb * nw;
   acc.for_each([&](int m, int n, double v) {
     if (mu0 + m < nb && q0 + n < nw) Y[(long)(mu0 + m) * nw + q0 + n] = v;
   });
 }
 
+// ---- element-wise and reduction steps (256-thread tiles) -------------------
+
 // MO J/K partial sums over a contiguous range of l (fixed split), then a
 // fixed-order reduction over the splits.  FP64 arithmetic in every mode.
-template <class T>
-__global__ __launch_bounds__(256) void k_jk_mo_partial(int na, int nw, int nsplit, const T* __restrict__ bmo,
-                                                       const double* __restrict__ d,
-                                                       double* __restrict__ part) {
-  const long w2 = (long)nw * nw;
-  const long pq = (long)blockIdx.x * 256 + threadIdx.x;
-  const int s = blockIdx.y;
+template <int P, class Cfg>
+__host__ __device__ inline long jkp_tiles(const JkArgs& a) { return (long)cdiv((long)a.nw * a.nw, 256) * a.nsplit; }
+template <int P, class Cfg>
+__device__ void jkp_tile(const JkArgs& a, long t, char*) {
+  const long w2 = (long)a.nw * a.nw;
+  const long nx = cdiv(w2, 256);
+  const long pq = (t % nx) * 256 + threadIdx.x;
+  const int s = (int)(t / nx);
   if (pq >= w2) return;
+  const int nw = a.nw, na = a.na, nsplit = a.nsplit;
   const int l0 = (int)((long)na * s / nsplit), l1 = (int)((long)na * (s + 1) / nsplit);
   const int p = (int)(pq / nw), q = (int)(pq - (long)p * nw);
+  const IOT<P>* bmo = (const IOT<P>*)a.bmo;
   double sj = 0.0, sk = 0.0;
   for (int l = l0; l < l1; ++l) {
     const double v = (double)bmo[(long)l * w2 + pq];
     sk = fma(v, v, sk);
-    sj = fma(d[(long)l * nw + p], d[(long)l * nw + q], sj);
+    sj = fma(a.d[(long)l * nw + p], a.d[(long)l * nw + q], sj);
   }
-  part[(2L * s) * w2 + pq] = sj;
-  part[(2L * s + 1) * w2 + pq] = sk;
+  a.part[(2L * s) * w2 + pq] = sj;
+  a.part[(2L * s + 1) * w2 + pq] = sk;
 }
 
-__global__ __launch_bounds__(256) void k_jk_mo_reduce(int nw, int nsplit, const double* __restrict__ part,
-                                                      double* __restrict__ J, double* __restrict__ K) {
-  const long w2 = (long)nw * nw;
-  const long pq = (long)blockIdx.x * 256 + threadIdx.x;
+template <int P, class Cfg>
+__host__ __device__ inline long jkr_tiles(const JkArgs& a) { return cdiv((long)a.nw * a.nw, 256); }
+template <int P, class Cfg>
+__device__ void jkr_tile(const JkArgs& a, long t, char*) {
+  const long w2 = (long)a.nw * a.nw;
+  const long pq = t * 256 + threadIdx.x;
   if (pq >= w2) return;
   double sj = 0.0, sk = 0.0;
-  for (int s = 0; s < nsplit; ++s) {
-    sj += part[(2L * s) * w2 + pq];
-    sk += part[(2L * s + 1) * w2 + pq];
+  for (int s = 0; s < a.nsplit; ++s) {
+    sj += a.part[(2L * s) * w2 + pq];
+    sk += a.part[(2L * s + 1) * w2 + pq];
   }
-  J[pq] = sj;
-  K[pq] = sk;
+  a.J[pq] = sj;
+  a.K[pq] = sk;
 }
 
 // Pair index of orbital p of Omega (explicit map or the default one).
@@ -356,36 +429,35 @@ __device__ __forceinline__ int pair_index(const int* pair_of, int p, int npairs,
 }
 
 // Coefficients A, B of E = 2 sum n_p H_pp + sum (A J + B K) (Eq. (2), PNOF7 or
-// PNOF5 Delta/Pi), with one energy partial per workgroup (fixed order).
-__global__ __launch_bounds__(256) void k_coef(int functional, int nw, int npairs, int ncwo,
-                                              const int* __restrict__ pair_of,
-                                              const double* __restrict__ occ,
-                                              const double* __restrict__ J, const double* __restrict__ K,
-                                              double* __restrict__ Ac, double* __restrict__ Bc,
-                                              double* __restrict__ epart) {
-  __shared__ double red[256];
+// PNOF5 Delta/Pi), with one energy partial per tile (fixed order).
+template <int P, class Cfg>
+__host__ __device__ inline long coef_tiles(const CoefArgs& a) { return cdiv((long)a.nw * a.nw, 256); }
+template <int P, class Cfg>
+__device__ void coef_tile(const CoefArgs& a, long t, char* smem) {
+  double* red = (double*)smem;
   const int tid = threadIdx.x;
+  const int nw = a.nw, npairs = a.npairs, ncwo = a.ncwo;
   const long w2 = (long)nw * nw;
-  const long idx = (long)blockIdx.x * 256 + tid;
+  const long idx = t * 256 + tid;
   double e = 0.0;
   if (idx < w2) {
     const int p = (int)(idx / nw), q = (int)(idx - (long)p * nw);
-    const double np = occ[p], nq = occ[q];
-    const int gp = pair_index(pair_of, p, npairs, ncwo), gq = pair_index(pair_of, q, npairs, ncwo);
-    double a, bb;
+    const double np = a.occ[p], nq = a.occ[q];
+    const int gp = pair_index(a.pair_of, p, npairs, ncwo), gq = pair_index(a.pair_of, q, npairs, ncwo);
+    double aa, bb;
     if (gp == gq) {
-      a = 0.0;
+      aa = 0.0;
       if (p == q) bb = np;
       else if (p >= npairs && q >= npairs) bb = sqrt(np * nq);
       else bb = -sqrt(np * nq);
     } else {
-      a = 2.0 * np * nq;
+      aa = 2.0 * np * nq;
       bb = -np * nq;
-      if (functional == RIF_PNOF7) bb -= sqrt(np * (1.0 - np)) * sqrt(nq * (1.0 - nq));
+      if (a.functional == RIF_PNOF7) bb -= sqrt(np * (1.0 - np)) * sqrt(nq * (1.0 - nq));
     }
-    Ac[idx] = a;
-    Bc[idx] = bb;
-    e = a * J[idx] + bb * K[idx];
+    a.Ac[idx] = aa;
+    a.Bc[idx] = bb;
+    e = aa * a.J[idx] + bb * a.K[idx];
   }
   red[tid] = e;
   __syncthreads();
@@ -393,59 +465,58 @@ __global__ __launch_bounds__(256) void k_coef(int functional, int nw, int npairs
     if (tid < s) red[tid] += red[tid + s];
     __syncthreads();
   }
-  if (tid == 0) epart[blockIdx.x] = red[0];
+  if (tid == 0) a.Ep[t] = red[0];
+  __syncthreads();
 }
 
 // H_pp = c_p^T H c_p, the energy (coefficient partials + 2 sum n_p H_pp, fixed
-// order) and the device-side validation of the occupations.  One workgroup.
-__global__ __launch_bounds__(256) void k_energy(int nw, int npairs, int ncwo, int nb, int nmo, int nparts,
-                                                const int* __restrict__ pair_of,
-                                                const double* __restrict__ occ,
-                                                const double* __restrict__ C,
-                                                const double* __restrict__ HC,
-                                                const double* __restrict__ epart,
-                                                double* __restrict__ energy, int* __restrict__ flag) {
+// order) and the device-side validation of the occupations.  One tile.
+template <int P, class Cfg>
+__host__ __device__ inline long energy_tiles(const EnergyArgs&) { return 1; }
+template <int P, class Cfg>
+__device__ void energy_tile(const EnergyArgs& a, long, char* smem) {
   constexpr int kStage = 2048;
-  __shared__ double socc[kStage];
-  __shared__ int spair[kStage];
-  __shared__ double red[256];
+  double* socc = (double*)smem;
+  int* spair = (int*)(socc + kStage);
+  double* red = (double*)(spair + kStage);
   const int tid = threadIdx.x;
+  const int nw = a.nw, npairs = a.npairs, ncwo = a.ncwo;
   const bool staged = nw <= kStage;
   if (staged) {
     for (int p = tid; p < nw; p += 256) {
-      socc[p] = occ[p];
-      spair[p] = pair_index(pair_of, p, npairs, ncwo);
+      socc[p] = a.occ[p];
+      spair[p] = pair_index(a.pair_of, p, npairs, ncwo);
     }
   }
   __syncthreads();
   int bad = 0;
   for (int p = tid; p < nw; p += 256) {
-    const double n = staged ? socc[p] : occ[p];
+    const double n = staged ? socc[p] : a.occ[p];
     if (!(n >= 0.0 && n <= 1.0)) bad |= kBadOcc;
-    const int g = staged ? spair[p] : pair_index(pair_of, p, npairs, ncwo);
+    const int g = staged ? spair[p] : pair_index(a.pair_of, p, npairs, ncwo);
     if (g < 0 || g >= npairs || (p < npairs && g != p)) bad |= kBadMap;
   }
   for (int g = tid; g < npairs; g += 256) {
     double s = 0.0;
     int cnt = 0;
     for (int p = 0; p < nw; ++p) {
-      const int gp = staged ? spair[p] : pair_index(pair_of, p, npairs, ncwo);
-      if (gp == g) { s += staged ? socc[p] : occ[p]; ++cnt; }
+      const int gp = staged ? spair[p] : pair_index(a.pair_of, p, npairs, ncwo);
+      if (gp == g) { s += staged ? socc[p] : a.occ[p]; ++cnt; }
     }
     if (!(fabs(s - 1.0) <= 1e-12)) bad |= kBadSum;
     if (cnt != 1 + ncwo) bad |= kBadCount;
   }
-  if (bad) atomicOr(flag, bad);
+  if (bad) atomicOr(a.flag, bad);
 
   double e = 0.0;
-  for (int i = tid; i < nparts; i += 256) e += epart[i];
+  for (int i = tid; i < a.nparts; i += 256) e += a.Ep[i];
   // H_pp: one wave per orbital, lanes over mu, fixed-order butterfly
   const int lane = tid & 63, wave = tid >> 6;
   for (int p = wave; p < nw; p += 4) {
     double h = 0.0;
-    for (int mu = lane; mu < nb; mu += 64) h = fma(C[(long)mu * nmo + p], HC[(long)mu * nw + p], h);
+    for (int mu = lane; mu < a.nb; mu += 64) h = fma(a.C[(long)mu * a.nmo + p], a.HC[(long)mu * nw + p], h);
     for (int off = 32; off > 0; off >>= 1) h += __shfl_xor(h, off, 64);
-    if (lane == 0) e += 2.0 * occ[p] * h;
+    if (lane == 0) e += 2.0 * a.occ[p] * h;
   }
   red[tid] = e;
   __syncthreads();
@@ -453,36 +524,90 @@ __global__ __launch_bounds__(256) void k_energy(int nw, int npairs, int ncwo, in
     if (tid < s) red[tid] += red[tid + s];
     __syncthreads();
   }
-  if (tid == 0) energy[0] = red[0];
+  if (tid == 0) a.energy[0] = red[0];
+  __syncthreads();
 }
+constexpr int kEnergySmem = 2048 * 8 + 2048 * 4 + 256 * 8;
 
-__global__ __launch_bounds__(256) void k_fock_reduce(int nb, int nw, int nsplit, const double* __restrict__ part,
-                                                     const double* __restrict__ occ,
-                                                     const double* __restrict__ HC, double* __restrict__ Y) {
-  const long n = (long)nb * nw;
-  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+// Y[mu][q] = n_q HC[mu][q] + sum_s Ypart[s][mu][q] (fixed order)
+template <int P, class Cfg>
+__host__ __device__ inline long fred_tiles(const FockRedArgs& a) { return cdiv((long)a.nb * a.nw, 256); }
+template <int P, class Cfg>
+__device__ void fred_tile(const FockRedArgs& a, long t, char*) {
+  const long n = (long)a.nb * a.nw;
+  const long i = t * 256 + threadIdx.x;
   if (i >= n) return;
-  const int q = (int)(i % nw);
-  double y = occ[q] * HC[i];
-  for (int s = 0; s < nsplit; ++s) y += part[(long)s * n + i];
-  Y[i] = y;
+  const int q = (int)(i % a.nw);
+  double y = a.occ[q] * a.HC[i];
+  for (int s = 0; s < a.nsplit; ++s) y += a.Yp[(long)s * n + i];
+  a.Y[i] = y;
 }
 
 // G[a][b] = 4 (L[a][b] - L[b][a]),  L[a][b] = lambda[a][b] for b < n_omega, else 0.
-__global__ __launch_bounds__(256) void k_grad(int nmo, int nw, const double* __restrict__ lam,
-                                              double* __restrict__ G) {
-  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+template <int P, class Cfg>
+__host__ __device__ inline long grad_tiles(const GradArgs& a) { return cdiv((long)a.nmo * a.nmo, 256); }
+template <int P, class Cfg>
+__device__ void grad_tile(const GradArgs& a, long t, char*) {
+  const int nmo = a.nmo, nw = a.nw;
+  const long i = t * 256 + threadIdx.x;
   if (i >= (long)nmo * nmo) return;
-  const int a = (int)(i / nmo), b = (int)(i - (long)a * nmo);
-  const double lab = b < nw ? lam[(long)a * nw + b] : 0.0;
-  const double lba = a < nw ? lam[(long)b * nw + a] : 0.0;
-  G[i] = 4.0 * (lab - lba);
+  const int r = (int)(i / nmo), c = (int)(i - (long)r * nmo);
+  const double lab = c < nw ? a.lam[(long)r * nw + c] : 0.0;
+  const double lba = r < nw ? a.lam[(long)c * nw + r] : 0.0;
+  a.G[i] = 4.0 * (lab - lba);
 }
 
+// ---- kernel wrappers ---------------------------------------------------------
+// k_<step>: one molecule, tile = (XCD-remapped) blockIdx.x.
+// k_<step>_g: persistent over a work-list spanning molecules: tile t of the
+// list belongs to molecule i with off[i] <= t < off[i+1]; workgroups stride the
+// list by gridDim.x.
+
+__device__ __forceinline__ int find_owner(const long* __restrict__ off, int n, long t) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+#define RIF_STEP_KERNELS(NAME, ARGS, SMEM_BYTES, NTHREADS, REMAP)                                  \
+  template <int P, class Cfg>                                                                      \
+  __global__ __launch_bounds__(NTHREADS) void k_##NAME(ARGS a) {                                   \
+    __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES];                                 \
+    const long t = REMAP ? xcd_remap(blockIdx.x, (long)gridDim.x) : (long)blockIdx.x;              \
+    NAME##_tile<P, Cfg>(a, t, smem);                                                               \
+  }                                                                                                \
+  template <int P, class Cfg>                                                                      \
+  __global__ __launch_bounds__(NTHREADS) void k_##NAME##_g(const ARGS* __restrict__ a,             \
+                                                           const long* __restrict__ off, int n,    \
+                                                           long total) {                           \
+    __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES];                                 \
+    for (long t = blockIdx.x; t < total; t += gridDim.x) {                                         \
+      const int i = find_owner(off, n, t);                                                         \
+      NAME##_tile<P, Cfg>(a[i], t - off[i], smem);                                                 \
+    }                                                                                              \
+  }
+
+#define GEMM_SMEM smem_bytes<typename EngineOf<P>::type, Cfg>()
+RIF_STEP_KERNELS(half, HalfArgs, GEMM_SMEM, Cfg::NT, false)
+RIF_STEP_KERNELS(mo, MoArgs, GEMM_SMEM, Cfg::NT, false)
+RIF_STEP_KERNELS(jao, JaoArgs, GEMM_SMEM, Cfg::NT, true)
+RIF_STEP_KERNELS(kao, KaoArgs, GEMM_SMEM, Cfg::NT, true)
+RIF_STEP_KERNELS(gemm, GemmArgs, GEMM_SMEM, Cfg::NT, false)
+RIF_STEP_KERNELS(fock, FockArgs, GEMM_SMEM, Cfg::NT, false)
+RIF_STEP_KERNELS(jkp, JkArgs, 16, 256, false)
+RIF_STEP_KERNELS(jkr, JkArgs, 16, 256, false)
+RIF_STEP_KERNELS(coef, CoefArgs, 256 * 8, 256, false)
+RIF_STEP_KERNELS(energy, EnergyArgs, kEnergySmem, 256, false)
+RIF_STEP_KERNELS(fred, FockRedArgs, 16, 256, false)
+RIF_STEP_KERNELS(grad, GradArgs, 16, 256, false)
+
 // ---------------------------------------------------------------------------
-// Launchers.  Each GEMM-shaped kernel exists in four tile variants per mode:
+// Launchers.  Each GEMM-shaped step exists in four tile variants per mode:
 //   0: 128x128   1: 64x64   2: 128x64   3: 64x128   (outputs per workgroup)
-// pick_variant() chooses one per (kernel, mode, shape): a wave-quantisation
+// pick_variant() chooses one per (step, mode, shape): a wave-quantisation
 // model by default, or the fastest measured one when autotuning is on.
 
 template <int BK> struct Vars;
@@ -498,6 +623,7 @@ template <> struct Vars<32> {  // BF16 split engines: smaller wave tiles (three 
   using V2 = TileCfg<128, 64, 32, 64, 32>;
   using V3 = TileCfg<64, 128, 32, 32, 64>;
 };
+struct Cfg256 { static constexpr int NT = 256; };  // element-wise steps
 
 template <int P, class F>
 static decltype(auto) dispatch(int v, F&& f) {
@@ -510,11 +636,9 @@ static decltype(auto) dispatch(int v, F&& f) {
   }
 }
 
-static const char* kPrecName[4] = {"f64", "f32", "bf16x3", "bf16x6"};
-
-// Relative time of a launch of `nwg` tiles of a variant with `wg_per_cu`
-// resident workgroups per CU: whole rounds of 256*wg_per_cu tiles, each round
-// as long as one tile running at 1/wg_per_cu of a CU.
+// Relative time of `nwg` tiles with `wg_per_cu` resident workgroups per CU:
+// whole rounds of 256*wg_per_cu tiles, each round as long as one tile running
+// at 1/wg_per_cu of a CU.
 static double est_cost(long nwg, int wg_per_cu, long tile_mn, double useful) {
   const long slots = 256L * wg_per_cu;
   const long rounds = (nwg + slots - 1) / slots;
@@ -527,7 +651,6 @@ static int wg_per_cu() {
   const int waves = 32 / Cfg::NWAVES;  // at most 8 waves per SIMD
   return std::max(1, std::min(std::min(lds, waves), 4));
 }
-
 template <class F>
 static int best_of(int nvar, F&& cost) {
   double best = 1e300;
@@ -539,220 +662,165 @@ static int best_of(int nvar, F&& cost) {
   return hv;
 }
 
-template <int P>
-static rif_status run_transform(rif_ctx* c, int nb, int na, int nw, int nmo, const double* b, const double* C,
-                                IOT<P>* bh, IOT<P>* bmo, double* d) {
-  const long nr = (long)na * nb, ns = (long)na * nw;
-  auto runh = [&](int v) {
-    return dispatch<P>(v, [&](auto cfg) {
-      using Cfg = decltype(cfg);
-      hipLaunchKernelGGL((k_half_transform<P, Cfg>), dim3(cdiv(nr, Cfg::BN), cdiv(nw, Cfg::BM)), dim3(Cfg::NT),
-                         0, c->stream, nb, nr, nw, nmo, b, C, bh);
-      return check_launch(c, "half_transform");
-    });
-  };
-  int hv = best_of(4, [&](int v) {
-    return dispatch<P>(v, [&](auto cfg) {
-      using Cfg = decltype(cfg);
-      const double useful = (double)nw / (cdiv(nw, Cfg::BM) * Cfg::BM);
-      return est_cost((long)cdiv(nr, Cfg::BN) * cdiv(nw, Cfg::BM), wg_per_cu<P, Cfg>(), Cfg::BM * Cfg::BN, useful);
-    });
-  });
-  int v = pick_variant(c, "half_transform", {P, nb, na, nw, nmo}, 4, hv, runh);
-  if (v < 0) return RIF_EHIP;
-  rif_status st;
-  {
-    ProfScope ps(c, "half_transform");
-    if ((st = runh(v))) return st;
-  }
-  auto runm = [&](int v) {
-    return dispatch<P>(v, [&](auto cfg) {
-      using Cfg = decltype(cfg);
-      hipLaunchKernelGGL((k_mo_transform<P, Cfg>), dim3(cdiv(ns, Cfg::BM), cdiv(nw, Cfg::BN)), dim3(Cfg::NT), 0,
-                         c->stream, nb, na, nw, nmo, bh, C, bmo, d);
-      return check_launch(c, "mo_transform");
-    });
-  };
-  hv = best_of(4, [&](int v) {
-    return dispatch<P>(v, [&](auto cfg) {
-      using Cfg = decltype(cfg);
-      const double useful = (double)nw / (cdiv(nw, Cfg::BN) * Cfg::BN);
-      return est_cost((long)cdiv(ns, Cfg::BM) * cdiv(nw, Cfg::BN), wg_per_cu<P, Cfg>(), Cfg::BM * Cfg::BN, useful);
-    });
-  });
-  v = pick_variant(c, "mo_transform", {P, nb, na, nw, nmo}, 4, hv, runm);
-  if (v < 0) return RIF_EHIP;
-  ProfScope ps(c, "mo_transform");
-  return runm(v);
+// Fraction of each tile that lands on real outputs, per step (for the model).
+template <class Cfg> static double useful_half(const HalfArgs& a) { return (double)a.nw / (cdiv(a.nw, Cfg::BM) * Cfg::BM); }
+template <class Cfg> static double useful_mo(const MoArgs& a) { return (double)a.nw / (cdiv(a.nw, Cfg::BN) * Cfg::BN); }
+template <class Cfg> static double useful_jao(const JaoArgs& a) { return (double)a.nw / (cdiv(a.nw, Cfg::BM) * Cfg::BM); }
+template <class Cfg> static double useful_kao(const KaoArgs& a) {
+  const long nbk = cdiv(a.nb, Cfg::BM);
+  return (double)a.nb * (a.nb + 1) / 2 / (nbk * (nbk + 1) / 2 * (double)Cfg::BM * Cfg::BM);
+}
+template <class Cfg> static double useful_fock(const FockArgs& a) {
+  return (double)a.nb * a.nw / ((double)cdiv(a.nb, Cfg::BM) * Cfg::BM * cdiv(a.nw, Cfg::BN) * Cfg::BN);
 }
 
+// Single-molecule launch of a GEMM-shaped step with variant selection.
+#define RIF_GEMM_STEP(NAME, ARGS, LABEL, NVAR, ...)                                                     \
+  template <int P>                                                                                      \
+  static rif_status step_##NAME(rif_ctx* c, const ARGS& a) {                                            \
+    auto run = [&](int v) {                                                                             \
+      return dispatch<P>(v, [&](auto cfg) {                                                             \
+        using Cfg = decltype(cfg);                                                                      \
+        if constexpr (NVAR == 2 && Cfg::BM != Cfg::BN) {                                                \
+          return fail(c, RIF_ENOTSUP, LABEL ": non-square tile variant");                               \
+        } else {                                                                                        \
+          hipLaunchKernelGGL((k_##NAME<P, Cfg>), dim3((unsigned)NAME##_tiles<P, Cfg>(a)), dim3(Cfg::NT), \
+                             0, c->stream, a);                                                          \
+          return check_launch(c, LABEL);                                                                \
+        }                                                                                               \
+      });                                                                                               \
+    };                                                                                                  \
+    const int hv = best_of(NVAR, [&](int v) {                                                           \
+      return dispatch<P>(v, [&](auto cfg) {                                                             \
+        using Cfg = decltype(cfg);                                                                      \
+        return est_cost(NAME##_tiles<P, Cfg>(a), wg_per_cu<P, Cfg>(), Cfg::BM * Cfg::BN,                \
+                        useful_##NAME<Cfg>(a));                                                         \
+      });                                                                                               \
+    });                                                                                                 \
+    const int v = pick_variant(c, LABEL, {P, __VA_ARGS__}, NVAR, hv, run);                              \
+    if (v < 0) return RIF_EHIP;                                                                         \
+    ProfScope ps(c, LABEL);                                                                             \
+    return run(v);                                                                                      \
+  }
+
+RIF_GEMM_STEP(half, HalfArgs, "half_transform", 4, a.nb, a.nr, a.nw, a.nmo)
+RIF_GEMM_STEP(mo, MoArgs, "mo_transform", 4, a.nb, a.na, a.nw, a.nmo)
+RIF_GEMM_STEP(jao, JaoArgs, "jao", 4, a.nb, a.na, a.nw)
+RIF_GEMM_STEP(kao, KaoArgs, "kao", 2, a.nb, a.na, a.nw)
+RIF_GEMM_STEP(fock, FockArgs, "fock", 4, a.nb, a.nw, a.nmo, a.nsplit)
+
+// Fixed-shape steps (64x64 FP64 GEMM tiles, 256-thread element-wise tiles).
+using CfgSmall = Vars<16>::V1;
+#define RIF_FIXED_STEP(NAME, ARGS, LABEL, PP, CFG)                                              \
+  static rif_status step1_##NAME(rif_ctx* c, const ARGS& a) {                                  \
+    ProfScope ps(c, LABEL);                                                                     \
+    hipLaunchKernelGGL((k_##NAME<PP, CFG>), dim3((unsigned)NAME##_tiles<PP, CFG>(a)), dim3(CFG::NT), 0, \
+                       c->stream, a);                                                           \
+    return check_launch(c, LABEL);                                                             \
+  }
+RIF_FIXED_STEP(gemm, GemmArgs, "small_gemm", kF64, CfgSmall)
+RIF_FIXED_STEP(coef, CoefArgs, "coef", kF64, Cfg256)
+RIF_FIXED_STEP(energy, EnergyArgs, "energy", kF64, Cfg256)
+RIF_FIXED_STEP(fred, FockRedArgs, "fock_reduce", kF64, Cfg256)
+RIF_FIXED_STEP(grad, GradArgs, "grad", kF64, Cfg256)
 template <int P>
-static rif_status run_jk_mo(rif_ctx* c, int na, int nw, const IOT<P>* bmo, const double* d, double* J, double* K) {
-  const long w2 = (long)nw * nw;
-  const int nx = cdiv(w2, 256);
-  const int nsplit = (int)std::max(1L, std::min((long)na, (1024L + nx - 1) / nx));
-  Carve cv;
-  const size_t o_part = cv.take<double>(2L * nsplit * w2);
-  rif_status st = ws_reserve(c, cv.off);
-  if (st) return st;
-  double* part = (double*)((char*)c->ws + o_part);
+static rif_status step1_jk(rif_ctx* c, const JkArgs& a) {
+  rif_status st;
   {
     ProfScope ps(c, "jk_mo_partial");
-    hipLaunchKernelGGL(k_jk_mo_partial<IOT<P>>, dim3(nx, nsplit), dim3(256), 0, c->stream, na, nw, nsplit, bmo, d,
-                       part);
+    hipLaunchKernelGGL((k_jkp<P, Cfg256>), dim3((unsigned)jkp_tiles<P, Cfg256>(a)), dim3(256), 0, c->stream, a);
+    if ((st = check_launch(c, "jk_mo_partial"))) return st;
   }
-  if ((st = check_launch(c, "jk_mo_partial"))) return st;
   ProfScope ps(c, "jk_mo_reduce");
-  hipLaunchKernelGGL(k_jk_mo_reduce, dim3(nx), dim3(256), 0, c->stream, nw, nsplit, part, J, K);
+  hipLaunchKernelGGL((k_jkr<P, Cfg256>), dim3((unsigned)jkr_tiles<P, Cfg256>(a)), dim3(256), 0, c->stream, a);
   return check_launch(c, "jk_mo_reduce");
 }
 
-template <int TMU, int TNU>
-static long jao_active(int nb) {  // blocks that touch the upper triangle
-  long n = 0;
-  for (int bi = 0; bi < cdiv(nb, TMU); ++bi) n += std::max(0, cdiv(nb, TNU) - jao_first_col(bi, TMU, TNU));
-  return n;
-}
-
-template <int P>
-static rif_status run_jk_ao(rif_ctx* c, int nb, int na, int nw, const double* b, const IOT<P>* bh,
-                            const double* d, IOT<P>* Jn, IOT<P>* Kn) {
-  rif_status st;
-  constexpr int TNU = 16;
-  auto runj = [&](int v) {
-    return dispatch<P>(v, [&](auto cfg) {
-      using Cfg = decltype(cfg);
-      const long n = jao_active<Cfg::BN / TNU, TNU>(nb) * cdiv(nw, Cfg::BM);
-      hipLaunchKernelGGL((k_jao<P, Cfg, TNU>), dim3((unsigned)n), dim3(Cfg::NT), 0, c->stream, nb, na, nw, b, d, Jn);
-      return check_launch(c, "jao");
-    });
-  };
-  int hv = best_of(4, [&](int v) {
-    return dispatch<P>(v, [&](auto cfg) {
-      using Cfg = decltype(cfg);
-      const long n = jao_active<Cfg::BN / TNU, TNU>(nb) * cdiv(nw, Cfg::BM);
-      const double useful = (double)nw / (cdiv(nw, Cfg::BM) * Cfg::BM);
-      return est_cost(n, wg_per_cu<P, Cfg>(), Cfg::BM * Cfg::BN, useful);
-    });
-  });
-  int v = pick_variant(c, "jao", {P, nb, na, nw}, 4, hv, runj);
-  if (v < 0) return RIF_EHIP;
-  {
-    ProfScope ps(c, "jao");
-    if ((st = runj(v))) return st;
+// ---- workspace plan of one molecule (shared by the single and batched paths)
+struct Plan {
+  int nb, na, nw, nmo, npairs, ncwo;
+  int jk_nsplit, fock_nsplit, fock_per, nparts;
+  size_t o_part, o_hc, o_a, o_b, o_yp, o_y, o_ep, bytes;
+  Plan(int nb_, int na_, int npairs_, int ncwo_, int nmo_) {
+    nb = nb_; na = na_; npairs = npairs_; ncwo = ncwo_; nmo = nmo_;
+    nw = npairs * (1 + ncwo);
+    const long w2 = (long)nw * nw;
+    const long nx = cdiv(w2, 256);
+    jk_nsplit = (int)std::max(1L, std::min((long)na, (1024L + nx - 1) / nx));
+    // fock split-K over the stacked slabs, sized so a 64x64-tile launch has >= 1024 tiles
+    const int slabs = 2 * nw;
+    const long mt = cdiv(nb, 64), nt = cdiv(nw, 64);
+    int ns = std::max(1, std::min(slabs, cdiv(1024, mt * nt)));
+    fock_per = cdiv(slabs, ns);
+    fock_nsplit = cdiv(slabs, fock_per);
+    nparts = (int)nx;
+    Carve cv;
+    o_part = cv.take<double>(2L * jk_nsplit * w2);
+    o_hc = cv.take<double>((size_t)nb * nw);
+    o_a = cv.take<double>((size_t)w2);
+    o_b = cv.take<double>((size_t)w2);
+    o_yp = cv.take<double>((size_t)fock_nsplit * nb * nw);
+    o_y = cv.take<double>((size_t)nb * nw);
+    o_ep = cv.take<double>((size_t)nparts);
+    bytes = cv.off;
   }
-  // K: square tiles only (variants 0 and 1)
-  auto runk = [&](int v) {
-    return dispatch<P>(v, [&](auto cfg) {
-      using Cfg = decltype(cfg);
-      if constexpr (Cfg::BM == Cfg::BN) {
-        const long nbk = cdiv(nb, Cfg::BM);
-        hipLaunchKernelGGL((k_kao<P, Cfg>), dim3((unsigned)(nbk * (nbk + 1) / 2 * nw)), dim3(Cfg::NT), 0,
-                           c->stream, nb, na, nw, bh, Kn);
-        return check_launch(c, "kao");
-      } else {
-        return fail(c, RIF_ENOTSUP, "kao: non-square tile variant");
-      }
-    });
-  };
-  hv = best_of(2, [&](int v) {
-    return dispatch<P>(v, [&](auto cfg) {
-      using Cfg = decltype(cfg);
-      const long nbk = cdiv(nb, Cfg::BM);
-      const double useful = (double)nb * (nb + 1) / 2 / (nbk * (nbk + 1) / 2 * (double)Cfg::BM * Cfg::BM);
-      return est_cost(nbk * (nbk + 1) / 2 * nw, wg_per_cu<P, Cfg>(), Cfg::BM * Cfg::BN, useful);
-    });
-  });
-  v = pick_variant(c, "kao", {P, nb, na, nw}, 2, hv, runk);
-  if (v < 0) return RIF_EHIP;
-  ProfScope ps(c, "kao");
-  return runk(v);
+};
+
+// All argument blocks of one build of one molecule, workspace at `ws`.
+struct BuildArgs {
+  HalfArgs half; MoArgs mo; JkArgs jk; JaoArgs jao; KaoArgs kao;
+  GemmArgs hc; CoefArgs coef; EnergyArgs energy; FockArgs fock; FockRedArgs fred; GemmArgs lam; GradArgs grad;
+};
+static BuildArgs make_build_args(const Plan& pl, const rif_instance& in, int functional, char* ws, int* flag) {
+  BuildArgs A;
+  const int nb = pl.nb, na = pl.na, nw = pl.nw, nmo = pl.nmo;
+  double* part = (double*)(ws + pl.o_part);
+  double* HC = (double*)(ws + pl.o_hc);
+  double* Ac = (double*)(ws + pl.o_a);
+  double* Bc = (double*)(ws + pl.o_b);
+  double* Yp = (double*)(ws + pl.o_yp);
+  double* Y = (double*)(ws + pl.o_y);
+  double* Ep = (double*)(ws + pl.o_ep);
+  A.half = HalfArgs{nb, nw, nmo, (long)na * nb, in.b, in.C, in.b_half};
+  A.mo = MoArgs{nb, na, nw, nmo, in.b_half, in.C, in.b_mo, in.d};
+  A.jk = JkArgs{na, nw, pl.jk_nsplit, in.b_mo, in.d, part, in.J, in.K};
+  A.jao = JaoArgs{nb, na, nw, in.b, in.d, in.Jn};
+  A.kao = KaoArgs{nb, na, nw, in.b_half, in.Kn};
+  A.hc = GemmArgs{nb, nw, nb, in.H, (long)nb, in.C, (long)nmo, HC, (long)nw};
+  A.coef = CoefArgs{functional, nw, pl.npairs, pl.ncwo, in.pair_of, in.occ, in.J, in.K, Ac, Bc, Ep};
+  A.energy = EnergyArgs{nw, pl.npairs, pl.ncwo, nb, nmo, pl.nparts, in.pair_of, in.occ, in.C, HC, Ep, in.energy, flag};
+  A.fock = FockArgs{nb, nw, nmo, pl.fock_per, pl.fock_nsplit, in.Jn, in.Kn, Ac, Bc, in.C, Yp};
+  A.fred = FockRedArgs{nb, nw, pl.fock_nsplit, Yp, in.occ, HC, Y};
+  A.lam = GemmArgs{nmo, nw, nb, in.C, (long)nmo, Y, (long)nw, in.lambda, (long)nw};
+  A.grad = GradArgs{nmo, nw, in.lambda, in.grad};
+  return A;
 }
 
 template <int P>
-static rif_status run_energy_grad(rif_ctx* c, int functional, int nb, int nmo, int npairs, int ncwo,
-                                  const int* pair_of, const double* H, const double* C, const double* occ,
-                                  const double* J, const double* K, const IOT<P>* Jn, const IOT<P>* Kn,
-                                  double* energy, double* lambda, double* grad) {
-  const int nw = npairs * (1 + ncwo);
-  using CS = Vars<16>::V1;
-  const int slabs = 2 * nw;
-  // split-K over the stacked slabs, sized so a 64x64-tile launch has >= 1024 tiles
-  const int mt = cdiv(nb, 64), nt = cdiv(nw, 64);
-  int nsplit = std::max(1, std::min(slabs, cdiv(1024, (long)mt * nt)));
-  const int per = cdiv(slabs, nsplit);
-  nsplit = cdiv(slabs, per);
-  const int nparts = cdiv((long)nw * nw, 256);
-  Carve cv;
-  const size_t o_hc = cv.take<double>((size_t)nb * nw);
-  const size_t o_a = cv.take<double>((size_t)nw * nw);
-  const size_t o_b = cv.take<double>((size_t)nw * nw);
-  const size_t o_yp = cv.take<double>((size_t)nsplit * nb * nw);
-  const size_t o_y = cv.take<double>((size_t)nb * nw);
-  const size_t o_ep = cv.take<double>((size_t)nparts);
-  rif_status st = ws_reserve(c, cv.off);
+static rif_status run_transform(rif_ctx* c, const HalfArgs& h, const MoArgs& m) {
+  rif_status st = step_half<P>(c, h);
   if (st) return st;
-  char* w = (char*)c->ws;
-  double *HC = (double*)(w + o_hc), *Ac = (double*)(w + o_a), *Bc = (double*)(w + o_b);
-  double *Yp = (double*)(w + o_yp), *Y = (double*)(w + o_y), *Ep = (double*)(w + o_ep);
-  {
-    ProfScope ps(c, "hc_gemm");
-    hipLaunchKernelGGL(k_gemm_tn<CS>, dim3(cdiv(nb, CS::BM), cdiv(nw, CS::BN)), dim3(CS::NT), 0, c->stream,
-                       nb, nw, nb, H, (long)nb, C, (long)nmo, HC, (long)nw);
-  }
-  if ((st = check_launch(c, "hc_gemm"))) return st;
-  {
-    ProfScope ps(c, "coef");
-    hipLaunchKernelGGL(k_coef, dim3(nparts), dim3(256), 0, c->stream, functional, nw, npairs, ncwo, pair_of, occ,
-                       J, K, Ac, Bc, Ep);
-  }
-  if ((st = check_launch(c, "coef"))) return st;
-  {
-    ProfScope ps(c, "energy");
-    hipLaunchKernelGGL(k_energy, dim3(1), dim3(256), 0, c->stream, nw, npairs, ncwo, nb, nmo, nparts, pair_of, occ,
-                       C, HC, Ep, energy, c->dflag);
-  }
-  if ((st = check_launch(c, "energy"))) return st;
-  auto runf = [&](int v) {
-    return dispatch<P>(v, [&](auto cfg) {
-      using Cfg = decltype(cfg);
-      hipLaunchKernelGGL((k_fock<P, Cfg>), dim3(cdiv(nb, Cfg::BM), cdiv(nw, Cfg::BN), nsplit), dim3(Cfg::NT), 0,
-                         c->stream, nb, nw, nmo, per, Jn, Kn, Ac, Bc, C, Yp);
-      return check_launch(c, "fock");
-    });
-  };
-  const int hv = best_of(4, [&](int v) {
-    return dispatch<P>(v, [&](auto cfg) {
-      using Cfg = decltype(cfg);
-      const long n = (long)cdiv(nb, Cfg::BM) * cdiv(nw, Cfg::BN) * nsplit;
-      const double useful = (double)nb * nw / ((double)cdiv(nb, Cfg::BM) * Cfg::BM * cdiv(nw, Cfg::BN) * Cfg::BN);
-      return est_cost(n, wg_per_cu<P, Cfg>(), Cfg::BM * Cfg::BN, useful);
-    });
-  });
-  const int v = pick_variant(c, "fock", {P, nb, nw, nmo, nsplit}, 4, hv, runf);
-  if (v < 0) return RIF_EHIP;
-  {
-    ProfScope ps(c, "fock");
-    if ((st = runf(v))) return st;
-  }
-  {
-    ProfScope ps(c, "fock_reduce");
-    hipLaunchKernelGGL(k_fock_reduce, dim3(cdiv((long)nb * nw, 256)), dim3(256), 0, c->stream, nb, nw, nsplit,
-                       Yp, occ, HC, Y);
-  }
-  if ((st = check_launch(c, "fock_reduce"))) return st;
-  {
-    ProfScope ps(c, "lambda_gemm");
-    hipLaunchKernelGGL(k_gemm_tn<CS>, dim3(cdiv(nmo, CS::BM), cdiv(nw, CS::BN)), dim3(CS::NT), 0, c->stream,
-                       nmo, nw, nb, C, (long)nmo, Y, (long)nw, lambda, (long)nw);
-  }
-  if ((st = check_launch(c, "lambda_gemm"))) return st;
-  ProfScope ps(c, "grad");
-  hipLaunchKernelGGL(k_grad, dim3(cdiv((long)nmo * nmo, 256)), dim3(256), 0, c->stream, nmo, nw, lambda, grad);
-  return check_launch(c, "grad");
+  return step_mo<P>(c, m);
+}
+template <int P>
+static rif_status run_jk_ao(rif_ctx* c, const JaoArgs& j, const KaoArgs& k) {
+  rif_status st = step_jao<P>(c, j);
+  if (st) return st;
+  return step_kao<P>(c, k);
+}
+template <int P>
+static rif_status run_energy_grad(rif_ctx* c, const BuildArgs& A) {
+  rif_status st;
+  if ((st = step1_gemm(c, A.hc))) return st;
+  if ((st = step1_coef(c, A.coef))) return st;
+  if ((st = step1_energy(c, A.energy))) return st;
+  if ((st = step_fock<P>(c, A.fock))) return st;
+  if ((st = step1_fred(c, A.fred))) return st;
+  if ((st = step1_gemm(c, A.lam))) return st;
+  return step1_grad(c, A.grad);
 }
 
-// ---- mode dispatch (the only entry points the ABI layer calls) ----
+// ---- mode dispatch (the single-molecule entry points the ABI layer calls) ----
 #define RIF_PREC_SWITCH(prec, call)                                              \
   switch (prec) {                                                                \
     case kF64: { constexpr int P = kF64; return call; }                          \
@@ -762,26 +830,353 @@ static rif_status run_energy_grad(rif_ctx* c, int functional, int nb, int nmo, i
     default: return fail(c, RIF_ENOTSUP, "precision mode not available");       \
   }
 
+static bool prec_ok(int prec) { return prec >= kF64 && prec <= kBF16x6; }
+
 rif_status op_transform(rif_ctx* c, int prec, int nb, int na, int nw, int nmo, const double* b, const double* C,
                         void* bh, void* bmo, double* d) {
-  RIF_PREC_SWITCH(prec, run_transform<P>(c, nb, na, nw, nmo, b, C, (IOT<P>*)bh, (IOT<P>*)bmo, d))
+  const HalfArgs h{nb, nw, nmo, (long)na * nb, b, C, bh};
+  const MoArgs m{nb, na, nw, nmo, bh, C, bmo, d};
+  RIF_PREC_SWITCH(prec, run_transform<P>(c, h, m))
 }
 
 rif_status op_jk_mo(rif_ctx* c, int prec, int na, int nw, const void* bmo, const double* d, double* J, double* K) {
-  RIF_PREC_SWITCH(prec, run_jk_mo<P>(c, na, nw, (const IOT<P>*)bmo, d, J, K))
+  if (!prec_ok(prec)) return fail(c, RIF_ENOTSUP, "precision mode not available");
+  const long w2 = (long)nw * nw;
+  const long nx = cdiv(w2, 256);
+  const int nsplit = (int)std::max(1L, std::min((long)na, (1024L + nx - 1) / nx));
+  Carve cv;
+  const size_t o_part = cv.take<double>(2L * nsplit * w2);
+  rif_status st = ws_reserve(c, cv.off);
+  if (st) return st;
+  const JkArgs a{na, nw, nsplit, bmo, d, (double*)((char*)c->ws + o_part), J, K};
+  RIF_PREC_SWITCH(prec, step1_jk<P>(c, a))
 }
 
 rif_status op_jk_ao(rif_ctx* c, int prec, int nb, int na, int nw, const double* b, const void* bh,
                     const double* d, void* Jn, void* Kn) {
-  RIF_PREC_SWITCH(prec, run_jk_ao<P>(c, nb, na, nw, b, (const IOT<P>*)bh, d, (IOT<P>*)Jn, (IOT<P>*)Kn))
+  const JaoArgs j{nb, na, nw, b, d, Jn};
+  const KaoArgs k{nb, na, nw, bh, Kn};
+  RIF_PREC_SWITCH(prec, run_jk_ao<P>(c, j, k))
 }
 
 rif_status op_energy_grad(rif_ctx* c, int prec, int functional, int nb, int nmo, int npairs, int ncwo,
                           const int* pair_of, const double* H, const double* C, const double* occ,
                           const double* J, const double* K, const void* Jn, const void* Kn, double* energy,
                           double* lambda, double* grad) {
-  RIF_PREC_SWITCH(prec, run_energy_grad<P>(c, functional, nb, nmo, npairs, ncwo, pair_of, H, C, occ, J, K,
-                                           (const IOT<P>*)Jn, (const IOT<P>*)Kn, energy, lambda, grad))
+  if (!prec_ok(prec)) return fail(c, RIF_ENOTSUP, "precision mode not available");
+  const Plan pl(nb, 1, npairs, ncwo, nmo);
+  rif_status st = ws_reserve(c, pl.bytes);
+  if (st) return st;
+  rif_instance in{};
+  in.n_bf = nb; in.n_aux = 1; in.n_pairs = npairs; in.n_cwo = ncwo; in.n_mo = nmo;
+  in.H = H; in.C = C; in.occ = occ; in.pair_of = pair_of; in.J = (double*)J; in.K = (double*)K;
+  in.Jn = (void*)Jn; in.Kn = (void*)Kn; in.energy = energy; in.lambda = lambda; in.grad = grad;
+  const BuildArgs A = make_build_args(pl, in, functional, (char*)c->ws, c->dflag);
+  RIF_PREC_SWITCH(prec, run_energy_grad<P>(c, A))
+}
+
+// ---------------------------------------------------------------------------
+// Batched builds of many molecules.  Every step is one persistent grouped
+// launch over a work-list spanning all molecules (largest molecules first, so
+// the small ones fill the tail), each step's tile variant chosen for the
+// batch as a whole.  The launch sequence can be captured in a hipGraph once
+// and replayed; nothing in it allocates or sets memory.
+
+struct GroupStep {
+  std::string name;
+  int nvar = 1;              // tile variants available (1 for fixed steps)
+  int variant = 0;
+  void* args_d = nullptr;    // device array of per-molecule argument blocks
+  long* off_d = nullptr;     // device [nvar][n+1] tile offsets
+  std::vector<long> total;   // per variant
+  std::vector<int> grid;     // per variant
+};
+
+struct BatchImpl {
+  rif_ctx* c = nullptr;
+  int prec = 0, n = 0;
+  std::vector<int> order;    // molecule indices, largest first
+  void* ws = nullptr;        // workspace of all molecules
+  std::vector<void*> dev;    // device allocations to free
+  GroupStep half, mo, jkp, jkr, jao, kao, hc, coef, energy, fock, fred, lam, grad;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+template <int P, class Cfg, class Args, class TilesFn>
+static void group_offsets(const std::vector<Args>& a, TilesFn tiles, std::vector<long>& off) {
+  off.assign(a.size() + 1, 0);
+  for (size_t i = 0; i < a.size(); ++i) off[i + 1] = off[i] + tiles(a[i]);
+}
+
+#define RIF_GROUP_SETUP(NAME, ARGS, LABEL, NVAR)                                                           \
+  template <int P>                                                                                         \
+  static rif_status setup_##NAME(BatchImpl* B, const std::vector<ARGS>& a) {                              \
+    GroupStep& g = B->NAME;                                                                                \
+    g.name = LABEL;                                                                                        \
+    g.nvar = NVAR;                                                                                         \
+    const int n = (int)a.size();                                                                           \
+    std::vector<long> offs((size_t)NVAR * (n + 1));                                                        \
+    g.total.assign(NVAR, 0);                                                                               \
+    g.grid.assign(NVAR, 0);                                                                                \
+    for (int v = 0; v < NVAR; ++v) {                                                                       \
+      dispatch<P>(v, [&](auto cfg) {                                                                       \
+        using Cfg = decltype(cfg);                                                                         \
+        long acc = 0;                                                                                      \
+        for (int i = 0; i < n; ++i) {                                                                      \
+          offs[(size_t)v * (n + 1) + i] = acc;                                                             \
+          acc += NAME##_tiles<P, Cfg>(a[i]);                                                               \
+        }                                                                                                  \
+        offs[(size_t)v * (n + 1) + n] = acc;                                                               \
+        g.total[v] = acc;                                                                                  \
+        g.grid[v] = (int)std::min(acc, 256L * wg_per_cu<P, Cfg>());                                        \
+        return 0;                                                                                          \
+      });                                                                                                  \
+    }                                                                                                      \
+    if (hipMalloc(&g.args_d, sizeof(ARGS) * n) != hipSuccess ||                                           \
+        hipMalloc((void**)&g.off_d, sizeof(long) * offs.size()) != hipSuccess)                            \
+      return fail(B->c, RIF_ENOMEM, "batch: device allocation failed");                                    \
+    B->dev.push_back(g.args_d);                                                                            \
+    B->dev.push_back(g.off_d);                                                                             \
+    if (hipMemcpy(g.args_d, a.data(), sizeof(ARGS) * n, hipMemcpyHostToDevice) != hipSuccess ||           \
+        hipMemcpy(g.off_d, offs.data(), sizeof(long) * offs.size(), hipMemcpyHostToDevice) != hipSuccess) \
+      return fail(B->c, RIF_EHIP, "batch: upload failed");                                                 \
+    return RIF_OK;                                                                                         \
+  }                                                                                                        \
+  template <int P>                                                                                         \
+  static rif_status launch_##NAME(BatchImpl* B, int v) {                                                   \
+    GroupStep& g = B->NAME;                                                                                \
+    const int n = B->n;                                                                                    \
+    return dispatch<P>(v, [&](auto cfg) {                                                                  \
+      using Cfg = decltype(cfg);                                                                           \
+      if constexpr (NVAR == 2 && Cfg::BM != Cfg::BN) {                                                     \
+        return fail(B->c, RIF_ENOTSUP, LABEL ": non-square tile variant");                                 \
+      } else {                                                                                             \
+        if (g.total[v] == 0) return RIF_OK;                                                                \
+        hipLaunchKernelGGL((k_##NAME##_g<P, Cfg>), dim3(g.grid[v]), dim3(Cfg::NT), 0, B->c->stream,        \
+                           (const ARGS*)g.args_d, g.off_d + (size_t)v * (n + 1), n, g.total[v]);           \
+        return check_launch(B->c, LABEL);                                                                  \
+      }                                                                                                    \
+    });                                                                                                    \
+  }
+
+// element-wise steps are not tile variants; dispatch<> is only used for the count
+#define RIF_GROUP_FIXED(NAME, TILE, ARGS, LABEL, PP, CFG)                                                  \
+  static rif_status setup_##NAME(BatchImpl* B, const std::vector<ARGS>& a) {                              \
+    GroupStep& g = B->NAME;                                                                                \
+    g.name = LABEL;                                                                                        \
+    g.nvar = 1;                                                                                            \
+    const int n = (int)a.size();                                                                           \
+    std::vector<long> offs(n + 1, 0);                                                                      \
+    for (int i = 0; i < n; ++i) offs[i + 1] = offs[i] + TILE##_tiles<PP, CFG>(a[i]);                      \
+    g.total.assign(1, offs[n]);                                                                            \
+    g.grid.assign(1, (int)std::min(offs[n], 256L * 8));                                                    \
+    if (hipMalloc(&g.args_d, sizeof(ARGS) * n) != hipSuccess ||                                           \
+        hipMalloc((void**)&g.off_d, sizeof(long) * (n + 1)) != hipSuccess)                                \
+      return fail(B->c, RIF_ENOMEM, "batch: device allocation failed");                                    \
+    B->dev.push_back(g.args_d);                                                                            \
+    B->dev.push_back(g.off_d);                                                                             \
+    if (hipMemcpy(g.args_d, a.data(), sizeof(ARGS) * n, hipMemcpyHostToDevice) != hipSuccess ||           \
+        hipMemcpy(g.off_d, offs.data(), sizeof(long) * (n + 1), hipMemcpyHostToDevice) != hipSuccess)     \
+      return fail(B->c, RIF_EHIP, "batch: upload failed");                                                 \
+    return RIF_OK;                                                                                         \
+  }                                                                                                        \
+  static rif_status launch_##NAME(BatchImpl* B, int) {                                                     \
+    GroupStep& g = B->NAME;                                                                                \
+    if (g.total[0] == 0) return RIF_OK;                                                                    \
+    hipLaunchKernelGGL((k_##TILE##_g<PP, CFG>), dim3(g.grid[0]), dim3(CFG::NT), 0, B->c->stream,           \
+                       (const ARGS*)g.args_d, g.off_d, B->n, g.total[0]);                                  \
+    return check_launch(B->c, LABEL);                                                                      \
+  }
+
+RIF_GROUP_SETUP(half, HalfArgs, "g_half_transform", 4)
+RIF_GROUP_SETUP(mo, MoArgs, "g_mo_transform", 4)
+RIF_GROUP_SETUP(jao, JaoArgs, "g_jao", 4)
+RIF_GROUP_SETUP(kao, KaoArgs, "g_kao", 2)
+RIF_GROUP_SETUP(fock, FockArgs, "g_fock", 4)
+#define RIF_GROUP_FIXED_P(NAME, ARGS, LABEL)                                                               \
+  template <int P>                                                                                         \
+  static rif_status setup_##NAME(BatchImpl* B, const std::vector<ARGS>& a) {                              \
+    GroupStep& g = B->NAME;                                                                                \
+    g.name = LABEL;                                                                                        \
+    g.nvar = 1;                                                                                            \
+    const int n = (int)a.size();                                                                           \
+    std::vector<long> offs(n + 1, 0);                                                                      \
+    for (int i = 0; i < n; ++i) offs[i + 1] = offs[i] + NAME##_tiles<P, Cfg256>(a[i]);                    \
+    g.total.assign(1, offs[n]);                                                                            \
+    g.grid.assign(1, (int)std::min(offs[n], 256L * 8));                                                    \
+    if (hipMalloc(&g.args_d, sizeof(ARGS) * n) != hipSuccess ||                                           \
+        hipMalloc((void**)&g.off_d, sizeof(long) * (n + 1)) != hipSuccess)                                \
+      return fail(B->c, RIF_ENOMEM, "batch: device allocation failed");                                    \
+    B->dev.push_back(g.args_d);                                                                            \
+    B->dev.push_back(g.off_d);                                                                             \
+    if (hipMemcpy(g.args_d, a.data(), sizeof(ARGS) * n, hipMemcpyHostToDevice) != hipSuccess ||           \
+        hipMemcpy(g.off_d, offs.data(), sizeof(long) * (n + 1), hipMemcpyHostToDevice) != hipSuccess)     \
+      return fail(B->c, RIF_EHIP, "batch: upload failed");                                                 \
+    return RIF_OK;                                                                                         \
+  }                                                                                                        \
+  template <int P>                                                                                         \
+  static rif_status launch_##NAME(BatchImpl* B, int) {                                                     \
+    GroupStep& g = B->NAME;                                                                                \
+    if (g.total[0] == 0) return RIF_OK;                                                                    \
+    hipLaunchKernelGGL((k_##NAME##_g<P, Cfg256>), dim3(g.grid[0]), dim3(256), 0, B->c->stream,             \
+                       (const ARGS*)g.args_d, g.off_d, B->n, g.total[0]);                                  \
+    return check_launch(B->c, LABEL);                                                                      \
+  }
+RIF_GROUP_FIXED_P(jkp, JkArgs, "g_jk_mo_partial")
+RIF_GROUP_FIXED_P(jkr, JkArgs, "g_jk_mo_reduce")
+RIF_GROUP_FIXED(hc, gemm, GemmArgs, "g_hc_gemm", kF64, CfgSmall)
+RIF_GROUP_FIXED(lam, gemm, GemmArgs, "g_lambda_gemm", kF64, CfgSmall)
+RIF_GROUP_FIXED(coef, coef, CoefArgs, "g_coef", kF64, Cfg256)
+RIF_GROUP_FIXED(energy, energy, EnergyArgs, "g_energy", kF64, Cfg256)
+RIF_GROUP_FIXED(fred, fred, FockRedArgs, "g_fock_reduce", kF64, Cfg256)
+RIF_GROUP_FIXED(grad, grad, GradArgs, "g_grad", kF64, Cfg256)
+
+template <int P>
+static rif_status batch_setup(BatchImpl* B, const std::vector<BuildArgs>& A) {
+  std::vector<HalfArgs> half; std::vector<MoArgs> mo; std::vector<JkArgs> jk; std::vector<JaoArgs> jao;
+  std::vector<KaoArgs> kao; std::vector<GemmArgs> hc, lam; std::vector<CoefArgs> coef;
+  std::vector<EnergyArgs> en; std::vector<FockArgs> fock; std::vector<FockRedArgs> fred; std::vector<GradArgs> grad;
+  for (auto& x : A) {
+    half.push_back(x.half); mo.push_back(x.mo); jk.push_back(x.jk); jao.push_back(x.jao); kao.push_back(x.kao);
+    hc.push_back(x.hc); lam.push_back(x.lam); coef.push_back(x.coef); en.push_back(x.energy);
+    fock.push_back(x.fock); fred.push_back(x.fred); grad.push_back(x.grad);
+  }
+  rif_status st;
+  if ((st = setup_half<P>(B, half)) || (st = setup_mo<P>(B, mo)) || (st = setup_jkp<P>(B, jk)) ||
+      (st = setup_jkr<P>(B, jk)) || (st = setup_jao<P>(B, jao)) || (st = setup_kao<P>(B, kao)) ||
+      (st = setup_hc(B, hc)) || (st = setup_coef(B, coef)) || (st = setup_energy(B, en)) ||
+      (st = setup_fock<P>(B, fock)) || (st = setup_fred(B, fred)) || (st = setup_lam(B, lam)) ||
+      (st = setup_grad(B, grad)))
+    return st;
+  // tile variants for the grouped GEMM steps: measured if autotuning, else the
+  // variant with the fewest tile-area rounds
+  auto choose = [&](GroupStep& g, const std::function<rif_status(int)>& run) {
+    long key = 0;
+    for (long t : g.total) key = key * 1000003 + t;
+    int hv = 0;
+    double best = 1e300;
+    for (int v = 0; v < g.nvar; ++v) {
+      const double e = (double)dispatch<P>(v, [&](auto cfg) {
+        using Cfg = decltype(cfg);
+        const long slots = (long)g.grid[v];
+        return (double)((g.total[v] + slots - 1) / std::max(1L, slots)) * Cfg::BM * Cfg::BN * wg_per_cu<P, Cfg>();
+      });
+      if (e < best) { best = e; hv = v; }
+    }
+    g.variant = pick_variant(B->c, g.name.c_str(), {P, B->n, key}, g.nvar, hv, run);
+    return g.variant < 0 ? RIF_EHIP : RIF_OK;
+  };
+  if ((st = choose(B->half, [&](int v) { return launch_half<P>(B, v); }))) return st;
+  if ((st = choose(B->mo, [&](int v) { return launch_mo<P>(B, v); }))) return st;
+  if ((st = choose(B->jao, [&](int v) { return launch_jao<P>(B, v); }))) return st;
+  if ((st = choose(B->kao, [&](int v) { return launch_kao<P>(B, v); }))) return st;
+  if ((st = choose(B->fock, [&](int v) { return launch_fock<P>(B, v); }))) return st;
+  return RIF_OK;
+}
+
+template <int P>
+static rif_status batch_enqueue(BatchImpl* B) {
+  rif_ctx* c = B->c;
+  rif_status st;
+#define RIF_G(STEP, ...)                                         \
+  {                                                              \
+    ProfScope ps(c, B->STEP.name.c_str());                       \
+    if ((st = launch_##STEP __VA_ARGS__(B, B->STEP.variant))) return st; \
+  }
+  RIF_G(half, <P>)
+  RIF_G(mo, <P>)
+  RIF_G(jkp, <P>)
+  RIF_G(jkr, <P>)
+  RIF_G(jao, <P>)
+  RIF_G(kao, <P>)
+  RIF_G(hc)
+  RIF_G(coef)
+  RIF_G(energy)
+  RIF_G(fock, <P>)
+  RIF_G(fred)
+  RIF_G(lam)
+  RIF_G(grad)
+#undef RIF_G
+  return RIF_OK;
+}
+
+rif_status op_batch_create(rif_ctx* c, int prec, int functional, int n, const rif_instance* inst, void** out) {
+  if (!prec_ok(prec)) return fail(c, RIF_ENOTSUP, "precision mode not available");
+  BatchImpl* B = new BatchImpl();
+  B->c = c;
+  B->prec = prec;
+  B->n = n;
+  // largest molecules first
+  B->order.resize(n);
+  for (int i = 0; i < n; ++i) B->order[i] = i;
+  auto cost = [&](int i) { return (double)inst[i].n_aux * inst[i].n_bf * inst[i].n_bf * inst[i].n_pairs * (1 + inst[i].n_cwo); };
+  std::stable_sort(B->order.begin(), B->order.end(), [&](int x, int y) { return cost(x) > cost(y); });
+  std::vector<Plan> plans;
+  std::vector<size_t> base;
+  size_t total = 0;
+  for (int k = 0; k < n; ++k) {
+    const rif_instance& in = inst[B->order[k]];
+    plans.emplace_back(in.n_bf, in.n_aux, in.n_pairs, in.n_cwo, in.n_mo);
+    base.push_back(total);
+    total += (plans.back().bytes + 255) & ~size_t(255);
+  }
+  if (hipMalloc(&B->ws, std::max(total, (size_t)256)) != hipSuccess) {
+    (void)hipGetLastError();
+    delete B;
+    return fail(c, RIF_ENOMEM, "batch: workspace allocation failed");
+  }
+  std::vector<BuildArgs> A;
+  for (int k = 0; k < n; ++k)
+    A.push_back(make_build_args(plans[k], inst[B->order[k]], functional, (char*)B->ws + base[k], c->dflag));
+  rif_status st;
+  auto setup = [&]() -> rif_status { RIF_PREC_SWITCH(prec, batch_setup<P>(B, A)) };
+  if ((st = setup())) {
+    op_batch_destroy(B);
+    return st;
+  }
+  *out = B;
+  return RIF_OK;
+}
+
+rif_status op_batch_run(void* handle, int use_graph) {
+  BatchImpl* B = (BatchImpl*)handle;
+  rif_ctx* c = B->c;
+  auto enqueue = [&]() -> rif_status { RIF_PREC_SWITCH(B->prec, batch_enqueue<P>(B)) };
+  if (!use_graph) return enqueue();
+  if (!B->exec) {
+    const bool prof = c->prof;
+    c->prof = false;  // no event pairs inside the captured sequence
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      c->prof = prof;
+      return fail(c, RIF_EHIP, "hipStreamBeginCapture failed");
+    }
+    rif_status st = enqueue();
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->stream, &g);
+    c->prof = prof;
+    if (st) { if (g) (void)hipGraphDestroy(g); return st; }
+    if (e != hipSuccess || !g) return fail(c, RIF_EHIP, "hipStreamEndCapture failed");
+    B->graph = g;
+    if (hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      B->exec = nullptr;
+      return fail(c, RIF_EHIP, "hipGraphInstantiate failed");
+    }
+  }
+  ProfScope ps(c, "batch_graph");
+  if (hipGraphLaunch(B->exec, c->stream) != hipSuccess) return fail(c, RIF_EHIP, "hipGraphLaunch failed");
+  return RIF_OK;
+}
+
+void op_batch_destroy(void* handle) {
+  BatchImpl* B = (BatchImpl*)handle;
+  if (!B) return;
+  (void)hipStreamSynchronize(B->c->stream);
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  for (void* p : B->dev) (void)hipFree(p);
+  if (B->ws) (void)hipFree(B->ws);
+  delete B;
 }
 
 }  // namespace rif

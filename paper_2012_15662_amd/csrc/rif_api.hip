@@ -88,7 +88,7 @@ ProfScope::ProfScope(rif_ctx* c_, const char* name) : c(c_) {
     }
     return e;
   };
-  rif_ctx::Ev ev{name, get(), get()};
+  rif_ctx::Ev ev{std::string(name), get(), get()};
   if (!ev.a || !ev.b) return;
   hipEventRecord(ev.a, c->stream);
   c->evs.push_back(ev);
@@ -229,6 +229,68 @@ rif_status pnof_energy_grad(rif_ctx* c, rif_functional fn, int nb, int nmo, int 
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
   return op_energy_grad(c, (int)prec, (int)fn, nb, nmo, npairs, ncwo, pair_of, H, C, occ, J, K, Jn, Kn, energy,
                         lambda, grad);
+}
+
+static rif_status check_instance(rif_ctx* c, const rif_instance* in, const char* who) {
+  if (!in) return fail(c, RIF_EINVAL, std::string(who) + ": NULL instance");
+  const long nw = (long)in->n_pairs * (1 + in->n_cwo);
+  if (!dims_ok(in->n_bf) || !dims_ok(in->n_aux) || !dims_ok(in->n_mo) || !dims_ok(in->n_pairs) || in->n_cwo < 1 ||
+      nw > in->n_mo || in->n_mo > in->n_bf)
+    return fail(c, RIF_EINVAL, std::string(who) + ": need n_pairs (1 + n_cwo) <= n_mo <= n_bf, n_aux > 0");
+  if (!in->b || !in->C || !in->H || !in->occ || !in->b_half || !in->b_mo || !in->d || !in->J || !in->K ||
+      !in->Jn || !in->Kn || !in->energy || !in->lambda || !in->grad)
+    return fail(c, RIF_EINVAL, std::string(who) + ": NULL pointer");
+  return RIF_OK;
+}
+
+rif_status rif_build(rif_ctx* c, const rif_instance* in, rif_prec prec, rif_functional fn) {
+  if (!c) return RIF_EINVAL;
+  rif_status st = check_instance(c, in, "rif_build");
+  if (st) return st;
+  const int nw = in->n_pairs * (1 + in->n_cwo);
+  if ((st = rif_transform(c, in->n_bf, in->n_aux, nw, in->n_mo, in->b, in->C, prec, in->b_half, in->b_mo, in->d)))
+    return st;
+  if ((st = rif_jk_mo(c, in->n_aux, nw, in->b_mo, in->d, prec, in->J, in->K))) return st;
+  if ((st = rif_jk_ao_per_mo(c, in->n_bf, in->n_aux, nw, in->b, in->b_half, in->d, prec, in->Jn, in->Kn)))
+    return st;
+  return pnof_energy_grad(c, fn, in->n_bf, in->n_mo, in->n_pairs, in->n_cwo, in->pair_of, in->H, in->C, in->occ,
+                          in->J, in->K, in->Jn, in->Kn, prec, in->energy, in->lambda, in->grad);
+}
+
+struct rif_batch {
+  rif_ctx* c;
+  void* impl;
+};
+
+rif_status rif_batch_create(rif_ctx* c, int n, const rif_instance* inst, rif_prec prec, rif_functional fn,
+                            rif_batch** out) {
+  if (!c) return RIF_EINVAL;
+  if (!out || n <= 0 || !inst) return fail(c, RIF_EINVAL, "rif_batch_create: need n_inst > 0, inst and out");
+  *out = nullptr;
+  if (fn != RIF_PNOF7 && fn != RIF_PNOF5) return fail(c, RIF_EINVAL, "rif_batch_create: unknown functional");
+  for (int i = 0; i < n; ++i) {
+    rif_status st = check_instance(c, &inst[i], "rif_batch_create");
+    if (st) return st;
+  }
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  void* impl = nullptr;
+  rif_status st = op_batch_create(c, (int)prec, (int)fn, n, inst, &impl);
+  if (st) return st;
+  *out = new rif_batch{c, impl};
+  return RIF_OK;
+}
+
+rif_status rif_batch_run(rif_batch* b, int use_graph) {
+  if (!b) return RIF_EINVAL;
+  if (hipSetDevice(b->c->device) != hipSuccess) return fail(b->c, RIF_EHIP, "hipSetDevice failed");
+  return op_batch_run(b->impl, use_graph);
+}
+
+void rif_batch_destroy(rif_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->c->device);
+  op_batch_destroy(b->impl);
+  delete b;
 }
 
 rif_status pnof7_energy_grad(rif_ctx* c, int nb, int nmo, int npairs, int ncwo, const int* pair_of,

@@ -21,7 +21,7 @@ struct rif_ctx {
   int* dflag = nullptr;       // device status word for device-side validation
   // profiling
   bool prof = false;
-  struct Ev { const char* name; hipEvent_t a, b; };
+  struct Ev { std::string name; hipEvent_t a, b; };
   std::vector<Ev> evs;        // recorded pairs, not yet folded
   std::vector<hipEvent_t> pool;
   struct Tot { std::string name; long launches; double ms; };
@@ -84,5 +84,9 @@ rif_status op_energy_grad(rif_ctx* c, int prec, int functional, int nb, int nmo,
                           const int* pair_of, const double* H, const double* C, const double* occ,
                           const double* J, const double* K, const void* Jn, const void* Kn, double* energy,
                           double* lambda, double* grad);
+// Batched builds (inst already validated); the handle is opaque to the ABI layer.
+rif_status op_batch_create(rif_ctx* c, int prec, int functional, int n, const rif_instance* inst, void** out);
+rif_status op_batch_run(void* handle, int use_graph);
+void op_batch_destroy(void* handle);
 
 }  // namespace rif
