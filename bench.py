@@ -158,12 +158,108 @@ def bench_batch(args):
     print(json.dumps(line))
 
 
+def bench_onwarm(args):
+    """Learned ON warm start at scale: 2000 training molecules (n_bf ~ U{48..200},
+    n_aux = 3 n_bf, pairs = n_bf//12, Ncwo ~ U{1..6}) solved by the plain ON
+    optimiser from the cold start; the MLP trains on their converged ONs on the
+    GPU; 200 held-out molecules and one n_bf=1000 / n_aux=3000 / 60-pair /
+    Ncwo=6 molecule are then solved cold and warm."""
+    import numpy as np
+    import torch
+
+    import paper_2012_15662_amd as rif
+    import synth
+    from paper_2012_15662_amd import warmstart as ws
+
+    ctx = rif.Context(0)
+    rng = np.random.default_rng(10)
+
+    def make(n, seed0):
+        out = []
+        for i in range(n):
+            nb = int(rng.integers(48, 201))
+            inp, npair, ncwo = synth.make_instance_device(nb, 3 * nb, nb // 12, int(rng.integers(1, 7)), seed0 + i)
+            out.append(ws.jk_problem(ctx, inp, npair, ncwo))
+            del inp
+        torch.cuda.synchronize()
+        return out
+
+    t0 = time.perf_counter()
+    train = make(args.n_train, 10000)
+    test = make(args.n_test, 20000)
+    t_data = time.perf_counter() - t0
+    print(f"data: {len(train)} train / {len(test)} test molecules, {t_data:.1f} s", file=sys.stderr, flush=True)
+    tr = rif.OnSet(ctx, train)
+    it_tr, st_tr, t_tr = ws.solve(ctx, tr, ws.prior_rows(tr))
+    X, T, M = ws.features(ctx, tr, with_targets=True)
+    mu, sd = ws.standardisation(X)
+    X, T, M = ws.features(ctx, tr, with_targets=True, mu=mu, sigma=sd)
+    net = ws.WarmStartMLP(ctx, seed=0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    losses = net.fit(X, T, M, epochs=args.epochs, lr=3e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    print(f"trained {args.epochs} epochs on {X.shape[0]} pairs in {t_train:.1f} s, loss "
+          f"{losses[0]:.3e} -> {losses[-1]:.3e}", file=sys.stderr, flush=True)
+
+    def cold_warm(probs):
+        c = rif.OnSet(ctx, probs)
+        ic, sc, tc = ws.solve(ctx, c, ws.prior_rows(c))
+        w = rif.OnSet(ctx, probs)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        Xt, _, Mt = ws.features(ctx, w, mu=mu, sigma=sd)
+        P = net.predict(Xt, Mt)
+        torch.cuda.synchronize()
+        t_inf = time.perf_counter() - ta
+        iw, sw, tw = ws.solve(ctx, w, P)
+        Ec, Ew = c.energy.cpu().numpy(), w.energy.cpu().numpy()
+        return {"iters_cold_mean": float(ic.mean()), "iters_warm_mean": float(iw.mean()),
+                "iters_cold_median": float(np.median(ic)), "iters_warm_median": float(np.median(iw)),
+                "iter_reduction": round(1.0 - float(iw.mean()) / float(ic.mean()), 4),
+                "converged_cold": int((sc == 0).sum()), "converged_warm": int((sw == 0).sum()),
+                "n": len(probs), "same_minimum": int((np.abs(Ec - Ew) <= 1e-9 * np.abs(Ec)).sum()),
+                "warm_lower_energy": int((Ew < Ec - 1e-9 * np.abs(Ec)).sum()),
+                "time_cold_s": round(tc, 5), "time_warm_s": round(tw + t_inf, 5), "time_inference_s": round(t_inf, 5)}
+
+    held = cold_warm(test)
+    print("held-out:", held, file=sys.stderr, flush=True)
+    inp, npair, ncwo = synth.make_instance_device(1000, 3000, 60, 6, 4)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    big_prob = ws.jk_problem(ctx, inp, npair, ncwo)
+    torch.cuda.synchronize()
+    t_big_jk = time.perf_counter() - tb
+    del inp
+    torch.cuda.empty_cache()
+    big = cold_warm([big_prob])
+    big["jk_build_s"] = round(t_big_jk, 4)
+    line = {
+        "metric": "ON iterations to max|dE/dgamma| <= 1e-8, learned warm start vs cold start",
+        "value": held["iter_reduction"], "unit": "fractional reduction in mean ON iterations (held-out)",
+        "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+        "config": {"workload": f"onwarm: {args.n_train} train / {args.n_test} held-out molecules "
+                               "n_bf ~ U{48..200}, n_aux = 3 n_bf, pairs = n_bf//12, Ncwo ~ U{1..6}; "
+                               "large: n_bf 1000, n_aux 3000, 60 pairs, Ncwo 6"},
+        "train": {"iters_mean": float(it_tr.mean()), "converged": int((st_tr == 0).sum()),
+                  "pairs": int(X.shape[0]), "epochs": args.epochs, "loss_first": losses[0],
+                  "loss_last": losses[-1], "train_s": round(t_train, 2), "data_s": round(t_data, 1)},
+        "held_out": held, "large": big,
+    }
+    ctx.close()
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c6h12", choices=["tiny", "c6h12", "c10h20", "batch64"])
+    ap.add_argument("--workload", default="c6h12", choices=["tiny", "c6h12", "c10h20", "batch64", "onwarm"])
+    ap.add_argument("--n-train", type=int, default=2000)
+    ap.add_argument("--n-test", type=int, default=200)
+    ap.add_argument("--epochs", type=int, default=800)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-tune", action="store_true", help="heuristic tile shapes instead of autotuning")
@@ -177,6 +273,8 @@ def main():
 
     if args.workload == "batch64":
         return bench_batch(args)
+    if args.workload == "onwarm":
+        return bench_onwarm(args)
 
     import numpy as np
     import torch

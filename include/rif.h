@@ -175,6 +175,65 @@ rif_status rif_batch_create(rif_ctx *ctx, int n_inst, const rif_instance *inst, 
 rif_status rif_batch_run(rif_batch *batch, int use_graph);
 void rif_batch_destroy(rif_batch *batch);
 
+/* ---- Occupation-number (ON) optimisation and its learned warm start ----
+ * The occupancy optimisation of Sec. II: minimise Eq. (2) over the ONs at
+ * fixed H_pp, J, K through auxiliary variables gamma (unconstrained):
+ *   n_g = (1 + cos^2 gamma_g)/2 for the strong orbital of pair g; the weak
+ *   orbitals of g (ascending index) get (1 - n_g) w_k with hyperspherical
+ *   weights w_1 = cos^2 b_1, w_k = prod_{j<k} sin^2 b_j cos^2 b_k,
+ *   w_last = prod sin^2 b_j; variables [gamma_g, b_1..b_{ncwo-1}] at g*ncwo+j.
+ * One problem per molecule; all pointers are device pointers.
+ *   Hpp [n_omega], J, K [n_omega][n_omega] FP64 (from rif_hpp / rif_jk_mo)
+ *   gamma [n_pairs*n_cwo] in: start, out: optimum; occ [n_omega] out
+ *   energy, iters, status: out (status 0 converged to max|dE/dgamma| <= tol,
+ *   1 max_it reached, 2 line search failed, 3 bad pair map)
+ *   work: rif_on_work_size(...) doubles of scratch owned by the caller
+ *   row0: first row of this problem in the per-pair feature/prediction arrays */
+typedef struct rif_on_problem {
+  int n_pairs, n_cwo, n_omega, functional, max_it, row0;
+  double tol;
+  const double *Hpp, *J, *K;
+  const int *pair_of;
+  double *gamma, *occ, *energy;
+  int *iters, *status;
+  double *work;
+} rif_on_problem;
+
+/* Scratch doubles one problem needs (host function, no GPU call). */
+long rif_on_work_size(int n_omega, int n_pairs, int n_cwo);
+/* H_pp = c_p^T H c_p for the n_omega orbitals of Omega (Eq. (1)). */
+rif_status rif_hpp(rif_ctx *ctx, int n_bf, int n_mo, int n_omega, const double *H, const double *C,
+                   double *Hpp);
+/* L-BFGS (history 8, Armijo backtracking) in FP64, one workgroup per problem,
+ * all problems in one launch.  probs is a HOST array (copied). */
+rif_status rif_on_optimize(rif_ctx *ctx, int n_prob, const rif_on_problem *probs);
+/* Per-pair MLP features X [rows][39] (optionally standardised: (x - mu)/sigma
+ * where sigma > 0), and, if T/M are non-NULL, targets T [rows][7] = the
+ * pair's ONs from occ (strong, then weak slots) and masks M [rows][7].
+ * Rows: problem i owns rows row0 .. row0 + n_pairs - 1. */
+rif_status rif_on_features(rif_ctx *ctx, int n_prob, const rif_on_problem *probs, float *X, float *T,
+                           float *M, const float *mu, const float *sigma);
+/* Predicted pair ONs P [rows][7] -> starting gamma of every problem. */
+rif_status rif_on_warmstart(rif_ctx *ctx, int n_prob, const rif_on_problem *probs, const float *P);
+
+/* Warm-start MLP: 39 -> 128 -> 128 -> 128 -> 7, tanh hidden layers, masked
+ * softmax output (FP32).  Parameters: one flat FP32 vector of
+ * rif_mlp_n_params() values, layer l stored as W_aug = [W (in x out); b (out)]
+ * row-major.  Buffers owned by the caller:
+ *   X [rows][39], M [rows][7] masks, T [rows][7] targets,
+ *   H [3][rows][128] hidden activations, Z [rows][7] logits, P [rows][7] ONs,
+ *   dA [2][rows][128] scratch, grad [n_params], loss: device double (mean
+ *   over rows of sum_k M (P - T)^2). */
+long rif_mlp_n_params(void);
+rif_status rif_mlp_forward(rif_ctx *ctx, int rows, const float *X, const float *M, const float *theta,
+                           float *H, float *Z, float *P);
+rif_status rif_mlp_backward(rif_ctx *ctx, int rows, const float *X, const float *M, const float *T,
+                            const float *theta, const float *H, const float *Z, float *dA, float *grad,
+                            double *loss);
+/* Adam with bias correction; step counts from 1. */
+rif_status rif_adam(rif_ctx *ctx, int n, float *theta, const float *grad, float *m, float *v, int step,
+                    float lr, float beta1, float beta2, float eps);
+
 /* Tile-shape selection for the MFMA kernels.  Each GEMM-shaped kernel has up
  * to four tile variants (0: 128x128, 1: 64x64, 2: 128x64, 3: 64x128 outputs
  * per workgroup).  mode 0 picks one per shape with a wave-quantisation

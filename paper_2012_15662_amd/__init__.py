@@ -15,7 +15,7 @@ import ctypes
 import os
 
 __all__ = [
-    "Context", "Batch", "Instance", "RifError", "load_library", "LIB_PATH", "FP64", "FP32", "BF16X3", "BF16X6",
+    "Context", "Batch", "Instance", "OnProblem", "OnSet", "RifError", "load_library", "LIB_PATH", "FP64", "FP32", "BF16X3", "BF16X6",
     "FP16X3", "PNOF7", "PNOF5", "EXPORTS",
 ]
 
@@ -32,6 +32,14 @@ class Instance(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int) for n in ("n_bf", "n_aux", "n_pairs", "n_cwo", "n_mo")] + \
                [(n, ctypes.c_void_p) for n in ("b", "C", "H", "occ", "pair_of", "b_half", "b_mo", "d", "J",
                                                "K", "Jn", "Kn", "energy", "lambda_", "grad")]
+
+
+class OnProblem(ctypes.Structure):
+    """struct rif_on_problem (include/rif.h)."""
+    _fields_ = [(n, ctypes.c_int) for n in ("n_pairs", "n_cwo", "n_omega", "functional", "max_it", "row0")] + \
+               [("tol", ctypes.c_double)] + \
+               [(n, ctypes.c_void_p) for n in ("Hpp", "J", "K", "pair_of", "gamma", "occ", "energy", "iters",
+                                               "status", "work")]
 
 
 # name -> (restype, argtypes); mirrors include/rif.h
@@ -53,6 +61,16 @@ EXPORTS = {
     "rif_batch_create": (_i, [_vp, _i, ctypes.POINTER(Instance), _i, _i, ctypes.POINTER(_vp)]),
     "rif_batch_run": (_i, [_vp, _i]),
     "rif_batch_destroy": (None, [_vp]),
+    "rif_on_work_size": (ctypes.c_long, [_i, _i, _i]),
+    "rif_hpp": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
+    "rif_on_optimize": (_i, [_vp, _i, ctypes.POINTER(OnProblem)]),
+    "rif_on_features": (_i, [_vp, _i, ctypes.POINTER(OnProblem), _vp, _vp, _vp, _vp, _vp]),
+    "rif_on_warmstart": (_i, [_vp, _i, ctypes.POINTER(OnProblem), _vp]),
+    "rif_mlp_n_params": (ctypes.c_long, []),
+    "rif_mlp_forward": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "rif_mlp_backward": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "rif_adam": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _i, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                      ctypes.c_float]),
     "rif_autotune": (_i, [_vp, _i]),
     "rif_set_tile_variant": (_i, [_vp, _i]),
     "rif_tune_report": (_i, [_vp, ctypes.c_char_p, _i]),
@@ -286,6 +304,58 @@ class Context:
         """items: list of (inputs dict, n_pairs, n_cwo, outputs dict or None)."""
         return Batch(self, items, prec, functional)
 
+    # ---- ON optimisation and the warm-start MLP ----------------------------
+    def hpp(self, H, C, n_omega, out=None):
+        import torch
+        n_bf, n_mo = C.shape
+        out = torch.empty(n_omega, dtype=torch.float64, device=C.device) if out is None else out
+        self._chk(self.lib.rif_hpp(self.h, n_bf, n_mo, n_omega, _ptr(H, "H", torch.float64, n_bf * n_bf),
+                                   _ptr(C, "C", torch.float64, n_bf * n_mo), _ptr(out, "Hpp", torch.float64, n_omega)))
+        return out
+
+    def on_optimize(self, onset):
+        self._chk(self.lib.rif_on_optimize(self.h, len(onset.arr), onset.arr))
+
+    def on_features(self, onset, X, T=None, M=None, mu=None, sigma=None):
+        import torch
+        f32 = torch.float32
+        self._chk(self.lib.rif_on_features(
+            self.h, len(onset.arr), onset.arr, _ptr(X, "X", f32, onset.rows * 39),
+            _ptr(T, "T", f32, onset.rows * 7), _ptr(M, "M", f32, onset.rows * 7),
+            _ptr(mu, "mu", f32, 39), _ptr(sigma, "sigma", f32, 39)))
+
+    def on_warmstart(self, onset, P):
+        import torch
+        self._chk(self.lib.rif_on_warmstart(self.h, len(onset.arr), onset.arr,
+                                            _ptr(P, "P", torch.float32, onset.rows * 7)))
+
+    def mlp_n_params(self) -> int:
+        return int(self.lib.rif_mlp_n_params())
+
+    def mlp_forward(self, X, M, theta, H, Z, P):
+        import torch
+        f = torch.float32
+        n = X.shape[0]
+        self._chk(self.lib.rif_mlp_forward(self.h, n, _ptr(X, "X", f, n * 39), _ptr(M, "M", f, n * 7),
+                                           _ptr(theta, "theta", f), _ptr(H, "H", f, 3 * n * 128),
+                                           _ptr(Z, "Z", f, n * 7), _ptr(P, "P", f, n * 7)))
+
+    def mlp_backward(self, X, M, T, theta, H, Z, dA, grad, loss):
+        import torch
+        f = torch.float32
+        n = X.shape[0]
+        self._chk(self.lib.rif_mlp_backward(
+            self.h, n, _ptr(X, "X", f, n * 39), _ptr(M, "M", f, n * 7), _ptr(T, "T", f, n * 7),
+            _ptr(theta, "theta", f), _ptr(H, "H", f, 3 * n * 128), _ptr(Z, "Z", f, n * 7),
+            _ptr(dA, "dA", f, 2 * n * 128), _ptr(grad, "grad", f), _ptr(loss, "loss", torch.float64, 1)))
+
+    def adam(self, theta, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        import torch
+        f = torch.float32
+        n = theta.numel()
+        self._chk(self.lib.rif_adam(self.h, n, _ptr(theta, "theta", f, n), _ptr(grad, "grad", f, n),
+                                    _ptr(m, "m", f, n), _ptr(v, "v", f, n), step, lr, beta1, beta2, eps))
+
     # ---- tile selection ---------------------------------------------------
     def autotune(self, on: bool = True):
         self._chk(self.lib.rif_autotune(self.h, 1 if on else 0))
@@ -343,3 +413,51 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class OnSet:
+    """A set of ON-optimisation problems (one per molecule) with their device
+    buffers: gamma, occ, energy, iters, status and work.  `problems` is a list
+    of (Hpp, J, K, pair_of or None, n_pairs, n_cwo) device tensors/ints."""
+
+    def __init__(self, lib_ctx: Context, problems, tol=1e-8, max_it=2000, functional=PNOF7, device="cuda"):
+        import torch
+        self.ctx = lib_ctx
+        n = len(problems)
+        self.keep = []
+        self.arr = (OnProblem * n)()
+        self.rows = 0
+        sizes = [(p[4], p[5]) for p in problems]
+        nv = [a * b for a, b in sizes]
+        self.gamma = torch.zeros(sum(nv), dtype=torch.float64, device=device)
+        self.occ = torch.zeros(sum(a * (1 + b) for a, b in sizes), dtype=torch.float64, device=device)
+        self.energy = torch.zeros(n, dtype=torch.float64, device=device)
+        self.iters = torch.zeros(n, dtype=torch.int32, device=device)
+        self.status = torch.zeros(n, dtype=torch.int32, device=device)
+        ws = [int(lib_ctx.lib.rif_on_work_size(a * (1 + b), a, b)) for a, b in sizes]
+        self.work = torch.zeros(sum(ws), dtype=torch.float64, device=device)
+        self.gslices, self.oslices = [], []
+        go = oo = wo = 0
+        for i, (Hpp, J, K, pm, npair, ncwo) in enumerate(problems):
+            w = npair * (1 + ncwo)
+            q = self.arr[i]
+            q.n_pairs, q.n_cwo, q.n_omega, q.functional, q.max_it, q.row0 = npair, ncwo, w, functional, max_it, self.rows
+            q.tol = tol
+            q.Hpp = _ptr(Hpp, "Hpp", torch.float64, w)
+            q.J = _ptr(J, "J", torch.float64, w * w)
+            q.K = _ptr(K, "K", torch.float64, w * w)
+            q.pair_of = _ptr(pm, "pair_of", torch.int32, w) if pm is not None else None
+            q.gamma = self.gamma.data_ptr() + 8 * go
+            q.occ = self.occ.data_ptr() + 8 * oo
+            q.energy = self.energy.data_ptr() + 8 * i
+            q.iters = self.iters.data_ptr() + 4 * i
+            q.status = self.status.data_ptr() + 4 * i
+            q.work = self.work.data_ptr() + 8 * wo
+            self.keep.append((Hpp, J, K, pm))
+            self.gslices.append(slice(go, go + npair * ncwo))
+            self.oslices.append(slice(oo, oo + w))
+            go += npair * ncwo
+            oo += w
+            wo += ws[i]
+            self.rows += npair
+        self.sizes = sizes

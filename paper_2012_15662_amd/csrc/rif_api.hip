@@ -301,6 +301,94 @@ rif_status pnof7_energy_grad(rif_ctx* c, int nb, int nmo, int npairs, int ncwo, 
                           lambda, grad);
 }
 
+long rif_on_work_size(int nw, int npairs, int ncwo) {
+  if (nw <= 0 || npairs <= 0 || ncwo <= 0) return 0;
+  return on_work_doubles(nw, npairs, ncwo);
+}
+
+rif_status rif_hpp(rif_ctx* c, int nb, int nmo, int nw, const double* H, const double* C, double* Hpp) {
+  if (!c) return RIF_EINVAL;
+  if (!dims_ok(nb) || !dims_ok(nmo) || !dims_ok(nw) || nw > nmo || nmo > nb)
+    return fail(c, RIF_EINVAL, "rif_hpp: need 0 < n_omega <= n_mo <= n_bf");
+  if (!H || !C || !Hpp) return fail(c, RIF_EINVAL, "rif_hpp: NULL pointer");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  return op_hpp(c, nb, nmo, nw, H, C, Hpp);
+}
+
+static rif_status check_on(rif_ctx* c, int n, const rif_on_problem* p, bool need_opt, const char* who) {
+  if (n <= 0 || !p) return fail(c, RIF_EINVAL, std::string(who) + ": need n_prob > 0 and a problem array");
+  for (int i = 0; i < n; ++i) {
+    const rif_on_problem& q = p[i];
+    if (q.n_pairs <= 0 || q.n_cwo < 1 || q.n_cwo > 14 || q.n_omega != q.n_pairs * (1 + q.n_cwo) || q.row0 < 0)
+      return fail(c, RIF_EINVAL, std::string(who) + ": need n_omega = n_pairs (1 + n_cwo), 1 <= n_cwo <= 14");
+    if (q.functional != RIF_PNOF7 && q.functional != RIF_PNOF5)
+      return fail(c, RIF_EINVAL, std::string(who) + ": unknown functional");
+    if (!q.Hpp || !q.J || !q.K) return fail(c, RIF_EINVAL, std::string(who) + ": NULL Hpp/J/K");
+    if (need_opt && (!q.gamma || !q.occ || !q.energy || !q.iters || !q.status || !q.work || q.max_it < 0 ||
+                     !(q.tol > 0.0)))
+      return fail(c, RIF_EINVAL, std::string(who) + ": NULL output/work pointer, max_it < 0 or tol <= 0");
+  }
+  return RIF_OK;
+}
+
+rif_status rif_on_optimize(rif_ctx* c, int n, const rif_on_problem* p) {
+  if (!c) return RIF_EINVAL;
+  rif_status st = check_on(c, n, p, true, "rif_on_optimize");
+  if (st) return st;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  return op_on_optimize(c, n, p);
+}
+
+rif_status rif_on_features(rif_ctx* c, int n, const rif_on_problem* p, float* X, float* T, float* M,
+                           const float* mu, const float* sigma) {
+  if (!c) return RIF_EINVAL;
+  rif_status st = check_on(c, n, p, false, "rif_on_features");
+  if (st) return st;
+  if (!X) return fail(c, RIF_EINVAL, "rif_on_features: NULL X");
+  for (int i = 0; i < n; ++i)
+    if (T && !p[i].occ) return fail(c, RIF_EINVAL, "rif_on_features: targets need occ");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  return op_on_features(c, n, p, X, T, M, mu, sigma);
+}
+
+rif_status rif_on_warmstart(rif_ctx* c, int n, const rif_on_problem* p, const float* P) {
+  if (!c) return RIF_EINVAL;
+  rif_status st = check_on(c, n, p, false, "rif_on_warmstart");
+  if (st) return st;
+  for (int i = 0; i < n; ++i)
+    if (!p[i].gamma) return fail(c, RIF_EINVAL, "rif_on_warmstart: NULL gamma");
+  if (!P) return fail(c, RIF_EINVAL, "rif_on_warmstart: NULL P");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  return op_on_warmstart(c, n, p, P);
+}
+
+long rif_mlp_n_params(void) { return mlp_n_params(); }
+
+rif_status rif_mlp_forward(rif_ctx* c, int rows, const float* X, const float* M, const float* theta, float* H,
+                           float* Z, float* P) {
+  if (!c) return RIF_EINVAL;
+  if (rows <= 0 || !X || !M || !theta || !H || !Z || !P) return fail(c, RIF_EINVAL, "rif_mlp_forward: bad arguments");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  return op_mlp_forward(c, rows, X, M, theta, H, Z, P);
+}
+
+rif_status rif_mlp_backward(rif_ctx* c, int rows, const float* X, const float* M, const float* T, const float* theta,
+                            const float* H, const float* Z, float* dA, float* grad, double* loss) {
+  if (!c) return RIF_EINVAL;
+  if (rows <= 0 || !X || !M || !T || !theta || !H || !Z || !dA || !grad || !loss)
+    return fail(c, RIF_EINVAL, "rif_mlp_backward: bad arguments");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  return op_mlp_backward(c, rows, X, M, T, theta, H, Z, dA, grad, loss);
+}
+
+rif_status rif_adam(rif_ctx* c, int n, float* theta, const float* grad, float* m, float* v, int step, float lr,
+                    float b1, float b2, float eps) {
+  if (!c) return RIF_EINVAL;
+  if (n <= 0 || step < 1 || !theta || !grad || !m || !v) return fail(c, RIF_EINVAL, "rif_adam: bad arguments");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  return op_adam(c, n, theta, grad, m, v, step, lr, b1, b2, eps);
+}
+
 rif_status rif_autotune(rif_ctx* c, int mode) {
   if (!c || mode < 0 || mode > 1) return RIF_EINVAL;
   c->tune_mode = mode;

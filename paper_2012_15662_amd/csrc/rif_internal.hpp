@@ -84,6 +84,23 @@ rif_status op_energy_grad(rif_ctx* c, int prec, int functional, int nb, int nmo,
                           const int* pair_of, const double* H, const double* C, const double* occ,
                           const double* J, const double* K, const void* Jn, const void* Kn, double* energy,
                           double* lambda, double* grad);
+// ON optimisation and the warm-start MLP (on_mlp.hip)
+typedef rif_on_problem OnProblem;
+long on_work_doubles(int nw, int npairs, int ncwo);
+long mlp_n_params();
+rif_status op_hpp(rif_ctx* c, int nb, int nmo, int nw, const double* H, const double* C, double* Hpp);
+rif_status op_on_optimize(rif_ctx* c, int n, const OnProblem* probs);
+rif_status op_on_features(rif_ctx* c, int n, const OnProblem* probs, float* X, float* T, float* M, const float* mu,
+                          const float* sigma);
+rif_status op_on_warmstart(rif_ctx* c, int n, const OnProblem* probs, const float* Pn);
+rif_status op_mlp_forward(rif_ctx* c, int nrows, const float* X, const float* M, const float* theta, float* H,
+                          float* Z, float* Pn);
+rif_status op_mlp_backward(rif_ctx* c, int nrows, const float* X, const float* M, const float* T,
+                           const float* theta, const float* H, const float* Z, float* dA, float* grad,
+                           double* loss);
+rif_status op_adam(rif_ctx* c, int n, float* theta, const float* grad, float* m, float* v, int step, float lr,
+                   float b1, float b2, float eps);
+
 // Batched builds (inst already validated); the handle is opaque to the ABI layer.
 rif_status op_batch_create(rif_ctx* c, int prec, int functional, int n, const rif_instance* inst, void** out);
 rif_status op_batch_run(void* handle, int use_graph);

@@ -147,3 +147,42 @@ def make_batch(n_inst: int = 64, seed: int = 3, base: int = 3000, n_cwo: int = 2
     """Uneven batch: n_aux = 3 n_bf, pairs = n_bf // 12, per-instance seed base+i."""
     return [make_instance(int(nb), 3 * int(nb), int(nb) // 12, n_cwo, base + i)
             for i, nb in enumerate(batch_sizes(n_inst, seed, lo, hi))]
+
+
+def make_instance_device(n_bf: int, n_aux: int, n_pairs: int, n_cwo: int, seed: int, device="cuda",
+                         n_mo: int | None = None):
+    """Same recipe as make_instance, with b drawn on the GPU (torch.Generator
+    seeded with `seed`) so that large or many instances are cheap to make; C, H
+    and the ONs come from numpy default_rng(seed + 2**32) in the order C -> H -> ON.
+    The streams differ from make_instance's, so the two never mix in one test.
+    Returns (dict of device tensors b, C, H, occ, pair_of; n_pairs; n_cwo)."""
+    import torch
+    n_mo = n_bf if n_mo is None else n_mo
+    W = n_pairs * (1 + n_cwo)
+    if W > n_mo or n_mo > n_bf:
+        raise ValueError("need n_omega <= n_mo <= n_bf")
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    b = torch.empty((n_aux, n_bf, n_bf), dtype=torch.float64, device=device)
+    scale = torch.exp(-3.0 * torch.arange(n_aux, dtype=torch.float64, device=device) / n_aux)
+    chunk = max(1, (1 << 27) // (n_bf * n_bf))
+    for p0 in range(0, n_aux, chunk):
+        p1 = min(n_aux, p0 + chunk)
+        G = torch.randn((p1 - p0, n_bf, n_bf), dtype=torch.float64, device=device, generator=gen)
+        G *= 1.0 / math.sqrt(n_bf)
+        b[p0:p1] = (G + G.transpose(1, 2)) * (0.5 * scale[p0:p1, None, None])
+        del G
+    rng = np.random.default_rng(seed + 2 ** 32)
+    C, _ = np.linalg.qr(rng.standard_normal((n_bf, n_mo)))
+    Hx = rng.standard_normal((n_bf, n_bf))
+    H = np.triu(Hx) + np.triu(Hx, 1).T
+    strong = rng.uniform(0.9, 0.99, size=n_pairs)
+    pair_of = default_pair_map(n_pairs, n_cwo)
+    occ = np.empty(W)
+    occ[:n_pairs] = strong
+    for i in range(n_pairs, W):
+        occ[i] = (1.0 - strong[pair_of[i]]) / n_cwo
+    t = {"b": b, "C": torch.from_numpy(np.ascontiguousarray(C)).to(device),
+         "H": torch.from_numpy(np.ascontiguousarray(H)).to(device), "occ": torch.from_numpy(occ).to(device),
+         "pair_of": torch.from_numpy(pair_of.astype(np.int32)).to(device)}
+    return t, n_pairs, n_cwo
