@@ -264,6 +264,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-tune", action="store_true", help="heuristic tile shapes instead of autotuning")
     ap.add_argument("--prec", default="fp64", choices=list(MODES))
+    ap.add_argument("--calib", action="store_true",
+                    help="run one 1 GiB device-to-device copy first (reference for HBM counters)")
     ap.add_argument("--no-modes", action="store_true", help="skip timing the other precision modes")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -291,6 +293,12 @@ def main():
     H = torch.from_numpy(inst.H).to(dev)
     occ = torch.from_numpy(inst.occ).to(dev)
     pm = torch.from_numpy(inst.pair_of.astype(np.int32)).to(dev)
+    if args.calib:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = rif.Context(0)
     ctx.autotune(not args.no_tune)
     el, out, prof = time_builds(ctx, b, Cd, H, occ, pm, inst, MODES[args.prec], args.steps, args.warmup,

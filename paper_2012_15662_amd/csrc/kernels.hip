@@ -82,10 +82,9 @@ struct EnergyArgs {
 struct FockRedArgs { int nb, nw, nsplit; const double *Yp, *occ, *HC; double* Y; };
 struct GradArgs { int nmo, nw; const double* lam; double* G; };
 
-// Half transform.  Since b[l] is symmetric, b[l][mu][nu] = b[l][nu][mu] and the
-// step is one GEMM: bh[q][r] = sum_mu C[mu][q] bflat[r][mu] with r = l*n_bf + nu.
-// M = q, N = r (stores run along r, contiguous in b_half), K = mu.  Tiles:
-// q-tile fastest.
+// Half transform, Eq. (12): bh[q][r] = sum_mu C[mu][q] b[l][mu][nu] with the
+// output column r = l*n_bf + nu flattened over (l, nu).  M = q, N = r (loads of
+// b and stores of b_half both run along nu), K = mu.  Tiles: q-tile fastest.
 template <int P, class Cfg>
 __host__ __device__ inline long half_tiles(const HalfArgs& a) {
   return (long)cdiv(a.nw, Cfg::BM) * cdiv(a.nr, Cfg::BN);
@@ -97,16 +96,17 @@ __device__ void half_tile(const HalfArgs& a, long t, char* smem) {
   const int q0 = (int)(t % nqt) * Cfg::BM;
   const long r0 = (t / nqt) * Cfg::BN;
   const int nb = a.nb, nw = a.nw;
-  const long nr = a.nr;
-  const double* b = a.b;
+  const long nr = a.nr, B2 = (long)nb * nb;
   IOT<P>* bh = (IOT<P>*)a.bh;
   XCS<P, double, Cfg::BM, Cfg::NT> la;
   la.init(a.C, a.nmo, nb, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
-  KCS<P, double, Cfg::BN, Cfg::NT> lb;
-  lb.init([&](int x) -> const double* {
-    const long r = r0 + x;
-    return r < nr ? b + r * nb : nullptr;
-  }, b, nb);
+  // column r = l*n_bf + nu of b[l][mu][nu] at k = mu: x-contiguous within a slab
+  XCS<P, double, Cfg::BN, Cfg::NT> lb;
+  lb.init(a.b, nb, nb, [&](int x, long& o) {
+    const long r = r0 + x, l = r / nb;
+    o = l * B2 + (r - l * nb);
+    return r < nr;
+  });
   typename E::template Acc<Cfg> acc;
   gemm_mainloop<E, Cfg>(la, lb, cdiv(nb, E::BK), acc, smem);
   acc.for_each([&](int m, int n, double v) {
@@ -611,11 +611,11 @@ RIF_STEP_KERNELS(grad, GradArgs, 16, 256, false)
 // model by default, or the fastest measured one when autotuning is on.
 
 template <int BK> struct Vars;
-template <> struct Vars<16> {  // FP64 / FP32 engines: 4 waves
-  using V0 = TileCfg<128, 128, 16, 64, 64>;
-  using V1 = TileCfg<64, 64, 16, 32, 32>;
-  using V2 = TileCfg<128, 64, 16, 64, 32>;
-  using V3 = TileCfg<64, 128, 16, 32, 64>;
+template <> struct Vars<16> {  // FP64 / FP32 engines: 8 waves (measured ~10% over 4 at these shapes)
+  using V0 = TileCfg<128, 128, 16, 64, 32>;
+  using V1 = TileCfg<64, 64, 16, 16, 32>;
+  using V2 = TileCfg<128, 64, 16, 32, 32>;
+  using V3 = TileCfg<64, 128, 16, 32, 32>;
 };
 template <> struct Vars<32> {  // BF16 split engines: smaller wave tiles (three accumulator sets)
   using V0 = TileCfg<128, 128, 32, 64, 32>;
@@ -710,7 +710,7 @@ RIF_GEMM_STEP(kao, KaoArgs, "kao", 2, a.nb, a.na, a.nw)
 RIF_GEMM_STEP(fock, FockArgs, "fock", 4, a.nb, a.nw, a.nmo, a.nsplit)
 
 // Fixed-shape steps (64x64 FP64 GEMM tiles, 256-thread element-wise tiles).
-using CfgSmall = Vars<16>::V1;
+using CfgSmall = TileCfg<64, 64, 16, 32, 32>;
 #define RIF_FIXED_STEP(NAME, ARGS, LABEL, PP, CFG)                                              \
   static rif_status step1_##NAME(rif_ctx* c, const ARGS& a) {                                  \
     ProfScope ps(c, LABEL);                                                                     \

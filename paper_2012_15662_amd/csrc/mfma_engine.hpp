@@ -97,11 +97,18 @@ struct XCSrc {
 };
 
 // k-contiguous operand: element (x, k) at row(x)[k].
+//   KV == 1 (k-major LDS): lanes run along x sixteen at a time, so one wave's
+//     LDS writes cover 16 consecutive x of 4 k rows (no bank conflicts) while
+//     its global loads read 4 consecutive k of 16 rows.  Thread t holds one k
+//     (kq) of NP rows x = xl0 + 16*(xh0 + p*XSTEP16).
+//   KV > 1 (x-major LDS): a thread holds KV consecutive k of NP rows.
 template <class T, int BX, int BK, int NT, int KV>
 struct KCSrc {
-  static constexpr int TPR = BK / KV;   // threads per row
-  static constexpr int RSTEP = NT / TPR;
-  static_assert(NT % TPR == 0 && BX % RSTEP == 0, "bad KC tiling");
+  static constexpr bool XFAST = (KV == 1);
+  static constexpr int TPR = BK / KV;                         // k-groups per row
+  static constexpr int RSTEP = XFAST ? 16 * (NT / (16 * BK)) : NT / TPR;   // rows per pass
+  static_assert(XFAST ? (NT % (16 * BK) == 0 && BX % 16 == 0) : (NT % TPR == 0), "bad KC tiling");
+  static_assert(BX % RSTEP == 0, "bad KC tiling");
   static constexpr int NP = BX / RSTEP;
   static constexpr int R = NP * KV, RR = R;
   using type = T;
@@ -112,8 +119,13 @@ struct KCSrc {
   // valid row, read in its place and masked.
   template <class RowPtr>
   __device__ void init(RowPtr rowptr, const T* fallback, int K) {
-    kg = threadIdx.x % TPR;
-    xr = threadIdx.x / TPR;
+    if constexpr (XFAST) {
+      kg = (threadIdx.x / 16) % BK;
+      xr = threadIdx.x % 16 + 16 * (threadIdx.x / (16 * BK));
+    } else {
+      kg = threadIdx.x % TPR;
+      xr = threadIdx.x / TPR;
+    }
     kmax = K;
     vmask = 0;
 #pragma unroll
@@ -145,9 +157,10 @@ __device__ __forceinline__ void wave_origin(int WAVES_N, int WM, int WN, int& wm
 }
 
 // ---------------------------------------------------------------------------
-// FP64 engine
-struct EngF64 {
-  static constexpr int BK = 16, KV = 1, PAD = 16, CHUNK = 1 << 30;
+// FP64 engine (BK_ = slice depth)
+template <int BK_ = 16>
+struct EngF64T {
+  static constexpr int BK = BK_, KV = 1, PAD = 16, CHUNK = 1 << 30;
   template <int BX>
   static constexpr int stage_bytes() { return BK * (BX + PAD) * 8; }
   template <class Cfg>
@@ -406,6 +419,7 @@ template <class E, class Cfg>
 constexpr int smem_bytes() { return 2 * (E::template stage_bytes<Cfg::BM>() + E::template stage_bytes<Cfg::BN>()); }
 
 template <int P> struct EngineOf;
+using EngF64 = EngF64T<16>;
 template <> struct EngineOf<kF64> { using type = EngF64; };
 template <> struct EngineOf<kF32> { using type = EngF32; };
 template <> struct EngineOf<kBF16x3> { using type = EngBF16<2>; };
