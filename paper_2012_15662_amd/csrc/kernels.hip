@@ -58,7 +58,15 @@ struct HalfArgs { int nb, nw, nmo; long nr; const double* b; const double* C; vo
 struct MoArgs { int nb, na, nw, nmo; const void* bh; const double* C; void* bmo; double* d; };
 struct JaoArgs { int nb, na, nw; const double* b; const double* d; void* Jn; };
 struct KaoArgs { int nb, na, nw; const void* bh; void* Kn; };
-struct GemmArgs { int M, N, K; const double* A; long lda; const double* B; long ldb; double* out; long ldo; };
+// Split over k: out + s*ostride receives the partial product over
+// k in [s*kc, min(K, (s+1)*kc)), s < ksplit.
+struct GemmArgs {
+  int M, N, K;
+  const double* A; long lda;
+  const double* B; long ldb;
+  double* out; long ldo;
+  int ksplit, kc; long ostride;
+};
 struct FockArgs {
   int nb, nw, nmo, per, nsplit;
   const void *Jn, *Kn;
@@ -71,6 +79,10 @@ struct CoefArgs {
   const int* pair_of;
   const double *occ, *J, *K;
   double *Ac, *Bc, *Ep;
+  long nhc;              // also: HC = sum of the hc_split partials HCp (nhc elements each)
+  int hc_split;
+  const double* HCp;
+  double* HC;
 };
 struct EnergyArgs {
   int nw, npairs, ncwo, nb, nmo, nparts;
@@ -80,7 +92,7 @@ struct EnergyArgs {
   int* flag;
 };
 struct FockRedArgs { int nb, nw, nsplit; const double *Yp, *occ, *HC; double* Y; };
-struct GradArgs { int nmo, nw; const double* lam; double* G; };
+struct GradArgs { int nmo, nw, lsplit; const double* lp; double *lam, *G; };
 
 // Half transform, Eq. (12): bh[q][r] = sum_mu C[mu][q] b[l][mu][nu] with the
 // output column r = l*n_bf + nu flattened over (l, nu).  M = q, N = r (loads of
@@ -223,6 +235,10 @@ __device__ void jao_tile(const JaoArgs& a, long t, char* smem) {
 
 // Per-MO AO exchange: Kn[q] = X_q^T X_q with X_q = b_half[q] ([n_aux][n_bf]).
 // Square blocks bi <= bj only (the blocks of one q adjacent), mirrored like J.
+// A block with every 16x16 fragment needed runs the regular wave layout.  In
+// FP64/FP32, a block on the diagonal (fragments I <= J only) or on the ragged
+// edge trims each wave's fragment rows to the live ones under a balanced wave
+// plan, and a diagonal block stages its single operand panel once.
 template <int P, class Cfg>
 __host__ __device__ inline long kao_tiles(const KaoArgs& a) {
   const long nbk = cdiv(a.nb, Cfg::BM);
@@ -248,38 +264,65 @@ __device__ void kao_tile(const KaoArgs& a, long t, char* smem) {
   XCS<P, IOT<P>, Cfg::BN, Cfg::NT> lb;
   lb.init(X, nb, na, [&](int x, long& o) { o = nu0 + x; return nu0 + x < nb; });
   typename E::template Acc<Cfg> acc;
-  gemm_mainloop<E, Cfg>(la, lb, cdiv(na, E::BK), acc, smem);
   const long B2 = (long)nb * nb;
   IOT<P>* K = (IOT<P>*)a.Kn + (long)q * B2;
-  acc.for_each([&](int m, int n, double v) {
+  auto store = [&](int m, int n, double v) {
     const int mu = mu0 + m, nu = nu0 + n;
     if (mu < nb && nu < nb) {
       if (mu <= nu) K[(long)mu * nb + nu] = (IOT<P>)v;
       if (mu < nu) K[(long)nu * nb + mu] = (IOT<P>)v;
     }
-  });
+  };
+  constexpr int FB = Cfg::BM / 16;
+  const int fim = min(FB, cdiv(nb - mu0, 16)), fjm = min(FB, cdiv(nb - nu0, 16));
+  const bool diag = bi == bj;
+  // The split-BF16 engines (VALU-bound by operand splitting, and short of
+  // registers for the extra loop copies) always compute whole blocks.
+  constexpr bool kPlan = P == kF64 || P == kF32;
+  if (!kPlan || (!diag && fim == FB && fjm == FB)) {
+    gemm_mainloop<E, Cfg>(la, lb, cdiv(na, E::BK), acc, smem);
+    acc.for_each(store);
+    return;
+  }
+  if constexpr (kPlan) {
+    const WavePlan w =
+        make_wave_plan<Cfg>([&](int I, int J) { return I < fim && J < fjm && (!diag || I <= J); });
+    with_rows<Cfg::TM>(w.ni, [&](auto rows) {
+      constexpr int NI = decltype(rows)::value;
+      gemm_mainloop_with<E, Cfg>(la, lb, cdiv(na, E::BK), acc, smem, diag,
+                                 [&](const lds_char* SA, const lds_char* SB, typename E::template Acc<Cfg>& c) {
+                                   E::template mma_rows<Cfg, NI>(SA, SB, c, w);
+                                 });
+    });
+    acc.for_each(w, store);
+  }
 }
 
 // FP64 GEMM out[m][n] = sum_k A[k][m] B[k][n], both operands x-contiguous;
-// used for H C_Omega and lambda = C^T Y.
+// used for H C_Omega and lambda = C^T Y.  These are small (n_bf x n_omega
+// outputs), so the k range is split into ksplit parts written to separate
+// partial outputs, which their consumers add in a fixed order.
 template <int P, class Cfg>
 __host__ __device__ inline long gemm_tiles(const GemmArgs& a) {
-  return (long)cdiv(a.M, Cfg::BM) * cdiv(a.N, Cfg::BN);
+  return (long)cdiv(a.M, Cfg::BM) * cdiv(a.N, Cfg::BN) * a.ksplit;
 }
 template <int P, class Cfg>
 __device__ void gemm_tile(const GemmArgs& a, long t, char* smem) {
   using E = typename EngineOf<P>::type;
-  const int nmt = cdiv(a.M, Cfg::BM);
-  const int m0 = (int)(t % nmt) * Cfg::BM, n0 = (int)(t / nmt) * Cfg::BN;
+  const int nmt = cdiv(a.M, Cfg::BM), nnt = cdiv(a.N, Cfg::BN);
+  const int m0 = (int)(t % nmt) * Cfg::BM, n0 = (int)((t / nmt) % nnt) * Cfg::BN;
+  const int s = (int)(t / ((long)nmt * nnt));
+  const int k0 = s * a.kc, kn = min(a.kc, a.K - k0);
   const int M = a.M, N = a.N;
   XCS<P, double, Cfg::BM, Cfg::NT> la;
-  la.init(a.A, a.lda, a.K, [&](int x, long& o) { o = m0 + x; return m0 + x < M; });
+  la.init(a.A + (long)k0 * a.lda, a.lda, kn, [&](int x, long& o) { o = m0 + x; return m0 + x < M; });
   XCS<P, double, Cfg::BN, Cfg::NT> lb;
-  lb.init(a.B, a.ldb, a.K, [&](int x, long& o) { o = n0 + x; return n0 + x < N; });
+  lb.init(a.B + (long)k0 * a.ldb, a.ldb, kn, [&](int x, long& o) { o = n0 + x; return n0 + x < N; });
   typename E::template Acc<Cfg> acc;
-  gemm_mainloop<E, Cfg>(la, lb, cdiv(a.K, E::BK), acc, smem);
+  gemm_mainloop<E, Cfg>(la, lb, cdiv(kn, E::BK), acc, smem);
+  double* out = a.out + s * a.ostride;
   acc.for_each([&](int m, int n, double v) {
-    if (m0 + m < M && n0 + n < N) a.out[(long)(m0 + m) * a.ldo + n0 + n] = v;
+    if (m0 + m < M && n0 + n < N) out[(long)(m0 + m) * a.ldo + n0 + n] = v;
   });
 }
 
@@ -467,36 +510,47 @@ __device__ void coef_tile(const CoefArgs& a, long t, char* smem) {
   }
   if (tid == 0) a.Ep[t] = red[0];
   __syncthreads();
+  // HC = sum of the k-split partials of H C_Omega (fixed order), spread over
+  // this step's threads
+  const long nthr = coef_tiles<P, Cfg>(a) * 256;
+  for (long i = t * 256 + tid; i < a.nhc; i += nthr) {
+    double v = 0.0;
+    for (int s = 0; s < a.hc_split; ++s) v += a.HCp[s * a.nhc + i];
+    a.HC[i] = v;
+  }
 }
 
 // H_pp = c_p^T H c_p, the energy (coefficient partials + 2 sum n_p H_pp, fixed
-// order) and the device-side validation of the occupations.  One tile.
+// order) and the device-side validation of the occupations.  One 1024-thread
+// tile; H_pp has lanes along p (coalesced rows of C and HC) and the 16 waves
+// over mu, combined in wave order.
+constexpr int kEnergyThreads = 1024;
 template <int P, class Cfg>
 __host__ __device__ inline long energy_tiles(const EnergyArgs&) { return 1; }
 template <int P, class Cfg>
 __device__ void energy_tile(const EnergyArgs& a, long, char* smem) {
-  constexpr int kStage = 2048;
+  constexpr int kStage = 2048, NT = kEnergyThreads, NWV = NT / 64;
   double* socc = (double*)smem;
   int* spair = (int*)(socc + kStage);
-  double* red = (double*)(spair + kStage);
+  double* red = (double*)(spair + kStage);   // NT doubles
   const int tid = threadIdx.x;
   const int nw = a.nw, npairs = a.npairs, ncwo = a.ncwo;
   const bool staged = nw <= kStage;
   if (staged) {
-    for (int p = tid; p < nw; p += 256) {
+    for (int p = tid; p < nw; p += NT) {
       socc[p] = a.occ[p];
       spair[p] = pair_index(a.pair_of, p, npairs, ncwo);
     }
   }
   __syncthreads();
   int bad = 0;
-  for (int p = tid; p < nw; p += 256) {
+  for (int p = tid; p < nw; p += NT) {
     const double n = staged ? socc[p] : a.occ[p];
     if (!(n >= 0.0 && n <= 1.0)) bad |= kBadOcc;
     const int g = staged ? spair[p] : pair_index(a.pair_of, p, npairs, ncwo);
     if (g < 0 || g >= npairs || (p < npairs && g != p)) bad |= kBadMap;
   }
-  for (int g = tid; g < npairs; g += 256) {
+  for (int g = tid; g < npairs; g += NT) {
     double s = 0.0;
     int cnt = 0;
     for (int p = 0; p < nw; ++p) {
@@ -509,25 +563,34 @@ __device__ void energy_tile(const EnergyArgs& a, long, char* smem) {
   if (bad) atomicOr(a.flag, bad);
 
   double e = 0.0;
-  for (int i = tid; i < a.nparts; i += 256) e += a.Ep[i];
-  // H_pp: one wave per orbital, lanes over mu, fixed-order butterfly
+  for (int i = tid; i < a.nparts; i += NT) e += a.Ep[i];
   const int lane = tid & 63, wave = tid >> 6;
-  for (int p = wave; p < nw; p += 4) {
+  for (int p0 = 0; p0 < nw; p0 += 64) {
+    const int p = p0 + lane;
     double h = 0.0;
-    for (int mu = lane; mu < a.nb; mu += 64) h = fma(a.C[(long)mu * a.nmo + p], a.HC[(long)mu * nw + p], h);
-    for (int off = 32; off > 0; off >>= 1) h += __shfl_xor(h, off, 64);
-    if (lane == 0) e += 2.0 * a.occ[p] * h;
+    if (p < nw) {
+#pragma unroll 4
+      for (int mu = wave; mu < a.nb; mu += NWV) h = fma(a.C[(long)mu * a.nmo + p], a.HC[(long)mu * nw + p], h);
+    }
+    red[tid] = h;
+    __syncthreads();
+    if (wave == 0 && p < nw) {
+      double hp = 0.0;
+      for (int w = 0; w < NWV; ++w) hp += red[w * 64 + lane];
+      e += 2.0 * (staged ? socc[p] : a.occ[p]) * hp;
+    }
+    __syncthreads();
   }
   red[tid] = e;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = NT / 2; s > 0; s >>= 1) {
     if (tid < s) red[tid] += red[tid + s];
     __syncthreads();
   }
   if (tid == 0) a.energy[0] = red[0];
   __syncthreads();
 }
-constexpr int kEnergySmem = 2048 * 8 + 2048 * 4 + 256 * 8;
+constexpr int kEnergySmem = 2048 * 8 + 2048 * 4 + kEnergyThreads * 8;
 
 // Y[mu][q] = n_q HC[mu][q] + sum_s Ypart[s][mu][q] (fixed order)
 template <int P, class Cfg>
@@ -539,10 +602,12 @@ __device__ void fred_tile(const FockRedArgs& a, long t, char*) {
   if (i >= n) return;
   const int q = (int)(i % a.nw);
   double y = a.occ[q] * a.HC[i];
+#pragma unroll 8
   for (int s = 0; s < a.nsplit; ++s) y += a.Yp[(long)s * n + i];
   a.Y[i] = y;
 }
 
+// lambda = sum of its k-split partials (fixed order), written out for b < n_omega;
 // G[a][b] = 4 (L[a][b] - L[b][a]),  L[a][b] = lambda[a][b] for b < n_omega, else 0.
 template <int P, class Cfg>
 __host__ __device__ inline long grad_tiles(const GradArgs& a) { return cdiv((long)a.nmo * a.nmo, 256); }
@@ -552,8 +617,15 @@ __device__ void grad_tile(const GradArgs& a, long t, char*) {
   const long i = t * 256 + threadIdx.x;
   if (i >= (long)nmo * nmo) return;
   const int r = (int)(i / nmo), c = (int)(i - (long)r * nmo);
-  const double lab = c < nw ? a.lam[(long)r * nw + c] : 0.0;
-  const double lba = r < nw ? a.lam[(long)c * nw + r] : 0.0;
+  const long ls = (long)nmo * nw;
+  auto lam = [&](int x, int y) {   // lambda[x][y], y < nw
+    double v = 0.0;
+    for (int s = 0; s < a.lsplit; ++s) v += a.lp[s * ls + (long)x * nw + y];
+    return v;
+  };
+  const double lab = c < nw ? lam(r, c) : 0.0;
+  const double lba = r < nw ? lam(c, r) : 0.0;
+  if (c < nw) a.lam[(long)r * nw + c] = lab;
   a.G[i] = 4.0 * (lab - lba);
 }
 
@@ -572,9 +644,10 @@ __device__ __forceinline__ int find_owner(const long* __restrict__ off, int n, l
   return lo;
 }
 
-#define RIF_STEP_KERNELS(NAME, ARGS, SMEM_BYTES, NTHREADS, REMAP)                                  \
+#define RIF_STEP_KERNELS(NAME, ARGS, SMEM_BYTES, NTHREADS, REMAP, WPE)                             \
   template <int P, class Cfg>                                                                      \
-  __global__ __launch_bounds__(NTHREADS) void k_##NAME(ARGS a) {                                   \
+  __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(WPE))) void k_##NAME(  \
+      ARGS a) {                                                                                    \
     __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES];                                 \
     const long t = REMAP ? xcd_remap(blockIdx.x, (long)gridDim.x) : (long)blockIdx.x;              \
     NAME##_tile<P, Cfg>(a, t, smem);                                                               \
@@ -590,19 +663,29 @@ __device__ __forceinline__ int find_owner(const long* __restrict__ off, int n, l
     }                                                                                              \
   }
 
+// Single-molecule GEMM tiles keep two workgroups per CU where the engine's
+// accumulators allow it: FP64 8-wave tiles are held to 128 VGPRs (4 waves per
+// SIMD); FP32 (FP32 partial and FP64 folded accumulators) and split-BF16
+// (three accumulator sets) 8-wave tiles to 256.  The grouped kernels (which
+// also carry the work-list search) are left to the compiler.
+template <int P, class Cfg>
+constexpr int gemm_wpe() {
+  return Cfg::NT == 512 ? (P == kF64 ? 4 : 2) : 1;
+}
 #define GEMM_SMEM smem_bytes<typename EngineOf<P>::type, Cfg>()
-RIF_STEP_KERNELS(half, HalfArgs, GEMM_SMEM, Cfg::NT, false)
-RIF_STEP_KERNELS(mo, MoArgs, GEMM_SMEM, Cfg::NT, false)
-RIF_STEP_KERNELS(jao, JaoArgs, GEMM_SMEM, Cfg::NT, true)
-RIF_STEP_KERNELS(kao, KaoArgs, GEMM_SMEM, Cfg::NT, true)
-RIF_STEP_KERNELS(gemm, GemmArgs, GEMM_SMEM, Cfg::NT, false)
-RIF_STEP_KERNELS(fock, FockArgs, GEMM_SMEM, Cfg::NT, false)
-RIF_STEP_KERNELS(jkp, JkArgs, 16, 256, false)
-RIF_STEP_KERNELS(jkr, JkArgs, 16, 256, false)
-RIF_STEP_KERNELS(coef, CoefArgs, 256 * 8, 256, false)
-RIF_STEP_KERNELS(energy, EnergyArgs, kEnergySmem, 256, false)
-RIF_STEP_KERNELS(fred, FockRedArgs, 16, 256, false)
-RIF_STEP_KERNELS(grad, GradArgs, 16, 256, false)
+#define GEMM_WPE (gemm_wpe<P, Cfg>())
+RIF_STEP_KERNELS(half, HalfArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
+RIF_STEP_KERNELS(mo, MoArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
+RIF_STEP_KERNELS(jao, JaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE)
+RIF_STEP_KERNELS(kao, KaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE)
+RIF_STEP_KERNELS(gemm, GemmArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
+RIF_STEP_KERNELS(fock, FockArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
+RIF_STEP_KERNELS(jkp, JkArgs, 16, 256, false, 1)
+RIF_STEP_KERNELS(jkr, JkArgs, 16, 256, false, 1)
+RIF_STEP_KERNELS(coef, CoefArgs, 256 * 8, 256, false, 1)
+RIF_STEP_KERNELS(energy, EnergyArgs, kEnergySmem, kEnergyThreads, false, 1)
+RIF_STEP_KERNELS(fred, FockRedArgs, 16, 256, false, 1)
+RIF_STEP_KERNELS(grad, GradArgs, 16, 256, false, 1)
 
 // ---------------------------------------------------------------------------
 // Launchers.  Each GEMM-shaped step exists in four tile variants per mode:
@@ -624,6 +707,7 @@ template <> struct Vars<32> {  // BF16 split engines: smaller wave tiles (three 
   using V3 = TileCfg<64, 128, 32, 32, 64>;
 };
 struct Cfg256 { static constexpr int NT = 256; };  // element-wise steps
+struct CfgEnergy { static constexpr int NT = kEnergyThreads; };
 
 template <int P, class F>
 static decltype(auto) dispatch(int v, F&& f) {
@@ -720,7 +804,7 @@ using CfgSmall = TileCfg<64, 64, 16, 32, 32>;
   }
 RIF_FIXED_STEP(gemm, GemmArgs, "small_gemm", kF64, CfgSmall)
 RIF_FIXED_STEP(coef, CoefArgs, "coef", kF64, Cfg256)
-RIF_FIXED_STEP(energy, EnergyArgs, "energy", kF64, Cfg256)
+RIF_FIXED_STEP(energy, EnergyArgs, "energy", kF64, CfgEnergy)
 RIF_FIXED_STEP(fred, FockRedArgs, "fock_reduce", kF64, Cfg256)
 RIF_FIXED_STEP(grad, GradArgs, "grad", kF64, Cfg256)
 template <int P>
@@ -739,29 +823,41 @@ static rif_status step1_jk(rif_ctx* c, const JkArgs& a) {
 // ---- workspace plan of one molecule (shared by the single and batched paths)
 struct Plan {
   int nb, na, nw, nmo, npairs, ncwo;
-  int jk_nsplit, fock_nsplit, fock_per, nparts;
-  size_t o_part, o_hc, o_a, o_b, o_yp, o_y, o_ep, bytes;
+  int jk_nsplit, fock_nsplit, fock_per, nparts, hc_split, lam_split, small_kc;
+  size_t o_part, o_hcp, o_hc, o_a, o_b, o_yp, o_y, o_ep, o_lp, bytes;
   Plan(int nb_, int na_, int npairs_, int ncwo_, int nmo_) {
     nb = nb_; na = na_; npairs = npairs_; ncwo = ncwo_; nmo = nmo_;
     nw = npairs * (1 + ncwo);
     const long w2 = (long)nw * nw;
     const long nx = cdiv(w2, 256);
     jk_nsplit = (int)std::max(1L, std::min((long)na, (1024L + nx - 1) / nx));
-    // fock split-K over the stacked slabs, sized so a 64x64-tile launch has >= 1024 tiles
+    // fock split-K over the stacked slabs, sized so a 64x64-tile launch has
+    // about 4096 tiles (a 128x128 one about 1024: several per CU)
     const int slabs = 2 * nw;
     const long mt = cdiv(nb, 64), nt = cdiv(nw, 64);
-    int ns = std::max(1, std::min(slabs, cdiv(1024, mt * nt)));
+    int ns = std::max(1, std::min(slabs, cdiv(4096, mt * nt)));
     fock_per = cdiv(slabs, ns);
     fock_nsplit = cdiv(slabs, fock_per);
     nparts = (int)nx;
+    // the two small GEMMs (n_bf x n_omega outputs, k = n_bf): k split so a
+    // launch has about 256 tiles of 64x64, at least two 16-deep slices each
+    {
+      const long tiles = cdiv(nb, 64) * cdiv(nw, 64);
+      const int slices = cdiv(nb, 16);
+      const int want = (int)std::max(1L, std::min((long)std::max(1, slices / 2), (long)cdiv(256, tiles)));
+      small_kc = 16 * cdiv(slices, want);
+      hc_split = lam_split = cdiv(nb, small_kc);
+    }
     Carve cv;
     o_part = cv.take<double>(2L * jk_nsplit * w2);
+    o_hcp = cv.take<double>((size_t)hc_split * nb * nw);
     o_hc = cv.take<double>((size_t)nb * nw);
     o_a = cv.take<double>((size_t)w2);
     o_b = cv.take<double>((size_t)w2);
     o_yp = cv.take<double>((size_t)fock_nsplit * nb * nw);
     o_y = cv.take<double>((size_t)nb * nw);
     o_ep = cv.take<double>((size_t)nparts);
+    o_lp = cv.take<double>((size_t)lam_split * nmo * nw);
     bytes = cv.off;
   }
 };
@@ -775,24 +871,30 @@ static BuildArgs make_build_args(const Plan& pl, const rif_instance& in, int fun
   BuildArgs A;
   const int nb = pl.nb, na = pl.na, nw = pl.nw, nmo = pl.nmo;
   double* part = (double*)(ws + pl.o_part);
+  double* HCp = (double*)(ws + pl.o_hcp);
   double* HC = (double*)(ws + pl.o_hc);
   double* Ac = (double*)(ws + pl.o_a);
   double* Bc = (double*)(ws + pl.o_b);
   double* Yp = (double*)(ws + pl.o_yp);
   double* Y = (double*)(ws + pl.o_y);
   double* Ep = (double*)(ws + pl.o_ep);
+  double* Lp = (double*)(ws + pl.o_lp);
   A.half = HalfArgs{nb, nw, nmo, (long)na * nb, in.b, in.C, in.b_half};
   A.mo = MoArgs{nb, na, nw, nmo, in.b_half, in.C, in.b_mo, in.d};
   A.jk = JkArgs{na, nw, pl.jk_nsplit, in.b_mo, in.d, part, in.J, in.K};
   A.jao = JaoArgs{nb, na, nw, in.b, in.d, in.Jn};
   A.kao = KaoArgs{nb, na, nw, in.b_half, in.Kn};
-  A.hc = GemmArgs{nb, nw, nb, in.H, (long)nb, in.C, (long)nmo, HC, (long)nw};
-  A.coef = CoefArgs{functional, nw, pl.npairs, pl.ncwo, in.pair_of, in.occ, in.J, in.K, Ac, Bc, Ep};
-  A.energy = EnergyArgs{nw, pl.npairs, pl.ncwo, nb, nmo, pl.nparts, in.pair_of, in.occ, in.C, HC, Ep, in.energy, flag};
+  A.hc = GemmArgs{nb, nw, nb, in.H, (long)nb, in.C, (long)nmo, HCp, (long)nw,
+                  pl.hc_split, pl.small_kc, (long)nb * nw};
+  A.coef = CoefArgs{functional, nw, pl.npairs, pl.ncwo, in.pair_of, in.occ, in.J, in.K, Ac, Bc, Ep,
+                    (long)nb * nw, pl.hc_split, HCp, HC};
+  A.energy = EnergyArgs{nw, pl.npairs, pl.ncwo, nb, nmo, pl.nparts, in.pair_of, in.occ, in.C, HC, Ep, in.energy,
+                        flag};
   A.fock = FockArgs{nb, nw, nmo, pl.fock_per, pl.fock_nsplit, in.Jn, in.Kn, Ac, Bc, in.C, Yp};
   A.fred = FockRedArgs{nb, nw, pl.fock_nsplit, Yp, in.occ, HC, Y};
-  A.lam = GemmArgs{nmo, nw, nb, in.C, (long)nmo, Y, (long)nw, in.lambda, (long)nw};
-  A.grad = GradArgs{nmo, nw, in.lambda, in.grad};
+  A.lam = GemmArgs{nmo, nw, nb, in.C, (long)nmo, Y, (long)nw, Lp, (long)nw, pl.lam_split, pl.small_kc,
+                   (long)nmo * nw};
+  A.grad = GradArgs{nmo, nw, pl.lam_split, Lp, in.lambda, in.grad};
   return A;
 }
 
@@ -1028,7 +1130,7 @@ RIF_GROUP_FIXED_P(jkr, JkArgs, "g_jk_mo_reduce")
 RIF_GROUP_FIXED(hc, gemm, GemmArgs, "g_hc_gemm", kF64, CfgSmall)
 RIF_GROUP_FIXED(lam, gemm, GemmArgs, "g_lambda_gemm", kF64, CfgSmall)
 RIF_GROUP_FIXED(coef, coef, CoefArgs, "g_coef", kF64, Cfg256)
-RIF_GROUP_FIXED(energy, energy, EnergyArgs, "g_energy", kF64, Cfg256)
+RIF_GROUP_FIXED(energy, energy, EnergyArgs, "g_energy", kF64, CfgEnergy)
 RIF_GROUP_FIXED(fred, fred, FockRedArgs, "g_fock_reduce", kF64, Cfg256)
 RIF_GROUP_FIXED(grad, grad, GradArgs, "g_grad", kF64, Cfg256)
 

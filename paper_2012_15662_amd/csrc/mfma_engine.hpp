@@ -26,6 +26,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace rif {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -156,6 +158,75 @@ __device__ __forceinline__ void wave_origin(int WAVES_N, int WM, int WN, int& wm
   wn0 = (wave % WAVES_N) * WN;
 }
 
+// Wave plan: which TM x TN block of 16x16 fragments a wave computes (origin
+// wm0, wn0 inside the tile) and how many of its fragment rows (ni <= TM, a
+// prefix) hold needed outputs.  The regular plan is the fixed layout with all
+// rows.  For tiles where some fragments are not needed (blocks on the diagonal
+// of a symmetric result, ragged edges), make_wave_plan() trims each region to
+// its live rows and hands the regions out so that each SIMD gets a heavy
+// region with a light one: regions are ranked by work and wave w takes rank
+// kRankOfWave[w], which pairs ranks (0,6) (7,1) (2,4) (5,3) for waves
+// {w, w+4} and (0,7) (2,5) (6,1) (4,3) for waves {2k, 2k+1}, whichever way
+// the waves of a workgroup are spread over the SIMDs.
+struct WavePlan {
+  int wm0, wn0, ni;
+};
+template <class Cfg>
+__device__ __forceinline__ WavePlan regular_plan() {
+  WavePlan w;
+  wave_origin(Cfg::WAVES_N, Cfg::WM, Cfg::WN, w.wm0, w.wn0);
+  w.ni = Cfg::TM;
+  return w;
+}
+// live(I, J): whether tile-local fragment (I, J) is needed.
+template <class Cfg, class Live>
+__device__ __forceinline__ WavePlan make_wave_plan(Live live) {
+  constexpr int NW = Cfg::NWAVES;
+  int rows[NW];
+#pragma unroll
+  for (int r = 0; r < NW; ++r) {
+    const int m0 = (r / Cfg::WAVES_N) * Cfg::TM, n0 = (r % Cfg::WAVES_N) * Cfg::TN;
+    int n = 0;
+#pragma unroll
+    for (int i = 0; i < Cfg::TM; ++i)
+#pragma unroll
+      for (int j = 0; j < Cfg::TN; ++j)
+        if (live(m0 + i, n0 + j)) n = i + 1;
+    rows[r] = n;
+  }
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int rank = wave;
+  if constexpr (NW == 8) {
+    constexpr int kRankOfWave[8] = {0, 7, 2, 5, 6, 1, 4, 3};
+    rank = kRankOfWave[wave];
+  }
+  // region of the given rank: most rows first, ties by region index
+  WavePlan w{0, 0, 0};
+#pragma unroll
+  for (int r = 0; r < NW; ++r) {
+    int above = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) above += rows[q] > rows[r] || (rows[q] == rows[r] && q < r);
+    if (above == rank) {
+      w.wm0 = (r / Cfg::WAVES_N) * Cfg::WM;
+      w.wn0 = (r % Cfg::WAVES_N) * Cfg::WN;
+      w.ni = rows[r];
+    }
+  }
+  return w;
+}
+// Calls f(std::integral_constant<int, n>) for n = ni in 0..TM, so each row
+// count gets its own straight-line code (callers put this outside their slice
+// loop, which keeps one variant's registers live at a time).
+template <int TM, class F>
+__device__ __forceinline__ void with_rows(int ni, F&& f) {
+  if (ni >= TM) {
+    f(std::integral_constant<int, TM>());
+  } else if constexpr (TM > 0) {
+    with_rows<TM - 1>(ni, f);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // FP64 engine (BK_ = slice depth)
 template <int BK_ = 16>
@@ -175,17 +246,19 @@ struct EngF64T {
     __device__ void flush() {}
     // f64 16x16x4: register r of lane l holds row l/16 + 4r, column l%16.
     template <class F>
-    __device__ void for_each(F&& f) const {
+    __device__ void for_each(F&& f) const { for_each(regular_plan<Cfg>(), f); }
+    template <class F>
+    __device__ void for_each(const WavePlan& w, F&& f) const {
       const int lane = threadIdx.x & 63;
-      int wm0, wn0;
-      wave_origin(Cfg::WAVES_N, Cfg::WM, Cfg::WN, wm0, wn0);
 #pragma unroll
       for (int i = 0; i < Cfg::TM; ++i)
 #pragma unroll
         for (int j = 0; j < Cfg::TN; ++j)
+          if (i < w.ni) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            f(wm0 + i * 16 + (lane >> 4) + 4 * r, wn0 + j * 16 + (lane & 15), v[i][j][r]);
+            for (int r = 0; r < 4; ++r)
+              f(w.wm0 + i * 16 + (lane >> 4) + 4 * r, w.wn0 + j * 16 + (lane & 15), v[i][j][r]);
+          }
     }
   };
   template <int BX, class L>
@@ -195,27 +268,32 @@ struct EngF64T {
     for (int p = 0; p < L::NP; ++p)
       s[ld.kl(p) * (BX + PAD) + ld.xl(p)] = ld.valid(p, 0, kt) ? ld.val(r, p, 0) : 0.0;
   }
-  template <class Cfg>
-  __device__ static void mma(const lds_char* SA, const lds_char* SB, Acc<Cfg>& acc) {
+  // Rows 0..NI-1 of the wave's fragment block (NI = TM for the regular layout).
+  template <class Cfg, int NI>
+  __device__ static void mma_rows(const lds_char* SA, const lds_char* SB, Acc<Cfg>& acc, const WavePlan& w) {
     const lds_f64* As = (const lds_f64*)SA;
     const lds_f64* Bs = (const lds_f64*)SB;
     const int lane = threadIdx.x & 63;
-    int wm0, wn0;
-    wave_origin(Cfg::WAVES_N, Cfg::WM, Cfg::WN, wm0, wn0);
     const int kr = lane >> 4, xc = lane & 15;
+    if constexpr (NI > 0) {
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      double a[Cfg::TM], b[Cfg::TN];
+      for (int kk = 0; kk < BK; kk += 4) {
+        double a[NI], b[Cfg::TN];
 #pragma unroll
-      for (int i = 0; i < Cfg::TM; ++i) a[i] = As[(kk + kr) * (Cfg::BM + PAD) + wm0 + i * 16 + xc];
+        for (int i = 0; i < NI; ++i) a[i] = As[(kk + kr) * (Cfg::BM + PAD) + w.wm0 + i * 16 + xc];
 #pragma unroll
-      for (int j = 0; j < Cfg::TN; ++j) b[j] = Bs[(kk + kr) * (Cfg::BN + PAD) + wn0 + j * 16 + xc];
+        for (int j = 0; j < Cfg::TN; ++j) b[j] = Bs[(kk + kr) * (Cfg::BN + PAD) + w.wn0 + j * 16 + xc];
 #pragma unroll
-      for (int i = 0; i < Cfg::TM; ++i)
+        for (int i = 0; i < NI; ++i)
 #pragma unroll
-        for (int j = 0; j < Cfg::TN; ++j)
-          acc.v[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc.v[i][j], 0, 0, 0);
+          for (int j = 0; j < Cfg::TN; ++j)
+            acc.v[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc.v[i][j], 0, 0, 0);
+      }
     }
+  }
+  template <class Cfg>
+  __device__ static void mma(const lds_char* SA, const lds_char* SB, Acc<Cfg>& acc, const WavePlan& w) {
+    mma_rows<Cfg, Cfg::TM>(SA, SB, acc, w);
   }
 };
 
@@ -250,17 +328,19 @@ struct EngF32 {
     }
     // f32 MFMA layout: register r of lane l holds row 4*(l/16) + r, column l%16.
     template <class F>
-    __device__ void for_each(F&& f) const {
+    __device__ void for_each(F&& f) const { for_each(regular_plan<Cfg>(), f); }
+    template <class F>
+    __device__ void for_each(const WavePlan& w, F&& f) const {
       const int lane = threadIdx.x & 63;
-      int wm0, wn0;
-      wave_origin(Cfg::WAVES_N, Cfg::WM, Cfg::WN, wm0, wn0);
 #pragma unroll
       for (int i = 0; i < Cfg::TM; ++i)
 #pragma unroll
         for (int j = 0; j < Cfg::TN; ++j)
+          if (i < w.ni) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            f(wm0 + i * 16 + 4 * (lane >> 4) + r, wn0 + j * 16 + (lane & 15), v[i][j][r]);
+            for (int r = 0; r < 4; ++r)
+              f(w.wm0 + i * 16 + 4 * (lane >> 4) + r, w.wn0 + j * 16 + (lane & 15), v[i][j][r]);
+          }
     }
   };
   template <int BX, class L>
@@ -270,27 +350,32 @@ struct EngF32 {
     for (int p = 0; p < L::NP; ++p)
       s[ld.kl(p) * (BX + PAD) + ld.xl(p)] = ld.valid(p, 0, kt) ? (float)ld.val(r, p, 0) : 0.f;
   }
-  template <class Cfg>
-  __device__ static void mma(const lds_char* SA, const lds_char* SB, Acc<Cfg>& acc) {
+  // Rows 0..NI-1 of the wave's fragment block (NI = TM for the regular layout).
+  template <class Cfg, int NI>
+  __device__ static void mma_rows(const lds_char* SA, const lds_char* SB, Acc<Cfg>& acc, const WavePlan& w) {
     const lds_f32* As = (const lds_f32*)SA;
     const lds_f32* Bs = (const lds_f32*)SB;
     const int lane = threadIdx.x & 63;
-    int wm0, wn0;
-    wave_origin(Cfg::WAVES_N, Cfg::WM, Cfg::WN, wm0, wn0);
     const int kr = lane >> 4, xc = lane & 15;
+    if constexpr (NI > 0) {
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      float a[Cfg::TM], b[Cfg::TN];
+      for (int kk = 0; kk < BK; kk += 4) {
+        float a[NI], b[Cfg::TN];
 #pragma unroll
-      for (int i = 0; i < Cfg::TM; ++i) a[i] = As[(kk + kr) * (Cfg::BM + PAD) + wm0 + i * 16 + xc];
+        for (int i = 0; i < NI; ++i) a[i] = As[(kk + kr) * (Cfg::BM + PAD) + w.wm0 + i * 16 + xc];
 #pragma unroll
-      for (int j = 0; j < Cfg::TN; ++j) b[j] = Bs[(kk + kr) * (Cfg::BN + PAD) + wn0 + j * 16 + xc];
+        for (int j = 0; j < Cfg::TN; ++j) b[j] = Bs[(kk + kr) * (Cfg::BN + PAD) + w.wn0 + j * 16 + xc];
 #pragma unroll
-      for (int i = 0; i < Cfg::TM; ++i)
+        for (int i = 0; i < NI; ++i)
 #pragma unroll
-        for (int j = 0; j < Cfg::TN; ++j)
-          acc.s[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc.s[i][j], 0, 0, 0);
+          for (int j = 0; j < Cfg::TN; ++j)
+            acc.s[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc.s[i][j], 0, 0, 0);
+      }
     }
+  }
+  template <class Cfg>
+  __device__ static void mma(const lds_char* SA, const lds_char* SB, Acc<Cfg>& acc, const WavePlan& w) {
+    mma_rows<Cfg, Cfg::TM>(SA, SB, acc, w);
   }
 };
 
@@ -342,17 +427,19 @@ struct EngBF16 {
         }
     }
     template <class F>
-    __device__ void for_each(F&& f) const {
+    __device__ void for_each(F&& f) const { for_each(regular_plan<Cfg>(), f); }
+    template <class F>
+    __device__ void for_each(const WavePlan& w, F&& f) const {
       const int lane = threadIdx.x & 63;
-      int wm0, wn0;
-      wave_origin(Cfg::WAVES_N, Cfg::WM, Cfg::WN, wm0, wn0);
 #pragma unroll
       for (int i = 0; i < Cfg::TM; ++i)
 #pragma unroll
         for (int j = 0; j < Cfg::TN; ++j)
+          if (i < w.ni) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            f(wm0 + i * 16 + 4 * (lane >> 4) + r, wn0 + j * 16 + (lane & 15), v[i][j][r]);
+            for (int r = 0; r < 4; ++r)
+              f(w.wm0 + i * 16 + 4 * (lane >> 4) + r, w.wn0 + j * 16 + (lane & 15), v[i][j][r]);
+          }
     }
   };
   // Splits each group of 8 consecutive k into NPC bf16 pieces and writes one
@@ -379,39 +466,44 @@ struct EngBF16 {
         *(lds_u16x8*)(S + s * piece_bytes<BX>() + off * 2) = pc[s];
     }
   }
-  template <class Cfg>
-  __device__ static void mma(const lds_char* SA, const lds_char* SB, Acc<Cfg>& acc) {
+  // Rows 0..NI-1 of the wave's fragment block (NI = TM for the regular layout).
+  template <class Cfg, int NI>
+  __device__ static void mma_rows(const lds_char* SA, const lds_char* SB, Acc<Cfg>& acc, const WavePlan& w) {
     const int lane = threadIdx.x & 63;
-    int wm0, wn0;
-    wave_origin(Cfg::WAVES_N, Cfg::WM, Cfg::WN, wm0, wn0);
     const int xc = lane & 15, k0 = 8 * (lane >> 4);
-    bf16x8 a[NPC][Cfg::TM], b[NPC][Cfg::TN];
+    if constexpr (NI > 0) {
+      bf16x8 a[NPC][NI], b[NPC][Cfg::TN];
 #pragma unroll
-    for (int s = 0; s < NPC; ++s) {
+      for (int s = 0; s < NPC; ++s) {
 #pragma unroll
-      for (int i = 0; i < Cfg::TM; ++i)
-        a[s][i] = __builtin_bit_cast(bf16x8, *(const lds_u16x8*)(SA + s * piece_bytes<Cfg::BM>() +
-                                                                  ((wm0 + i * 16 + xc) * ROW + k0) * 2));
+        for (int i = 0; i < NI; ++i)
+          a[s][i] = __builtin_bit_cast(bf16x8, *(const lds_u16x8*)(SA + s * piece_bytes<Cfg::BM>() +
+                                                                    ((w.wm0 + i * 16 + xc) * ROW + k0) * 2));
 #pragma unroll
-      for (int j = 0; j < Cfg::TN; ++j)
-        b[s][j] = __builtin_bit_cast(bf16x8, *(const lds_u16x8*)(SB + s * piece_bytes<Cfg::BN>() +
-                                                                  ((wn0 + j * 16 + xc) * ROW + k0) * 2));
-    }
-#pragma unroll
-    for (int i = 0; i < Cfg::TM; ++i)
-#pragma unroll
-      for (int j = 0; j < Cfg::TN; ++j) {
-        f4 x = acc.xx[i][j];
-        if constexpr (NPC == 3) {
-          x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], x, 0, 0, 0);
-          x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], x, 0, 0, 0);
-          x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], x, 0, 0, 0);
-        }
-        x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], x, 0, 0, 0);
-        x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], x, 0, 0, 0);
-        acc.xx[i][j] = x;
-        acc.hh[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc.hh[i][j], 0, 0, 0);
+        for (int j = 0; j < Cfg::TN; ++j)
+          b[s][j] = __builtin_bit_cast(bf16x8, *(const lds_u16x8*)(SB + s * piece_bytes<Cfg::BN>() +
+                                                                    ((w.wn0 + j * 16 + xc) * ROW + k0) * 2));
       }
+#pragma unroll
+      for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int j = 0; j < Cfg::TN; ++j) {
+          f4 x = acc.xx[i][j];
+          if constexpr (NPC == 3) {
+            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], x, 0, 0, 0);
+            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], x, 0, 0, 0);
+            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], x, 0, 0, 0);
+          }
+          x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], x, 0, 0, 0);
+          x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], x, 0, 0, 0);
+          acc.xx[i][j] = x;
+          acc.hh[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc.hh[i][j], 0, 0, 0);
+        }
+    }
+  }
+  template <class Cfg>
+  __device__ static void mma(const lds_char* SA, const lds_char* SB, Acc<Cfg>& acc, const WavePlan& w) {
+    mma_rows<Cfg, Cfg::TM>(SA, SB, acc, w);
   }
 };
 
@@ -426,40 +518,55 @@ template <> struct EngineOf<kBF16x3> { using type = EngBF16<2>; };
 template <> struct EngineOf<kBF16x6> { using type = EngBF16<3>; };
 
 // Main loop over nk slices.  smem: smem_bytes<E, Cfg>() bytes of LDS, laid
-// out [A stage 0][A stage 1][B stage 0][B stage 1].
-template <class E, class Cfg, class LA, class LB>
-__device__ __forceinline__ void gemm_mainloop(LA& la, LB& lb, int nk, typename E::template Acc<Cfg>& acc,
-                                              char* smem_generic) {
+// out [A stage 0][A stage 1][B stage 0][B stage 1].  mma(SA, SB, acc)
+// consumes one staged slice.  With b_is_a (square tiles whose two operands
+// are the same panel) only A is loaded and staged, and mma reads it twice.
+template <class E, class Cfg, class LA, class LB, class MMA>
+__device__ __forceinline__ void gemm_mainloop_with(LA& la, LB& lb, int nk, typename E::template Acc<Cfg>& acc,
+                                                   char* smem_generic, bool b_is_a, MMA&& mma) {
   constexpr int SA = E::template stage_bytes<Cfg::BM>();
   constexpr int SB = E::template stage_bytes<Cfg::BN>();
   lds_char* smem = (lds_char*)smem_generic;
   lds_char* As[2] = {smem, smem + SA};
   lds_char* Bs[2] = {smem + 2 * SA, smem + 2 * SA + SB};
+  if (b_is_a) {
+    Bs[0] = As[0];
+    Bs[1] = As[1];
+  }
   typename LA::type ra[LA::RR];
   typename LB::type rb[LB::RR];
   acc.zero();
   if (nk <= 0) return;
   la.fetch(0, ra);
-  lb.fetch(0, rb);
+  if (!b_is_a) lb.fetch(0, rb);
   E::template stash<Cfg::BM>(As[0], la, ra, 0);
-  E::template stash<Cfg::BN>(Bs[0], lb, rb, 0);
+  if (!b_is_a) E::template stash<Cfg::BN>(Bs[0], lb, rb, 0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     const bool more = kt + 1 < nk;
     if (more) {
       la.fetch(kt + 1, ra);
-      lb.fetch(kt + 1, rb);
+      if (!b_is_a) lb.fetch(kt + 1, rb);
     }
-    E::template mma<Cfg>(As[cur], Bs[cur], acc);
+    mma(As[cur], Bs[cur], acc);
     if ((kt + 1) % E::CHUNK == 0) acc.flush();
     if (more) {
       E::template stash<Cfg::BM>(As[cur ^ 1], la, ra, kt + 1);
-      E::template stash<Cfg::BN>(Bs[cur ^ 1], lb, rb, kt + 1);
+      if (!b_is_a) E::template stash<Cfg::BN>(Bs[cur ^ 1], lb, rb, kt + 1);
     }
     __syncthreads();
   }
   acc.flush();
+}
+
+template <class E, class Cfg, class LA, class LB>
+__device__ __forceinline__ void gemm_mainloop(LA& la, LB& lb, int nk, typename E::template Acc<Cfg>& acc,
+                                              char* smem_generic) {
+  gemm_mainloop_with<E, Cfg>(la, lb, nk, acc, smem_generic, false,
+                             [&](const lds_char* SA, const lds_char* SB, typename E::template Acc<Cfg>& c) {
+                               E::template mma<Cfg>(SA, SB, c, regular_plan<Cfg>());
+                             });
 }
 
 }  // namespace rif

@@ -54,20 +54,30 @@ int pick_variant(rif_ctx* c, const char* kernel, std::initializer_list<long> sha
   if (hipEventCreate(&e0) != hipSuccess) return -1;
   if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return -1; }
   rif_ctx::Tune t{key, heuristic, std::vector<float>(nvar, -1.f)};
-  float best = 1e30f;
   const bool prof = c->prof;
   c->prof = false;
-  for (int v = 0; v < nvar; ++v) {
-    if (run(v) != RIF_OK) continue;  // warm-up; variants a kernel lacks report an error
-    (void)hipEventRecord(e0, c->stream);
-    for (int r = 0; r < 3; ++r) run(v);
-    (void)hipEventRecord(e1, c->stream);
-    if (hipEventSynchronize(e1) != hipSuccess) { c->prof = prof; return -1; }
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    t.ms[v] = ms / 3;
-    if (t.ms[v] < best) { best = t.ms[v]; t.variant = v; }
-  }
+  // One warm-up launch per variant (variants a kernel lacks report an error),
+  // then kRounds interleaved rounds of kReps launches each; a variant's time
+  // is its fastest round, so a clock still ramping up at the start does not
+  // favour the variants timed last.
+  constexpr int kRounds = 3, kReps = 2;
+  std::vector<char> ok(nvar, 0);
+  for (int v = 0; v < nvar; ++v) ok[v] = run(v) == RIF_OK;
+  for (int round = 0; round < kRounds; ++round)
+    for (int v = 0; v < nvar; ++v) {
+      if (!ok[v]) continue;
+      (void)hipEventRecord(e0, c->stream);
+      for (int r = 0; r < kReps; ++r) run(v);
+      (void)hipEventRecord(e1, c->stream);
+      if (hipEventSynchronize(e1) != hipSuccess) { c->prof = prof; return -1; }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ms /= kReps;
+      if (t.ms[v] < 0.f || ms < t.ms[v]) t.ms[v] = ms;
+    }
+  float best = 1e30f;
+  for (int v = 0; v < nvar; ++v)
+    if (ok[v] && t.ms[v] < best) { best = t.ms[v]; t.variant = v; }
   c->prof = prof;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
