@@ -30,6 +30,33 @@ PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}   # MFMA products pe
 MODE_PEAK = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16"}
 HBM_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each divided by what the same
+# counter reads per byte of a 1 GiB device-to-device copy (FETCH_SIZE 0.5,
+# WRITE_SIZE 1.0).  "src" is the sha256 of the GEMM kernel sources the counters
+# were taken on: a figure is reported only while those sources are unchanged.
+# The runs and their command lines are in profiles/.
+TRAFFIC = {
+    ("half_transform", "c6h12", "fp64"): {"src": "32f8e15e2cfd05a2", "fetch": 1174195405, "write": 348756378,
+                                         "profile": "profiles/fp64_c6h12_counters.md"},
+}
+
+
+def kernel_src_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("mfma_engine.hpp", "kernels.hip"):
+        with open(os.path.join(ROOT, "paper_2012_15662_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_of(kernel, workload, prec):
+    t = TRAFFIC.get((kernel, workload, prec))
+    if t is None or t["src"] != kernel_src_hash():
+        return None, None
+    return t["fetch"] + t["write"], {"fetch_bytes": t["fetch"], "write_bytes": t["write"], "profile": t["profile"]}
+
 
 def kernel_flops(nb, na, nw, nmo):
     """Algorithmic flops per launch of each kernel (symmetric outputs counted once)."""
@@ -42,6 +69,16 @@ def kernel_flops(nb, na, nw, nmo):
         "hc_gemm": 2.0 * nb * nb * nw,
         "fock": 4.0 * nw * nw * nb * nb,
         "lambda_gemm": 2.0 * nmo * nb * nw,
+    }
+
+
+def kernel_bytes(nb, na, nw):
+    """Minimum HBM bytes per FP64 launch (operands read once, outputs written once)."""
+    return {
+        "half_transform": 8.0 * na * nb * nb + 8.0 * nw * na * nb,
+        "mo_transform": 8.0 * nw * na * nb + 8.0 * na * nw * nw,
+        "jao": 4.0 * na * nb * (nb + 1) + 8.0 * nw * nb * nb,
+        "kao": 8.0 * nw * na * nb + 8.0 * nw * nb * nb,
     }
 
 
@@ -316,6 +353,7 @@ def main():
             ent["tflops"] = round(kf[name] / (avg * 1e-3) / 1e12, 2)
         per_kernel[name] = ent
     dom = max(prof, key=lambda k: prof[k][1])
+    traffic, traffic_detail = traffic_of(dom, args.workload, args.prec)
     dom_avg_s = prof[dom][1] / prof[dom][0] * 1e-3
     achieved = kf.get(dom, 0.0) / dom_avg_s / 1e12
     builds_s = args.steps / el
@@ -342,7 +380,8 @@ def main():
                      "peak": PEAK[MODE_PEAK[args.prec]], "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK[MODE_PEAK[args.prec]], 4),
                      "mfma_products_per_fma": PRODUCTS[args.prec],
-                     "traffic": None},
+                     "traffic": traffic, "traffic_detail": traffic_detail,
+                     "algorithmic_bytes": kernel_bytes(nb, na, nw).get(dom)},
         "kernels": per_kernel,
         "tiles": ctx.tune_report().strip().splitlines(),
         "energy_at_C0": e_main,

@@ -20,8 +20,9 @@
 //
 // LDS layouts: FP64/FP32 slices are k-major ([k][x], x contiguous), which is
 // what the 16x16x4 fragments read (lane l takes x = l%16, k = l/16).  BF16
-// pieces are x-major with k contiguous ([x][k]), since a 16x16x32 fragment is
-// 8 consecutive k of one row per lane (x = l%16, k = 8*(l/16) .. +7).
+// pieces are x-major with k contiguous ([x][k], 16-byte chunks swizzled per
+// row), since a 16x16x32 fragment is 8 consecutive k of one row per lane
+// (x = l%16, k = 8*(l/16) .. +7).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -34,6 +35,8 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 // LDS pointer types: keep ds_read/ds_write (generic pointers would compile to
 // flat accesses, whose waits also drain the in-flight global prefetch).
 typedef __attribute__((address_space(3))) double lds_f64;
@@ -381,23 +384,16 @@ struct EngF32 {
 
 // ---------------------------------------------------------------------------
 // Split-BF16 engines.  NPC = pieces per operand (2 for x3, 3 for x6).
-__device__ __forceinline__ unsigned short bf16_bits(float x) {
-  // round to nearest even; operands here are finite
-  unsigned u = __float_as_uint(x);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ double bf16_value(unsigned short h) {
-  return (double)__uint_as_float((unsigned)h << 16);
-}
-
 template <int NPC>
 struct EngBF16 {
-  static constexpr int BK = 32, KV = 8, PAD = 8, CHUNK = 4;
-  static constexpr int ROW = BK + PAD;  // 16-bit elements per LDS row (80 B)
-  // one piece plane of BX rows; a stage holds NPC planes
+  static constexpr int BK = 32, KV = 8, CHUNK = 4;
+  // One piece plane of BX rows of 64 B (32 k); a stage holds NPC planes.  The
+  // four 16-byte chunks (8 k each) of row x sit at chunk c ^ ((x / 4) % 4), so
+  // sixteen consecutive rows at one chunk (a fragment read, or a wave's
+  // stores) cover all 64 banks, and so do 32 lanes over two chunks.
   template <int BX>
-  static constexpr int piece_bytes() { return BX * ROW * 2; }
+  static constexpr int piece_bytes() { return BX * BK * 2; }
+  __device__ static int chunk_off(int x, int c) { return x * (BK * 2) + ((c ^ ((x >> 2) & 3)) << 4); }
   template <int BX>
   static constexpr int stage_bytes() { return NPC * piece_bytes<BX>(); }
   template <class Cfg>
@@ -443,34 +439,50 @@ struct EngBF16 {
     }
   };
   // Splits each group of 8 consecutive k into NPC bf16 pieces and writes one
-  // 16-byte vector per piece.
+  // 16-byte vector per piece.  Pieces come from the packed round-to-nearest-
+  // even conversion of FP32 values: hi = bf16(f) with f = fp32(x), then the
+  // first residual x - hi = (x - f) + (f - hi) (both parts exact) rounded once
+  // to FP32 (about 2^-33 relative to x), whose further residuals are exact in
+  // FP32.  x6: hi + lo + lo2 holds x to about 2^-32; x3: hi + lo to 2^-17.
   template <int BX, class L>
   __device__ static void stash(lds_char* S, const L& ld, const typename L::type (&r)[L::RR], int kt) {
     static_assert(L::NP * KV <= L::RR, "groups of 8");
 #pragma unroll
     for (int p = 0; p < L::NP; ++p) {
-      u16x8 pc[NPC];
+      unsigned pc[NPC][KV / 2];
 #pragma unroll
-      for (int i = 0; i < KV; ++i) {
-        double x = ld.valid(p, i, kt) ? ld.val(r, p, i) : 0.0;
+      for (int i = 0; i < KV; i += 2) {
+        const double d0 = ld.valid(p, i, kt) ? ld.val(r, p, i) : 0.0;
+        const double d1 = ld.valid(p, i + 1, kt) ? ld.val(r, p, i + 1) : 0.0;
+        const float f0 = (float)d0, f1 = (float)d1;
+        const bf16x2 h = {(__bf16)f0, (__bf16)f1};
+        pc[0][i / 2] = __builtin_bit_cast(unsigned, h);
+        // x - hi = (x - f) + (f - hi): both parts exact, one FP32 rounding
+        float x0 = (float)(d0 - (double)f0) + (f0 - (float)h[0]);
+        float x1 = (float)(d1 - (double)f1) + (f1 - (float)h[1]);
 #pragma unroll
-        for (int s = 0; s < NPC; ++s) {
-          const unsigned short h = bf16_bits((float)x);
-          pc[s][i] = h;
-          x -= bf16_value(h);
+        for (int s = 1; s < NPC; ++s) {
+          const bf16x2 g = {(__bf16)x0, (__bf16)x1};
+          pc[s][i / 2] = __builtin_bit_cast(unsigned, g);
+          if (s + 1 < NPC) {
+            x0 -= (float)g[0];
+            x1 -= (float)g[1];
+          }
         }
       }
-      const int off = ld.xl(p) * ROW + ld.kl(p);
+      const int off = chunk_off(ld.xl(p), ld.kl(p) / KV);
 #pragma unroll
-      for (int s = 0; s < NPC; ++s)
-        *(lds_u16x8*)(S + s * piece_bytes<BX>() + off * 2) = pc[s];
+      for (int s = 0; s < NPC; ++s) {
+        const u32x4 v = {pc[s][0], pc[s][1], pc[s][2], pc[s][3]};
+        *(lds_u16x8*)(S + s * piece_bytes<BX>() + off) = __builtin_bit_cast(u16x8, v);
+      }
     }
   }
   // Rows 0..NI-1 of the wave's fragment block (NI = TM for the regular layout).
   template <class Cfg, int NI>
   __device__ static void mma_rows(const lds_char* SA, const lds_char* SB, Acc<Cfg>& acc, const WavePlan& w) {
     const int lane = threadIdx.x & 63;
-    const int xc = lane & 15, k0 = 8 * (lane >> 4);
+    const int xc = lane & 15, kc = lane >> 4;
     if constexpr (NI > 0) {
       bf16x8 a[NPC][NI], b[NPC][Cfg::TN];
 #pragma unroll
@@ -478,11 +490,11 @@ struct EngBF16 {
 #pragma unroll
         for (int i = 0; i < NI; ++i)
           a[s][i] = __builtin_bit_cast(bf16x8, *(const lds_u16x8*)(SA + s * piece_bytes<Cfg::BM>() +
-                                                                    ((w.wm0 + i * 16 + xc) * ROW + k0) * 2));
+                                                                    chunk_off(w.wm0 + i * 16 + xc, kc)));
 #pragma unroll
         for (int j = 0; j < Cfg::TN; ++j)
           b[s][j] = __builtin_bit_cast(bf16x8, *(const lds_u16x8*)(SB + s * piece_bytes<Cfg::BN>() +
-                                                                    ((w.wn0 + j * 16 + xc) * ROW + k0) * 2));
+                                                                    chunk_off(w.wn0 + j * 16 + xc, kc)));
       }
 #pragma unroll
       for (int i = 0; i < NI; ++i)
