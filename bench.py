@@ -383,6 +383,9 @@ def main():
                      "traffic": traffic, "traffic_detail": traffic_detail,
                      "algorithmic_bytes": kernel_bytes(nb, na, nw).get(dom)},
         "kernels": per_kernel,
+        "kernels_note": ("avg_ms is event time on the stream each kernel runs on; jk_mo_partial, "
+                         "jk_mo_reduce, energy and the H C_Omega small_gemm run on the side stream "
+                         "overlapped with the main chain, so theirs is overlapped wall time"),
         "tiles": ctx.tune_report().strip().splitlines(),
         "energy_at_C0": e_main,
     }

@@ -239,9 +239,20 @@ class Context:
 
     # ---- one build: every hot-path step once -----------------------------
     def build(self, b, C, H, occ, pair_of, n_pairs, n_cwo, prec=FP64, functional=PNOF7, out=None):
-        """Transform, J/K (MO), J^q/K^q (AO), energy, Lagrangian and gradient.
-        `out` (a dict from a previous call with the same shapes) is reused to
-        avoid allocations."""
+        """Transform, J/K (MO), J^q/K^q (AO), energy, Lagrangian and gradient in
+        one rif_build call.  `out` (a dict from a previous call with the same
+        shapes) is reused to avoid allocations."""
+        n_aux, n_bf, _ = b.shape
+        if out is None:
+            out = self.outputs(n_bf, n_aux, n_pairs, n_cwo, C.shape[1], prec, b.device)
+        inp = {"b": b, "C": C, "H": H, "occ": occ, "pair_of": pair_of}
+        inst = self.instance(inp, n_pairs, n_cwo, out, prec)
+        self._chk(self.lib.rif_build(self.h, ctypes.byref(inst), prec, functional))
+        return out
+
+    def build_steps(self, b, C, H, occ, pair_of, n_pairs, n_cwo, prec=FP64, functional=PNOF7, out=None):
+        """The same build as four ABI calls (rif_transform, rif_jk_mo,
+        rif_jk_ao_per_mo, pnof_energy_grad) on one stream."""
         n_omega = n_pairs * (1 + n_cwo)
         o = out if out is not None else {}
         o["b_half"], o["b_mo"], o["d"] = self.transform(b, C, n_omega, prec, o.get("b_half"),

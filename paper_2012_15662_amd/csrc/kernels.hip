@@ -440,6 +440,7 @@ __device__ void jkp_tile(const JkArgs& a, long t, char*) {
   const int p = (int)(pq / nw), q = (int)(pq - (long)p * nw);
   const IOT<P>* bmo = (const IOT<P>*)a.bmo;
   double sj = 0.0, sk = 0.0;
+#pragma unroll 8
   for (int l = l0; l < l1; ++l) {
     const double v = (double)bmo[(long)l * w2 + pq];
     sk = fma(v, v, sk);
@@ -670,7 +671,7 @@ __device__ __forceinline__ int find_owner(const long* __restrict__ off, int n, l
 // also carry the work-list search) are left to the compiler.
 template <int P, class Cfg>
 constexpr int gemm_wpe() {
-  return Cfg::NT == 512 ? (P == kF64 ? 4 : 2) : 1;
+  return Cfg::NT == 1024 ? 4 : Cfg::NT == 512 ? (P == kF64 ? 4 : 2) : 1;
 }
 #define GEMM_SMEM smem_bytes<typename EngineOf<P>::type, Cfg>()
 #define GEMM_WPE (gemm_wpe<P, Cfg>())
@@ -700,8 +701,8 @@ template <> struct Vars<16> {  // FP64 / FP32 engines: 8 waves (measured ~10% ov
   using V2 = TileCfg<128, 64, 16, 32, 32>;
   using V3 = TileCfg<64, 128, 16, 32, 32>;
 };
-template <> struct Vars<32> {  // BF16 split engines: smaller wave tiles (three accumulator sets)
-  using V0 = TileCfg<128, 128, 32, 64, 32>;
+template <> struct Vars<32> {  // BF16 split engines: 16-wave 128x128 (four waves per SIMD), then 8/4-wave tiles
+  using V0 = TileCfg<128, 128, 32, 32, 32>;
   using V1 = TileCfg<64, 64, 32, 32, 32>;
   using V2 = TileCfg<128, 64, 32, 64, 32>;
   using V3 = TileCfg<64, 128, 32, 32, 64>;
@@ -975,6 +976,71 @@ rif_status op_energy_grad(rif_ctx* c, int prec, int functional, int nb, int nmo,
   in.Jn = (void*)Jn; in.Kn = (void*)Kn; in.energy = energy; in.lambda = lambda; in.grad = grad;
   const BuildArgs A = make_build_args(pl, in, functional, (char*)c->ws, c->dflag);
   RIF_PREC_SWITCH(prec, run_energy_grad<P>(c, A))
+}
+
+// ---- one whole build (rif_build) ------------------------------------------
+// The main stream runs the chain that carries the time (half, mo, J^q, K^q,
+// coefficients, Fock, lambda, G).  H C_Omega, the J/K-MO reduction and the
+// energy feed neither of their neighbours, so they run on the side stream:
+//   main: fork | half  mo  [e_mo] J^q  K^q  (wait e_side) coef [e_coef]  fock fred lambda grad  (wait e_energy)
+//   side:      | H C_Omega  (wait e_mo) jk_mo [e_side]  (wait e_coef) energy [e_energy]
+// Every kernel and reduction order is the same as in the one-stream order.
+struct OnStream {  // launches of the enclosed steps go to `s`
+  rif_ctx* c;
+  hipStream_t saved;
+  OnStream(rif_ctx* c_, hipStream_t s) : c(c_), saved(c_->stream) { c->stream = s; }
+  ~OnStream() { c->stream = saved; }
+};
+
+template <int P>
+static rif_status run_build(rif_ctx* c, const BuildArgs& A) {
+  hipStream_t main = c->stream, side = c->side;
+  hipEvent_t e_fork = c->ev[0], e_mo = c->ev[1], e_side = c->ev[2], e_coef = c->ev[3], e_energy = c->ev[4];
+  rif_status st;
+  auto hip = [&](hipError_t e) { return e == hipSuccess ? RIF_OK : fail(c, RIF_EHIP, "stream fork/join failed"); };
+  if ((st = hip(hipEventRecord(e_fork, main))) || (st = hip(hipStreamWaitEvent(side, e_fork, 0)))) return st;
+  {
+    OnStream on(c, side);
+    if ((st = step1_gemm(c, A.hc))) return st;
+  }
+  if ((st = step_half<P>(c, A.half)) || (st = step_mo<P>(c, A.mo))) return st;
+  if ((st = hip(hipEventRecord(e_mo, main)))) return st;
+  {
+    OnStream on(c, side);
+    if ((st = hip(hipStreamWaitEvent(side, e_mo, 0))) || (st = step1_jk<P>(c, A.jk)) ||
+        (st = hip(hipEventRecord(e_side, side))))
+      return st;
+  }
+  if ((st = step_jao<P>(c, A.jao)) || (st = step_kao<P>(c, A.kao))) return st;
+  if ((st = hip(hipStreamWaitEvent(main, e_side, 0))) || (st = step1_coef(c, A.coef)) ||
+      (st = hip(hipEventRecord(e_coef, main))))
+    return st;
+  {
+    OnStream on(c, side);
+    if ((st = hip(hipStreamWaitEvent(side, e_coef, 0))) || (st = step1_energy(c, A.energy)) ||
+        (st = hip(hipEventRecord(e_energy, side))))
+      return st;
+  }
+  if ((st = step_fock<P>(c, A.fock)) || (st = step1_fred(c, A.fred)) || (st = step1_gemm(c, A.lam)) ||
+      (st = step1_grad(c, A.grad)))
+    return st;
+  return hip(hipStreamWaitEvent(main, e_energy, 0));
+}
+
+rif_status op_build(rif_ctx* c, int prec, int functional, const rif_instance& in) {
+  if (!prec_ok(prec)) return fail(c, RIF_ENOTSUP, "precision mode not available");
+  if (!c->side) {
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess)
+      return fail(c, RIF_EHIP, "side stream creation failed");
+    for (auto& e : c->ev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+        return fail(c, RIF_EHIP, "event creation failed");
+  }
+  const Plan pl(in.n_bf, in.n_aux, in.n_pairs, in.n_cwo, in.n_mo);
+  rif_status st = ws_reserve(c, pl.bytes);
+  if (st) return st;
+  const BuildArgs A = make_build_args(pl, in, functional, (char*)c->ws, c->dflag);
+  RIF_PREC_SWITCH(prec, run_build<P>(c, A))
 }
 
 // ---------------------------------------------------------------------------

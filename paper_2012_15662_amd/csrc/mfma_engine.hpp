@@ -36,12 +36,14 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 // LDS pointer types: keep ds_read/ds_write (generic pointers would compile to
 // flat accesses, whose waits also drain the in-flight global prefetch).
 typedef __attribute__((address_space(3))) double lds_f64;
 typedef __attribute__((address_space(3))) float lds_f32;
 typedef __attribute__((address_space(3))) u16x8 lds_u16x8;
+typedef __attribute__((address_space(3))) u32x2 lds_u32x2;
 typedef __attribute__((address_space(3))) char lds_char;
 
 enum Prec : int { kF64 = 0, kF32 = 1, kBF16x3 = 2, kBF16x6 = 3 };
@@ -386,7 +388,7 @@ struct EngF32 {
 // Split-BF16 engines.  NPC = pieces per operand (2 for x3, 3 for x6).
 template <int NPC>
 struct EngBF16 {
-  static constexpr int BK = 32, KV = 8, CHUNK = 4;
+  static constexpr int BK = 32, KV = 4, CHUNK = 4;
   // One piece plane of BX rows of 64 B (32 k); a stage holds NPC planes.  The
   // four 16-byte chunks (8 k each) of row x sit at chunk c ^ ((x / 4) % 4), so
   // sixteen consecutive rows at one chunk (a fragment read, or a wave's
@@ -438,28 +440,42 @@ struct EngBF16 {
           }
     }
   };
-  // Splits each group of 8 consecutive k into NPC bf16 pieces and writes one
-  // 16-byte vector per piece.  Pieces come from the packed round-to-nearest-
-  // even conversion of FP32 values: hi = bf16(f) with f = fp32(x), then the
-  // first residual x - hi = (x - f) + (f - hi) (both parts exact) rounded once
-  // to FP32 (about 2^-33 relative to x), whose further residuals are exact in
-  // FP32.  x6: hi + lo + lo2 holds x to about 2^-32; x3: hi + lo to 2^-17.
+  // Splits each group of KV = 4 consecutive k into NPC bf16 pieces and writes
+  // one 8-byte vector per piece.  Pieces come from the packed round-to-
+  // nearest-even conversion of FP32 values: hi = bf16(f) with f = fp32(x), then
+  // the first residual x - hi = (x - f) + (f - hi) (both parts exact) rounded
+  // once to FP32 (about 2^-33 relative to x), whose further residuals are exact
+  // in FP32.  x6: hi + lo + lo2 holds x to about 2^-32; x3: hi + lo to 2^-17.
   template <int BX, class L>
   __device__ static void stash(lds_char* S, const L& ld, const typename L::type (&r)[L::RR], int kt) {
-    static_assert(L::NP * KV <= L::RR, "groups of 8");
+    static_assert(L::NP * KV <= L::RR, "groups of KV");
 #pragma unroll
     for (int p = 0; p < L::NP; ++p) {
       unsigned pc[NPC][KV / 2];
 #pragma unroll
       for (int i = 0; i < KV; i += 2) {
-        const double d0 = ld.valid(p, i, kt) ? ld.val(r, p, i) : 0.0;
-        const double d1 = ld.valid(p, i + 1, kt) ? ld.val(r, p, i + 1) : 0.0;
-        const float f0 = (float)d0, f1 = (float)d1;
-        const bf16x2 h = {(__bf16)f0, (__bf16)f1};
-        pc[0][i / 2] = __builtin_bit_cast(unsigned, h);
-        // x - hi = (x - f) + (f - hi): both parts exact, one FP32 rounding
-        float x0 = (float)(d0 - (double)f0) + (f0 - (float)h[0]);
-        float x1 = (float)(d1 - (double)f1) + (f1 - (float)h[1]);
+        float x0, x1;
+        if constexpr (std::is_same<typename L::type, float>::value) {
+          // FP32 operand: x is its own FP32 value, so every residual is exact in FP32
+          x0 = ld.valid(p, i, kt) ? (float)ld.val(r, p, i) : 0.f;
+          x1 = ld.valid(p, i + 1, kt) ? (float)ld.val(r, p, i + 1) : 0.f;
+          const bf16x2 h = {(__bf16)x0, (__bf16)x1};
+          pc[0][i / 2] = __builtin_bit_cast(unsigned, h);
+          x0 -= (float)h[0];
+          x1 -= (float)h[1];
+        } else {
+          const double d0 = ld.valid(p, i, kt) ? ld.val(r, p, i) : 0.0;
+          const double d1 = ld.valid(p, i + 1, kt) ? ld.val(r, p, i + 1) : 0.0;
+          float f0 = (float)d0, f1 = (float)d1;
+          // keep the FP32 rounding visible: otherwise the two conversions fold into
+          // one emulated FP64 -> bf16 rounding (no instruction is emitted here)
+          asm("" : "+v"(f0), "+v"(f1));
+          const bf16x2 h = {(__bf16)f0, (__bf16)f1};
+          pc[0][i / 2] = __builtin_bit_cast(unsigned, h);
+          // x - hi = (x - f) + (f - hi): both parts exact, one FP32 rounding
+          x0 = (float)(d0 - (double)f0) + (f0 - (float)h[0]);
+          x1 = (float)(d1 - (double)f1) + (f1 - (float)h[1]);
+        }
 #pragma unroll
         for (int s = 1; s < NPC; ++s) {
           const bf16x2 g = {(__bf16)x0, (__bf16)x1};
@@ -470,47 +486,51 @@ struct EngBF16 {
           }
         }
       }
-      const int off = chunk_off(ld.xl(p), ld.kl(p) / KV);
+      const int k = ld.kl(p);
+      const int off = chunk_off(ld.xl(p), k / 8) + (k % 8) * 2;
 #pragma unroll
       for (int s = 0; s < NPC; ++s) {
-        const u32x4 v = {pc[s][0], pc[s][1], pc[s][2], pc[s][3]};
-        *(lds_u16x8*)(S + s * piece_bytes<BX>() + off) = __builtin_bit_cast(u16x8, v);
+        const u32x2 v = {pc[s][0], pc[s][1]};
+        *(lds_u32x2*)(S + s * piece_bytes<BX>() + off) = v;
       }
     }
   }
   // Rows 0..NI-1 of the wave's fragment block (NI = TM for the regular layout).
+  // The B pieces of the wave's TN columns stay in registers; the A pieces are
+  // loaded one fragment row at a time (keeps the 16-wave tiles within 128 VGPRs).
   template <class Cfg, int NI>
   __device__ static void mma_rows(const lds_char* SA, const lds_char* SB, Acc<Cfg>& acc, const WavePlan& w) {
     const int lane = threadIdx.x & 63;
     const int xc = lane & 15, kc = lane >> 4;
     if constexpr (NI > 0) {
-      bf16x8 a[NPC][NI], b[NPC][Cfg::TN];
+      bf16x8 b[NPC][Cfg::TN];
 #pragma unroll
-      for (int s = 0; s < NPC; ++s) {
-#pragma unroll
-        for (int i = 0; i < NI; ++i)
-          a[s][i] = __builtin_bit_cast(bf16x8, *(const lds_u16x8*)(SA + s * piece_bytes<Cfg::BM>() +
-                                                                    chunk_off(w.wm0 + i * 16 + xc, kc)));
+      for (int s = 0; s < NPC; ++s)
 #pragma unroll
         for (int j = 0; j < Cfg::TN; ++j)
           b[s][j] = __builtin_bit_cast(bf16x8, *(const lds_u16x8*)(SB + s * piece_bytes<Cfg::BN>() +
                                                                     chunk_off(w.wn0 + j * 16 + xc, kc)));
-      }
 #pragma unroll
-      for (int i = 0; i < NI; ++i)
+      for (int i = 0; i < NI; ++i) {
+        bf16x8 a[NPC];
+#pragma unroll
+        for (int s = 0; s < NPC; ++s)
+          a[s] = __builtin_bit_cast(bf16x8, *(const lds_u16x8*)(SA + s * piece_bytes<Cfg::BM>() +
+                                                                 chunk_off(w.wm0 + i * 16 + xc, kc)));
 #pragma unroll
         for (int j = 0; j < Cfg::TN; ++j) {
           f4 x = acc.xx[i][j];
           if constexpr (NPC == 3) {
-            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], x, 0, 0, 0);
-            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], x, 0, 0, 0);
-            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], x, 0, 0, 0);
+            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2][j], x, 0, 0, 0);
+            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1][j], x, 0, 0, 0);
+            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0][j], x, 0, 0, 0);
           }
-          x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], x, 0, 0, 0);
-          x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], x, 0, 0, 0);
+          x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1][j], x, 0, 0, 0);
+          x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0][j], x, 0, 0, 0);
           acc.xx[i][j] = x;
-          acc.hh[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc.hh[i][j], 0, 0, 0);
+          acc.hh[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0][j], acc.hh[i][j], 0, 0, 0);
         }
+      }
     }
   }
   template <class Cfg>
@@ -558,8 +578,12 @@ __device__ __forceinline__ void gemm_mainloop_with(LA& la, LB& lb, int nk, typen
     const int cur = kt & 1;
     const bool more = kt + 1 < nk;
     if (more) {
+      // issue the next slice's global loads ahead of other waves' MFMAs, so they
+      // are in flight for the whole slice
+      __builtin_amdgcn_s_setprio(1);
       la.fetch(kt + 1, ra);
       if (!b_is_a) lb.fetch(kt + 1, rb);
+      __builtin_amdgcn_s_setprio(0);
     }
     mma(As[cur], Bs[cur], acc);
     if ((kt + 1) % E::CHUNK == 0) acc.flush();

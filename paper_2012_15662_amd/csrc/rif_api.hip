@@ -154,6 +154,12 @@ void rif_destroy(rif_ctx* c) {
   for (auto e : c->pool) hipEventDestroy(e);
   if (c->ws) hipFree(c->ws);
   if (c->dflag) hipFree(c->dflag);
+  if (c->side) {
+    hipStreamSynchronize(c->side);
+    hipStreamDestroy(c->side);
+  }
+  for (auto e : c->ev)
+    if (e) hipEventDestroy(e);
   if (c->own_stream) hipStreamDestroy(c->own_stream);
   delete c;
 }
@@ -257,14 +263,9 @@ rif_status rif_build(rif_ctx* c, const rif_instance* in, rif_prec prec, rif_func
   if (!c) return RIF_EINVAL;
   rif_status st = check_instance(c, in, "rif_build");
   if (st) return st;
-  const int nw = in->n_pairs * (1 + in->n_cwo);
-  if ((st = rif_transform(c, in->n_bf, in->n_aux, nw, in->n_mo, in->b, in->C, prec, in->b_half, in->b_mo, in->d)))
-    return st;
-  if ((st = rif_jk_mo(c, in->n_aux, nw, in->b_mo, in->d, prec, in->J, in->K))) return st;
-  if ((st = rif_jk_ao_per_mo(c, in->n_bf, in->n_aux, nw, in->b, in->b_half, in->d, prec, in->Jn, in->Kn)))
-    return st;
-  return pnof_energy_grad(c, fn, in->n_bf, in->n_mo, in->n_pairs, in->n_cwo, in->pair_of, in->H, in->C, in->occ,
-                          in->J, in->K, in->Jn, in->Kn, prec, in->energy, in->lambda, in->grad);
+  if (fn != RIF_PNOF7 && fn != RIF_PNOF5) return fail(c, RIF_EINVAL, "rif_build: unknown functional");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  return op_build(c, (int)prec, (int)fn, *in);
 }
 
 struct rif_batch {

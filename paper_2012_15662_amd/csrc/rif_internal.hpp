@@ -31,6 +31,10 @@ struct rif_ctx {
   int force_variant = -1;     // >= 0: use this variant everywhere (clamped per kernel)
   struct Tune { std::string key; int variant; std::vector<float> ms; };
   std::vector<Tune> tune;
+  // second stream for the steps of a build that feed neither neighbour
+  // (default priority; created on first use) and the fork/join events
+  hipStream_t side = nullptr;
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace rif {
@@ -100,6 +104,10 @@ rif_status op_mlp_backward(rif_ctx* c, int nrows, const float* X, const float* M
                            double* loss);
 rif_status op_adam(rif_ctx* c, int n, float* theta, const float* grad, float* m, float* v, int step, float lr,
                    float b1, float b2, float eps);
+
+// a2..a8 of one molecule in one call (inst already validated), with the small
+// independent steps on the context's side stream.
+rif_status op_build(rif_ctx* c, int prec, int functional, const rif_instance& in);
 
 // Batched builds (inst already validated); the handle is opaque to the ABI layer.
 rif_status op_batch_create(rif_ctx* c, int prec, int functional, int n, const rif_instance* inst, void** out);

@@ -118,6 +118,21 @@ def test_deterministic_bitwise(ctx):
         assert np.array_equal(a[k], host(v)), k
 
 
+@pytest.mark.parametrize("prec", [0, 3])
+def test_build_equals_the_four_abi_steps(ctx, prec):
+    """rif_build (two streams) and the four step calls (one stream) run the same
+    kernels in the same reduction orders: identical results, bit for bit."""
+    inst = synth.make_instance(139, 157, 9, 3, 24)
+    t = to_dev(inst)
+    args = (t["b"], t["C"], t["H"], t["occ"], t["pair_of"], inst.n_pairs, inst.n_cwo)
+    o1 = ctx.build(*args, prec=prec)
+    a = {k: host(v).copy() for k, v in o1.items()}
+    o2 = ctx.build_steps(*args, prec=prec)
+    ctx.sync()
+    for k, v in o2.items():
+        assert np.array_equal(a[k], host(v)), k
+
+
 def test_invalid_occupations_reported(ctx):
     import torch
     import paper_2012_15662_amd as rif

@@ -64,6 +64,23 @@ def test_cyclohexane_like(ctx, mode):
     assert np.array_equal(Jn, Jn.transpose(0, 2, 1))
 
 
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_every_tile_variant(ctx, mode, variant):
+    """Each tile shape of every MFMA kernel in each reduced-precision mode, on a
+    case with ragged tails in all dimensions (variant 0 of the split modes is
+    the 16-wave 128x128 tile)."""
+    inst = synth.make_instance(139, 157, 9, 3, 40 + variant)
+    ctx.set_tile_variant(variant)
+    try:
+        e, _, _ = errors(ctx, inst, MODES[mode])
+    finally:
+        ctx.set_tile_variant(-1)
+    print(mode, "variant", variant, " ".join(f"{k}={v:.2e}" for k, v in e.items()), flush=True)
+    te, tg, tj = TOL[mode]
+    assert e["dE"] < te and e["grad"] < tg and e["Jn"] < tj and e["Kn"] < tj
+
+
 def test_fp16x3_not_available(ctx):
     import paper_2012_15662_amd as rif
     inst = synth.make_instance(20, 30, 2, 1, 3)
