@@ -46,6 +46,20 @@ template <int P, class T, int BX, int NT>
 using XCS = XCSrc<T, BX, EngineOf<P>::type::BK, NT, EngineOf<P>::type::KV>;
 template <int P, class T, int BX, int NT>
 using KCS = KCSrc<T, BX, EngineOf<P>::type::BK, NT, EngineOf<P>::type::KV>;
+// pieces per operand in the split-BF16 modes (0: the mode does not split)
+template <int P>
+constexpr int kPieces = P == kBF16x3 ? 2 : P == kBF16x6 ? 3 : 0;
+template <int P, int BX, int NT>
+using PCS = PieceSrc<kPieces<P> ? kPieces<P> : 1, BX, 32, NT>;
+// Which split-mode operands come from piece planes (measured): C_Omega in the
+// MO transform in both modes; C_Omega in the half transform and d in J^q only
+// with two pieces (with three, the 16-wave tiles spill under the 128-VGPR cap
+// and staging the FP64 values directly is faster).
+template <int P>
+constexpr bool kPlanesMo = kPieces<P> > 0;
+template <int P>
+constexpr bool kPlanesHalfJao = kPieces<P> == 2;
+constexpr int round32(int k) { return (k + 31) / 32 * 32; }
 
 // ---------------------------------------------------------------------------
 // Per-step argument blocks.  Each step is written once as a tile function
@@ -54,9 +68,16 @@ using KCS = KCSrc<T, BX, EngineOf<P>::type::BK, NT, EngineOf<P>::type::KV>;
 // work-list of tiles that spans many molecules (rif_batch_*).  The same tile
 // code and tile shape give bitwise-identical results in both.
 
-struct HalfArgs { int nb, nw, nmo; long nr; const double* b; const double* C; void* bh; };
-struct MoArgs { int nb, na, nw, nmo; const void* bh; const double* C; void* bmo; double* d; };
-struct JaoArgs { int nb, na, nw; const double* b; const double* d; void* Jn; };
+// Split-BF16 modes read C_Omega (half, mo) and d (J^q) as piece planes made once
+// per call by the psplit step (PSplitArgs): row q of C_Omega^T or d^T, k
+// contiguous, row length `ld`, planes `ps` elements apart.
+struct Planes { const unsigned short* p; long ps; int ld; };
+struct HalfArgs { int nb, nw, nmo; long nr; const double* b; const double* C; void* bh; Planes Cs; };
+struct MoArgs { int nb, na, nw, nmo; const void* bh; const double* C; void* bmo; double* d; Planes Cs; };
+struct JaoArgs { int nb, na, nw; const double* b; const double* d; void* Jn; Planes Ds; };
+// Pre-split of X (element (x, k) at X[k*sk + x]) into NPC bf16 planes
+// out[s*ps + x*ld + k], zero from k = K up to ld.
+struct PSplitArgs { const double* X; long sk; int nx, K, ld; unsigned short* out; long ps; };
 struct KaoArgs { int nb, na, nw; const void* bh; void* Kn; };
 // Split over k: out + s*ostride receives the partial product over
 // k in [s*kc, min(K, (s+1)*kc)), s < ksplit.
@@ -110,8 +131,12 @@ __device__ void half_tile(const HalfArgs& a, long t, char* smem) {
   const int nb = a.nb, nw = a.nw;
   const long nr = a.nr, B2 = (long)nb * nb;
   IOT<P>* bh = (IOT<P>*)a.bh;
-  XCS<P, double, Cfg::BM, Cfg::NT> la;
-  la.init(a.C, a.nmo, nb, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
+  // A: C_Omega^T (x = q, k = mu), from piece planes in the split modes
+  typename std::conditional<kPlanesHalfJao<P>, PCS<P, Cfg::BM, Cfg::NT>, XCS<P, double, Cfg::BM, Cfg::NT>>::type la;
+  if constexpr (kPlanesHalfJao<P>)
+    la.init(a.Cs.p, a.Cs.ps, a.Cs.ld, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
+  else
+    la.init(a.C, a.nmo, nb, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
   // column r = l*n_bf + nu of b[l][mu][nu] at k = mu: x-contiguous within a slab
   XCS<P, double, Cfg::BN, Cfg::NT> lb;
   lb.init(a.b, nb, nb, [&](int x, long& o) {
@@ -153,8 +178,12 @@ __device__ void mo_tile(const MoArgs& a, long t, char* smem) {
     const long l = s / nw, p = s - l * nw;
     return bh + p * AB + l * nb;
   }, bh, nb);
-  XCS<P, double, Cfg::BN, Cfg::NT> lb;
-  lb.init(a.C, a.nmo, nb, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
+  // B: C_Omega (x = q, k = nu), from piece planes in the split modes
+  typename std::conditional<kPlanesMo<P>, PCS<P, Cfg::BN, Cfg::NT>, XCS<P, double, Cfg::BN, Cfg::NT>>::type lb;
+  if constexpr (kPlanesMo<P>)
+    lb.init(a.Cs.p, a.Cs.ps, a.Cs.ld, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
+  else
+    lb.init(a.C, a.nmo, nb, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
   typename E::template Acc<Cfg> acc;
   gemm_mainloop<E, Cfg>(la, lb, cdiv(nb, E::BK), acc, smem);
   acc.for_each([&](int m, int n, double v) {
@@ -212,8 +241,12 @@ __device__ void jao_tile(const JaoArgs& a, long t, char* smem) {
   const int mu0 = bi * TMU, nu0 = bj * TNU;
   const int q0 = qt * Cfg::BM;
   const long B2 = (long)nb * nb;
-  XCS<P, double, Cfg::BM, Cfg::NT> la;
-  la.init(a.d, nw, na, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
+  // A: d^T (x = q, k = l), from piece planes in the split modes
+  typename std::conditional<kPlanesHalfJao<P>, PCS<P, Cfg::BM, Cfg::NT>, XCS<P, double, Cfg::BM, Cfg::NT>>::type la;
+  if constexpr (kPlanesHalfJao<P>)
+    la.init(a.Ds.p, a.Ds.ps, a.Ds.ld, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
+  else
+    la.init(a.d, nw, na, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
   XCS<P, double, Cfg::BN, Cfg::NT> lb;
   lb.init(a.b, B2, na, [&](int x, long& o) {
     const int mu = mu0 + x / TNU, nu = nu0 + x % TNU;
@@ -420,6 +453,26 @@ __device__ void fock_tile(const FockArgs& a, long t, char* smem) {
   acc.for_each([&](int m, int n, double v) {
     if (mu0 + m < nb && q0 + n < nw) Y[(long)(mu0 + m) * nw + q0 + n] = v;
   });
+}
+
+// ---- pre-split of the small reused operands (split-BF16 modes) --------------
+// One thread per pair of k of one row; same split arithmetic as the staging
+// path (split_pair), so a pre-split operand gives the same pieces.
+template <int P, class Cfg>
+__host__ __device__ inline long psplit_tiles(const PSplitArgs& a) { return cdiv((long)a.nx * (a.ld / 2), 256); }
+template <int P, class Cfg>
+__device__ void psplit_tile(const PSplitArgs& a, long t, char*) {
+  constexpr int NPC = kPieces<P> ? kPieces<P> : 1;
+  const long i = t * 256 + threadIdx.x;
+  const int hl = a.ld / 2;
+  if (i >= (long)a.nx * hl) return;
+  const int x = (int)(i / hl), k = 2 * (int)(i - (long)x * hl);
+  const double d0 = k < a.K ? a.X[(long)k * a.sk + x] : 0.0;
+  const double d1 = k + 1 < a.K ? a.X[(long)(k + 1) * a.sk + x] : 0.0;
+  unsigned pc[NPC];
+  split_pair<NPC>(d0, d1, pc);
+#pragma unroll
+  for (int s = 0; s < NPC; ++s) *(unsigned*)(a.out + s * a.ps + (long)x * a.ld + k) = pc[s];
 }
 
 // ---- element-wise and reduction steps (256-thread tiles) -------------------
@@ -687,6 +740,7 @@ RIF_STEP_KERNELS(coef, CoefArgs, 256 * 8, 256, false, 1)
 RIF_STEP_KERNELS(energy, EnergyArgs, kEnergySmem, kEnergyThreads, false, 1)
 RIF_STEP_KERNELS(fred, FockRedArgs, 16, 256, false, 1)
 RIF_STEP_KERNELS(grad, GradArgs, 16, 256, false, 1)
+RIF_STEP_KERNELS(psplit, PSplitArgs, 16, 256, false, 1)
 
 // ---------------------------------------------------------------------------
 // Launchers.  Each GEMM-shaped step exists in four tile variants per mode:
@@ -809,6 +863,16 @@ RIF_FIXED_STEP(energy, EnergyArgs, "energy", kF64, CfgEnergy)
 RIF_FIXED_STEP(fred, FockRedArgs, "fock_reduce", kF64, Cfg256)
 RIF_FIXED_STEP(grad, GradArgs, "grad", kF64, Cfg256)
 template <int P>
+static rif_status step_psplit(rif_ctx* c, const PSplitArgs& a) {
+  if constexpr (kPieces<P> == 0) {
+    return RIF_OK;
+  } else {
+    ProfScope ps(c, "presplit");
+    hipLaunchKernelGGL((k_psplit<P, Cfg256>), dim3((unsigned)psplit_tiles<P, Cfg256>(a)), dim3(256), 0, c->stream, a);
+    return check_launch(c, "presplit");
+  }
+}
+template <int P>
 static rif_status step1_jk(rif_ctx* c, const JkArgs& a) {
   rif_status st;
   {
@@ -825,7 +889,7 @@ static rif_status step1_jk(rif_ctx* c, const JkArgs& a) {
 struct Plan {
   int nb, na, nw, nmo, npairs, ncwo;
   int jk_nsplit, fock_nsplit, fock_per, nparts, hc_split, lam_split, small_kc;
-  size_t o_part, o_hcp, o_hc, o_a, o_b, o_yp, o_y, o_ep, o_lp, bytes;
+  size_t o_part, o_hcp, o_hc, o_a, o_b, o_yp, o_y, o_ep, o_lp, o_cs, o_ds, bytes;
   Plan(int nb_, int na_, int npairs_, int ncwo_, int nmo_) {
     nb = nb_; na = na_; npairs = npairs_; ncwo = ncwo_; nmo = nmo_;
     nw = npairs * (1 + ncwo);
@@ -859,12 +923,15 @@ struct Plan {
     o_y = cv.take<double>((size_t)nb * nw);
     o_ep = cv.take<double>((size_t)nparts);
     o_lp = cv.take<double>((size_t)lam_split * nmo * nw);
+    o_cs = cv.take<unsigned short>((size_t)3 * nw * round32(nb));   // C_Omega^T pieces (split modes)
+    o_ds = cv.take<unsigned short>((size_t)3 * nw * round32(na));   // d^T pieces (split modes)
     bytes = cv.off;
   }
 };
 
 // All argument blocks of one build of one molecule, workspace at `ws`.
 struct BuildArgs {
+  PSplitArgs psc, psd;
   HalfArgs half; MoArgs mo; JkArgs jk; JaoArgs jao; KaoArgs kao;
   GemmArgs hc; CoefArgs coef; EnergyArgs energy; FockArgs fock; FockRedArgs fred; GemmArgs lam; GradArgs grad;
 };
@@ -880,10 +947,16 @@ static BuildArgs make_build_args(const Plan& pl, const rif_instance& in, int fun
   double* Y = (double*)(ws + pl.o_y);
   double* Ep = (double*)(ws + pl.o_ep);
   double* Lp = (double*)(ws + pl.o_lp);
-  A.half = HalfArgs{nb, nw, nmo, (long)na * nb, in.b, in.C, in.b_half};
-  A.mo = MoArgs{nb, na, nw, nmo, in.b_half, in.C, in.b_mo, in.d};
+  unsigned short* Cs = (unsigned short*)(ws + pl.o_cs);
+  unsigned short* Ds = (unsigned short*)(ws + pl.o_ds);
+  const int lc = round32(nb), ldd = round32(na);
+  A.psc = PSplitArgs{in.C, (long)nmo, nw, nb, lc, Cs, (long)nw * lc};
+  A.psd = PSplitArgs{in.d, (long)nw, nw, na, ldd, Ds, (long)nw * ldd};
+  const Planes cs{Cs, (long)nw * lc, lc}, ds{Ds, (long)nw * ldd, ldd};
+  A.half = HalfArgs{nb, nw, nmo, (long)na * nb, in.b, in.C, in.b_half, cs};
+  A.mo = MoArgs{nb, na, nw, nmo, in.b_half, in.C, in.b_mo, in.d, cs};
   A.jk = JkArgs{na, nw, pl.jk_nsplit, in.b_mo, in.d, part, in.J, in.K};
-  A.jao = JaoArgs{nb, na, nw, in.b, in.d, in.Jn};
+  A.jao = JaoArgs{nb, na, nw, in.b, in.d, in.Jn, ds};
   A.kao = KaoArgs{nb, na, nw, in.b_half, in.Kn};
   A.hc = GemmArgs{nb, nw, nb, in.H, (long)nb, in.C, (long)nmo, HCp, (long)nw,
                   pl.hc_split, pl.small_kc, (long)nb * nw};
@@ -900,15 +973,15 @@ static BuildArgs make_build_args(const Plan& pl, const rif_instance& in, int fun
 }
 
 template <int P>
-static rif_status run_transform(rif_ctx* c, const HalfArgs& h, const MoArgs& m) {
-  rif_status st = step_half<P>(c, h);
-  if (st) return st;
+static rif_status run_transform(rif_ctx* c, const PSplitArgs& ps, const HalfArgs& h, const MoArgs& m) {
+  rif_status st = step_psplit<P>(c, ps);
+  if (st || (st = step_half<P>(c, h))) return st;
   return step_mo<P>(c, m);
 }
 template <int P>
-static rif_status run_jk_ao(rif_ctx* c, const JaoArgs& j, const KaoArgs& k) {
-  rif_status st = step_jao<P>(c, j);
-  if (st) return st;
+static rif_status run_jk_ao(rif_ctx* c, const PSplitArgs& ps, const JaoArgs& j, const KaoArgs& k) {
+  rif_status st = kPlanesHalfJao<P> ? step_psplit<P>(c, ps) : RIF_OK;
+  if (st || (st = step_jao<P>(c, j))) return st;
   return step_kao<P>(c, k);
 }
 template <int P>
@@ -937,9 +1010,18 @@ static bool prec_ok(int prec) { return prec >= kF64 && prec <= kBF16x6; }
 
 rif_status op_transform(rif_ctx* c, int prec, int nb, int na, int nw, int nmo, const double* b, const double* C,
                         void* bh, void* bmo, double* d) {
-  const HalfArgs h{nb, nw, nmo, (long)na * nb, b, C, bh};
-  const MoArgs m{nb, na, nw, nmo, bh, C, bmo, d};
-  RIF_PREC_SWITCH(prec, run_transform<P>(c, h, m))
+  if (!prec_ok(prec)) return fail(c, RIF_ENOTSUP, "precision mode not available");
+  const int lc = round32(nb);
+  Carve cv;
+  const size_t o_cs = cv.take<unsigned short>((size_t)3 * nw * lc);
+  rif_status st = ws_reserve(c, cv.off);
+  if (st) return st;
+  unsigned short* Cs = (unsigned short*)((char*)c->ws + o_cs);
+  const Planes cs{Cs, (long)nw * lc, lc};
+  const PSplitArgs ps{C, (long)nmo, nw, nb, lc, Cs, (long)nw * lc};
+  const HalfArgs h{nb, nw, nmo, (long)na * nb, b, C, bh, cs};
+  const MoArgs m{nb, na, nw, nmo, bh, C, bmo, d, cs};
+  RIF_PREC_SWITCH(prec, run_transform<P>(c, ps, h, m))
 }
 
 rif_status op_jk_mo(rif_ctx* c, int prec, int na, int nw, const void* bmo, const double* d, double* J, double* K) {
@@ -957,9 +1039,17 @@ rif_status op_jk_mo(rif_ctx* c, int prec, int na, int nw, const void* bmo, const
 
 rif_status op_jk_ao(rif_ctx* c, int prec, int nb, int na, int nw, const double* b, const void* bh,
                     const double* d, void* Jn, void* Kn) {
-  const JaoArgs j{nb, na, nw, b, d, Jn};
+  if (!prec_ok(prec)) return fail(c, RIF_ENOTSUP, "precision mode not available");
+  const int ldd = round32(na);
+  Carve cv;
+  const size_t o_ds = cv.take<unsigned short>((size_t)3 * nw * ldd);
+  rif_status st = ws_reserve(c, cv.off);
+  if (st) return st;
+  unsigned short* Ds = (unsigned short*)((char*)c->ws + o_ds);
+  const PSplitArgs ps{d, (long)nw, nw, na, ldd, Ds, (long)nw * ldd};
+  const JaoArgs j{nb, na, nw, b, d, Jn, Planes{Ds, (long)nw * ldd, ldd}};
   const KaoArgs k{nb, na, nw, bh, Kn};
-  RIF_PREC_SWITCH(prec, run_jk_ao<P>(c, j, k))
+  RIF_PREC_SWITCH(prec, run_jk_ao<P>(c, ps, j, k))
 }
 
 rif_status op_energy_grad(rif_ctx* c, int prec, int functional, int nb, int nmo, int npairs, int ncwo,
@@ -1003,7 +1093,7 @@ static rif_status run_build(rif_ctx* c, const BuildArgs& A) {
     OnStream on(c, side);
     if ((st = step1_gemm(c, A.hc))) return st;
   }
-  if ((st = step_half<P>(c, A.half)) || (st = step_mo<P>(c, A.mo))) return st;
+  if ((st = step_psplit<P>(c, A.psc)) || (st = step_half<P>(c, A.half)) || (st = step_mo<P>(c, A.mo))) return st;
   if ((st = hip(hipEventRecord(e_mo, main)))) return st;
   {
     OnStream on(c, side);
@@ -1011,7 +1101,9 @@ static rif_status run_build(rif_ctx* c, const BuildArgs& A) {
         (st = hip(hipEventRecord(e_side, side))))
       return st;
   }
-  if ((st = step_jao<P>(c, A.jao)) || (st = step_kao<P>(c, A.kao))) return st;
+  if ((kPlanesHalfJao<P> && (st = step_psplit<P>(c, A.psd))) || (st = step_jao<P>(c, A.jao)) ||
+      (st = step_kao<P>(c, A.kao)))
+    return st;
   if ((st = hip(hipStreamWaitEvent(main, e_side, 0))) || (st = step1_coef(c, A.coef)) ||
       (st = hip(hipEventRecord(e_coef, main))))
     return st;
@@ -1066,7 +1158,7 @@ struct BatchImpl {
   std::vector<int> order;    // molecule indices, largest first
   void* ws = nullptr;        // workspace of all molecules
   std::vector<void*> dev;    // device allocations to free
-  GroupStep half, mo, jkp, jkr, jao, kao, hc, coef, energy, fock, fred, lam, grad;
+  GroupStep psc, psd, half, mo, jkp, jkr, jao, kao, hc, coef, energy, fock, fred, lam, grad;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -1191,6 +1283,42 @@ RIF_GROUP_SETUP(fock, FockArgs, "g_fock", 4)
                        (const ARGS*)g.args_d, g.off_d, B->n, g.total[0]);                                  \
     return check_launch(B->c, LABEL);                                                                      \
   }
+// pre-split steps: same tile function (psplit) for C_Omega and d
+#define RIF_GROUP_PSPLIT(NAME, LABEL)                                                                      \
+  template <int P>                                                                                         \
+  static rif_status setup_##NAME(BatchImpl* B, const std::vector<PSplitArgs>& a) {                        \
+    GroupStep& g = B->NAME;                                                                                \
+    g.name = LABEL;                                                                                        \
+    g.nvar = 1;                                                                                            \
+    const int n = (int)a.size();                                                                           \
+    std::vector<long> offs(n + 1, 0);                                                                      \
+    for (int i = 0; i < n; ++i) offs[i + 1] = offs[i] + psplit_tiles<P, Cfg256>(a[i]);                    \
+    g.total.assign(1, offs[n]);                                                                            \
+    g.grid.assign(1, (int)std::min(offs[n], 256L * 8));                                                    \
+    if (hipMalloc(&g.args_d, sizeof(PSplitArgs) * n) != hipSuccess ||                                     \
+        hipMalloc((void**)&g.off_d, sizeof(long) * (n + 1)) != hipSuccess)                                \
+      return fail(B->c, RIF_ENOMEM, "batch: device allocation failed");                                    \
+    B->dev.push_back(g.args_d);                                                                            \
+    B->dev.push_back(g.off_d);                                                                             \
+    if (hipMemcpy(g.args_d, a.data(), sizeof(PSplitArgs) * n, hipMemcpyHostToDevice) != hipSuccess ||     \
+        hipMemcpy(g.off_d, offs.data(), sizeof(long) * (n + 1), hipMemcpyHostToDevice) != hipSuccess)     \
+      return fail(B->c, RIF_EHIP, "batch: upload failed");                                                 \
+    return RIF_OK;                                                                                         \
+  }                                                                                                        \
+  template <int P>                                                                                         \
+  static rif_status launch_##NAME(BatchImpl* B, int) {                                                     \
+    GroupStep& g = B->NAME;                                                                                \
+    if constexpr (kPieces<P> == 0) {                                                                       \
+      return RIF_OK;                                                                                       \
+    } else {                                                                                               \
+      if (g.total[0] == 0) return RIF_OK;                                                                  \
+      hipLaunchKernelGGL((k_psplit_g<P, Cfg256>), dim3(g.grid[0]), dim3(256), 0, B->c->stream,             \
+                         (const PSplitArgs*)g.args_d, g.off_d, B->n, g.total[0]);                          \
+      return check_launch(B->c, LABEL);                                                                    \
+    }                                                                                                      \
+  }
+RIF_GROUP_PSPLIT(psc, "g_presplit_C")
+RIF_GROUP_PSPLIT(psd, "g_presplit_d")
 RIF_GROUP_FIXED_P(jkp, JkArgs, "g_jk_mo_partial")
 RIF_GROUP_FIXED_P(jkr, JkArgs, "g_jk_mo_reduce")
 RIF_GROUP_FIXED(hc, gemm, GemmArgs, "g_hc_gemm", kF64, CfgSmall)
@@ -1202,16 +1330,19 @@ RIF_GROUP_FIXED(grad, grad, GradArgs, "g_grad", kF64, Cfg256)
 
 template <int P>
 static rif_status batch_setup(BatchImpl* B, const std::vector<BuildArgs>& A) {
+  std::vector<PSplitArgs> psc, psd;
   std::vector<HalfArgs> half; std::vector<MoArgs> mo; std::vector<JkArgs> jk; std::vector<JaoArgs> jao;
   std::vector<KaoArgs> kao; std::vector<GemmArgs> hc, lam; std::vector<CoefArgs> coef;
   std::vector<EnergyArgs> en; std::vector<FockArgs> fock; std::vector<FockRedArgs> fred; std::vector<GradArgs> grad;
   for (auto& x : A) {
+    psc.push_back(x.psc); psd.push_back(x.psd);
     half.push_back(x.half); mo.push_back(x.mo); jk.push_back(x.jk); jao.push_back(x.jao); kao.push_back(x.kao);
     hc.push_back(x.hc); lam.push_back(x.lam); coef.push_back(x.coef); en.push_back(x.energy);
     fock.push_back(x.fock); fred.push_back(x.fred); grad.push_back(x.grad);
   }
   rif_status st;
-  if ((st = setup_half<P>(B, half)) || (st = setup_mo<P>(B, mo)) || (st = setup_jkp<P>(B, jk)) ||
+  if ((st = setup_psc<P>(B, psc)) || (st = setup_psd<P>(B, psd)) ||
+      (st = setup_half<P>(B, half)) || (st = setup_mo<P>(B, mo)) || (st = setup_jkp<P>(B, jk)) ||
       (st = setup_jkr<P>(B, jk)) || (st = setup_jao<P>(B, jao)) || (st = setup_kao<P>(B, kao)) ||
       (st = setup_hc(B, hc)) || (st = setup_coef(B, coef)) || (st = setup_energy(B, en)) ||
       (st = setup_fock<P>(B, fock)) || (st = setup_fred(B, fred)) || (st = setup_lam(B, lam)) ||
@@ -1252,10 +1383,12 @@ static rif_status batch_enqueue(BatchImpl* B) {
     ProfScope ps(c, B->STEP.name.c_str());                       \
     if ((st = launch_##STEP __VA_ARGS__(B, B->STEP.variant))) return st; \
   }
+  RIF_G(psc, <P>)
   RIF_G(half, <P>)
   RIF_G(mo, <P>)
   RIF_G(jkp, <P>)
   RIF_G(jkr, <P>)
+  if (kPlanesHalfJao<P>) RIF_G(psd, <P>)
   RIF_G(jao, <P>)
   RIF_G(kao, <P>)
   RIF_G(hc)

@@ -386,6 +386,93 @@ struct EngF32 {
 
 // ---------------------------------------------------------------------------
 // Split-BF16 engines.  NPC = pieces per operand (2 for x3, 3 for x6).
+// Split of two operand values into NPC bf16 pieces each, packed two to a
+// 32-bit word per piece (element 0 in the low half).  Shared by the staging
+// path and the pre-split kernel.  Pieces come from the packed round-to-
+// nearest-even conversion of FP32 values: hi = bf16(f) with f = fp32(x), then
+// the first residual x - hi = (x - f) + (f - hi) (both parts exact) rounded
+// once to FP32 (about 2^-33 relative to x), whose further residuals are exact
+// in FP32.  x6 (three pieces): hi + lo + lo2 holds x to about 2^-32; x3 (two):
+// hi + lo to 2^-17.  FP32 operands are their own FP32 value, so every residual
+// is exact in FP32.
+template <int NPC>
+__device__ __forceinline__ void split_tail(float x0, float x1, unsigned (&pc)[NPC]) {
+#pragma unroll
+  for (int s = 1; s < NPC; ++s) {
+    const bf16x2 g = {(__bf16)x0, (__bf16)x1};
+    pc[s] = __builtin_bit_cast(unsigned, g);
+    if (s + 1 < NPC) {
+      x0 -= (float)g[0];
+      x1 -= (float)g[1];
+    }
+  }
+}
+template <int NPC>
+__device__ __forceinline__ void split_pair(double d0, double d1, unsigned (&pc)[NPC]) {
+  float f0 = (float)d0, f1 = (float)d1;
+  // keep the FP32 rounding visible: otherwise the two conversions fold into
+  // one emulated FP64 -> bf16 rounding (no instruction is emitted here)
+  asm("" : "+v"(f0), "+v"(f1));
+  const bf16x2 h = {(__bf16)f0, (__bf16)f1};
+  pc[0] = __builtin_bit_cast(unsigned, h);
+  split_tail<NPC>((float)(d0 - (double)f0) + (f0 - (float)h[0]), (float)(d1 - (double)f1) + (f1 - (float)h[1]),
+                  pc);
+}
+template <int NPC>
+__device__ __forceinline__ void split_pair(float x0, float x1, unsigned (&pc)[NPC]) {
+  const bf16x2 h = {(__bf16)x0, (__bf16)x1};
+  pc[0] = __builtin_bit_cast(unsigned, h);
+  split_tail<NPC>(x0 - (float)h[0], x1 - (float)h[1], pc);
+}
+
+// Operand already split into NPC bf16 piece planes (split_pair arithmetic):
+// element (x, k) of piece s at planes[s * pstride + row(x) * ld + k], k
+// contiguous, every row zero-filled from its length up to ld (a multiple of
+// 32), so no k is ever out of range.  A thread loads KV = 4 consecutive k of
+// one row per piece (8 bytes); rows beyond the operand read row 0 and are
+// zeroed when staged.
+template <int NPC_, int BX, int BK, int NT>
+struct PieceSrc {
+  static constexpr int NPC = NPC_, KV = 4, TPR = BK / KV, RSTEP = NT / TPR;
+  static_assert(NT % TPR == 0 && BX % RSTEP == 0, "bad piece tiling");
+  static constexpr int NP = BX / RSTEP;
+  static constexpr int RR = NP * NPC;
+  static constexpr bool kPresplit = true;
+  using type = u32x2;
+  const unsigned short* rp[NP];
+  long pstride;
+  unsigned vmask;
+  int kg, xr;
+  // row(x, o) sets o = the plane row of operand column x and returns whether it exists
+  template <class Row>
+  __device__ void init(const unsigned short* planes, long pstride_, long ld, Row row) {
+    kg = threadIdx.x % TPR;
+    xr = threadIdx.x / TPR;
+    pstride = pstride_;
+    vmask = 0;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      long o = 0;
+      const bool ok = row(xr + p * RSTEP, o);
+      vmask |= (unsigned)ok << p;
+      rp[p] = planes + (ok ? o : 0) * ld + kg * KV;
+    }
+  }
+  __device__ int xl(int p) const { return xr + p * RSTEP; }
+  __device__ int kl(int) const { return kg * KV; }
+  __device__ bool row_ok(int p) const { return vmask >> p & 1; }
+  __device__ void fetch(int kt, u32x2 (&r)[RR]) const {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int s = 0; s < NPC; ++s) r[p * NPC + s] = *(const u32x2*)(rp[p] + s * pstride + kt * BK);
+  }
+};
+template <class L, class = void>
+struct is_presplit : std::false_type {};
+template <class L>
+struct is_presplit<L, std::void_t<decltype(L::kPresplit)>> : std::true_type {};
+
 template <int NPC>
 struct EngBF16 {
   static constexpr int BK = 32, KV = 4, CHUNK = 4;
@@ -440,58 +527,44 @@ struct EngBF16 {
           }
     }
   };
-  // Splits each group of KV = 4 consecutive k into NPC bf16 pieces and writes
-  // one 8-byte vector per piece.  Pieces come from the packed round-to-
-  // nearest-even conversion of FP32 values: hi = bf16(f) with f = fp32(x), then
-  // the first residual x - hi = (x - f) + (f - hi) (both parts exact) rounded
-  // once to FP32 (about 2^-33 relative to x), whose further residuals are exact
-  // in FP32.  x6: hi + lo + lo2 holds x to about 2^-32; x3: hi + lo to 2^-17.
+  // Writes each group of KV = 4 consecutive k as NPC bf16 pieces, one 8-byte
+  // vector per piece: split here (split_pair) or loaded already split.
   template <int BX, class L>
   __device__ static void stash(lds_char* S, const L& ld, const typename L::type (&r)[L::RR], int kt) {
-    static_assert(L::NP * KV <= L::RR, "groups of KV");
+    if constexpr (is_presplit<L>::value) {
+      static_assert(L::NPC == NPC && L::KV == KV, "piece planes of another split");
 #pragma unroll
-    for (int p = 0; p < L::NP; ++p) {
-      unsigned pc[NPC][KV / 2];
+      for (int p = 0; p < L::NP; ++p) {
+        const int k = ld.kl(p);
+        const int off = chunk_off(ld.xl(p), k / 8) + (k % 8) * 2;
+        const bool ok = ld.row_ok(p);
 #pragma unroll
-      for (int i = 0; i < KV; i += 2) {
-        float x0, x1;
-        if constexpr (std::is_same<typename L::type, float>::value) {
-          // FP32 operand: x is its own FP32 value, so every residual is exact in FP32
-          x0 = ld.valid(p, i, kt) ? (float)ld.val(r, p, i) : 0.f;
-          x1 = ld.valid(p, i + 1, kt) ? (float)ld.val(r, p, i + 1) : 0.f;
-          const bf16x2 h = {(__bf16)x0, (__bf16)x1};
-          pc[0][i / 2] = __builtin_bit_cast(unsigned, h);
-          x0 -= (float)h[0];
-          x1 -= (float)h[1];
-        } else {
-          const double d0 = ld.valid(p, i, kt) ? ld.val(r, p, i) : 0.0;
-          const double d1 = ld.valid(p, i + 1, kt) ? ld.val(r, p, i + 1) : 0.0;
-          float f0 = (float)d0, f1 = (float)d1;
-          // keep the FP32 rounding visible: otherwise the two conversions fold into
-          // one emulated FP64 -> bf16 rounding (no instruction is emitted here)
-          asm("" : "+v"(f0), "+v"(f1));
-          const bf16x2 h = {(__bf16)f0, (__bf16)f1};
-          pc[0][i / 2] = __builtin_bit_cast(unsigned, h);
-          // x - hi = (x - f) + (f - hi): both parts exact, one FP32 rounding
-          x0 = (float)(d0 - (double)f0) + (f0 - (float)h[0]);
-          x1 = (float)(d1 - (double)f1) + (f1 - (float)h[1]);
-        }
-#pragma unroll
-        for (int s = 1; s < NPC; ++s) {
-          const bf16x2 g = {(__bf16)x0, (__bf16)x1};
-          pc[s][i / 2] = __builtin_bit_cast(unsigned, g);
-          if (s + 1 < NPC) {
-            x0 -= (float)g[0];
-            x1 -= (float)g[1];
-          }
+        for (int s = 0; s < NPC; ++s) {
+          const u32x2 v = ok ? r[p * NPC + s] : u32x2{0u, 0u};
+          *(lds_u32x2*)(S + s * piece_bytes<BX>() + off) = v;
         }
       }
-      const int k = ld.kl(p);
-      const int off = chunk_off(ld.xl(p), k / 8) + (k % 8) * 2;
+    } else {
+      static_assert(L::NP * KV <= L::RR, "groups of KV");
 #pragma unroll
-      for (int s = 0; s < NPC; ++s) {
-        const u32x2 v = {pc[s][0], pc[s][1]};
-        *(lds_u32x2*)(S + s * piece_bytes<BX>() + off) = v;
+      for (int p = 0; p < L::NP; ++p) {
+        unsigned pc[KV / 2][NPC];
+#pragma unroll
+        for (int i = 0; i < KV; i += 2) {
+          if constexpr (std::is_same<typename L::type, float>::value)
+            split_pair<NPC>(ld.valid(p, i, kt) ? (float)ld.val(r, p, i) : 0.f,
+                            ld.valid(p, i + 1, kt) ? (float)ld.val(r, p, i + 1) : 0.f, pc[i / 2]);
+          else
+            split_pair<NPC>(ld.valid(p, i, kt) ? ld.val(r, p, i) : 0.0,
+                            ld.valid(p, i + 1, kt) ? ld.val(r, p, i + 1) : 0.0, pc[i / 2]);
+        }
+        const int k = ld.kl(p);
+        const int off = chunk_off(ld.xl(p), k / 8) + (k % 8) * 2;
+#pragma unroll
+        for (int s = 0; s < NPC; ++s) {
+          const u32x2 v = {pc[0][s], pc[1][s]};
+          *(lds_u32x2*)(S + s * piece_bytes<BX>() + off) = v;
+        }
       }
     }
   }
