@@ -234,7 +234,7 @@ def bench_onwarm(args):
     net = ws.WarmStartMLP(ctx, seed=0)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    losses = net.fit(X, T, M, epochs=args.epochs, lr=3e-3)
+    losses = net.fit(X, T, M, epochs=args.epochs, lr=args.lr, lr_final=args.lr_final)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     print(f"trained {args.epochs} epochs on {X.shape[0]} pairs in {t_train:.1f} s, loss "
@@ -296,7 +296,9 @@ def main():
     ap.add_argument("--workload", default="c6h12", choices=["tiny", "c6h12", "c10h20", "batch64", "onwarm"])
     ap.add_argument("--n-train", type=int, default=2000)
     ap.add_argument("--n-test", type=int, default=200)
-    ap.add_argument("--epochs", type=int, default=800)
+    ap.add_argument("--epochs", type=int, default=2000)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--lr-final", type=float, default=1e-4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-tune", action="store_true", help="heuristic tile shapes instead of autotuning")

@@ -204,8 +204,10 @@ long rif_on_work_size(int n_omega, int n_pairs, int n_cwo);
 /* H_pp = c_p^T H c_p for the n_omega orbitals of Omega (Eq. (1)). */
 rif_status rif_hpp(rif_ctx *ctx, int n_bf, int n_mo, int n_omega, const double *H, const double *C,
                    double *Hpp);
-/* L-BFGS (history 8, Armijo backtracking) in FP64, one workgroup per problem,
- * all problems in one launch.  probs is a HOST array (copied). */
+/* L-BFGS (history 8; backtracking with the Armijo test, or the approximate
+ * Wolfe conditions once energy changes are below rounding noise) in FP64, one
+ * workgroup per problem, all problems in one launch.  probs is a HOST array
+ * (copied). */
 rif_status rif_on_optimize(rif_ctx *ctx, int n_prob, const rif_on_problem *probs);
 /* Per-pair MLP features X [rows][39] (optionally standardised: (x - mu)/sigma
  * where sigma > 0), and, if T/M are non-NULL, targets T [rows][7] = the

@@ -8,8 +8,8 @@
 //   w_1 = cos^2 b_1, w_k = prod_{j<k} sin^2 b_j cos^2 b_k, w_last = prod sin^2 b_j,
 //   variables [gamma_g, b_1 .. b_{ncwo-1}] at g*ncwo + j.
 //
-//   k_on_opt      one workgroup per problem runs L-BFGS (history 8, Armijo
-//                 backtracking) to max|dE/dgamma| <= tol, all in FP64 with
+//   k_on_opt      one workgroup per problem runs L-BFGS (history 8, backtracking
+//                 with Armijo or, within rounding noise, approximate Wolfe) to max|dE/dgamma| <= tol, all in FP64 with
 //                 fixed-order reductions.
 //   k_on_feat     per-pair features (39) and ON targets/masks for the MLP.
 //   k_on_warm     MLP ON predictions -> starting gamma.
@@ -272,7 +272,10 @@ __global__ __launch_bounds__(kOnThreads) void k_on_opt(const OnProblem* __restri
       hist = 0;
       gd = dot(v.g, v.d, nv, red);
     }
-    // Armijo backtracking
+    // Backtracking with the Armijo test, or, once the energy change is below
+    // its rounding noise, the approximate Wolfe conditions on the directional
+    // derivative (Hager and Zhang, 2005): 0.9 phi'(0) <= phi'(a) <= -0.8 phi'(0).
+    const double epsE = 1e-12 * fabs(E);
     double step = 1.0, En = 0.0;
     bool ok = false;
     for (int ls = 0; ls < 50; ++ls) {
@@ -280,6 +283,10 @@ __global__ __launch_bounds__(kOnThreads) void k_on_opt(const OnProblem* __restri
       __syncthreads();
       En = on_eval(v, v.xn, v.gn, red);
       if (En <= E + 1e-4 * step * gd) { ok = true; break; }
+      if (En <= E + epsE) {
+        const double gnd = dot(v.gn, v.d, nv, red);
+        if (gnd >= 0.9 * gd && gnd <= -0.8 * gd) { ok = true; break; }
+      }
       step *= 0.5;
     }
     if (!ok) { status = 2; break; }

@@ -75,19 +75,21 @@ class WarmStartMLP:
                 torch.empty((rows, N_OUT), dtype=f, device=self.device),
                 torch.empty((rows, N_OUT), dtype=f, device=self.device))
 
-    def fit(self, X, T, M, epochs=400, lr=3e-3):
-        """Full-batch Adam on the GPU; returns the loss history (host floats)."""
+    def fit(self, X, T, M, epochs=400, lr=3e-3, lr_final=None):
+        """Full-batch Adam on the GPU, the learning rate decaying geometrically
+        from lr to lr_final (default: constant); returns the loss history."""
         import torch
         rows = X.shape[0]
         H, Z, P = self._bufs(rows)
         dA = torch.empty((2, rows, N_HID), dtype=torch.float32, device=self.device)
         loss = torch.zeros(1, dtype=torch.float64, device=self.device)
         hist = []
-        for _ in range(epochs):
+        decay = 1.0 if lr_final is None else (lr_final / lr) ** (1.0 / max(1, epochs - 1))
+        for e in range(epochs):
             self.ctx.mlp_forward(X, M, self.theta, H, Z, P)
             self.ctx.mlp_backward(X, M, T, self.theta, H, Z, dA, self.grad, loss)
             self.step += 1
-            self.ctx.adam(self.theta, self.grad, self.m, self.v, self.step, lr)
+            self.ctx.adam(self.theta, self.grad, self.m, self.v, self.step, lr * decay ** e)
             hist.append(loss)
             loss = torch.zeros(1, dtype=torch.float64, device=self.device)
         return [float(h.item()) for h in hist]
