@@ -10,5 +10,9 @@ Modules:
   brute     -- independent checks: explicit four-index integrals with the
                conventional algorithm (Table 1), a closed-shell HF route,
                and an antisymmetrised-geminal-product expectation value.
+  on_opt    -- ON optimisation at fixed orbitals (gamma variables, scipy L-BFGS).
+  mlp       -- the warm-start network: features, forward, backward, Adam.
+  orbital   -- orbital optimisation by iterative diagonalisation of F^lambda
+               and the outer/inner loop of Fig. 1.
 """
 from . import pnof7_ri, brute  # noqa: F401
