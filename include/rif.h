@@ -236,6 +236,62 @@ rif_status rif_mlp_backward(rif_ctx *ctx, int rows, const float *X, const float 
 rif_status rif_adam(rif_ctx *ctx, int n, float *theta, const float *grad, float *m, float *v, int step,
                     float lr, float beta1, float beta2, float eps);
 
+/* ---- Orbital optimisation and the outer/inner loop ----
+ * Sec. II, orbital optimisation with RI: at fixed ONs the natural orbitals are
+ * found by repeated diagonalisation of a symmetric matrix F^lambda built from
+ * the Lagrange multipliers, so orthonormality holds at every step; Fig. 1
+ * alternates this (inner iterations) with the ON optimisation (outer).
+ * F^lambda is not printed in the paper; the reading implemented here: off the
+ * diagonal F_pq = lambda_{hi,lo} - lambda_{lo,hi} with hi = max(p,q),
+ * lo = min(p,q) and lambda_ab = 0 for b outside Omega (F vanishes off the
+ * diagonal exactly when the orbital gradient does); the diagonal is lambda_pp
+ * at the first step of an inner loop and the previous step's eigenvalues
+ * after that (aufbau order: eigenvectors by ascending eigenvalue, an
+ * orbital's role -- strong, weak of a pair, or outside Omega -- by index).
+ *
+ * rif_orbital_step: one diagonalisation.  Device pointers:
+ *   lambda  [n_mo][n_omega] FP64 (rif_build's lambda)
+ *   eps_in  [n_mo] diagonal of F^lambda, or NULL for lambda_pp
+ *   C       [n_bf][n_mo] in/out: replaced by C V, V the eigenvectors
+ *   eps_out [n_mo] eigenvalues, ascending (may be eps_in)
+ *   info    device int or NULL: 0, or the eigensolver's failure count
+ * The eigen-decomposition is rocSOLVER's dsyevd on the context's stream with
+ * its workspace in the context arena; the rotation is an FP64 MFMA GEMM.
+ * Asynchronous.  RIF_EINVAL: need 0 < n_omega <= n_mo <= n_bf, non-NULL
+ * lambda, C and eps_out. */
+rif_status rif_orbital_step(rif_ctx *ctx, int n_bf, int n_mo, int n_omega, const double *lambda,
+                            const double *eps_in, double *C, double *eps_out, int *info);
+
+/* Fig. 1 loop.  Each outer iteration: J, K (MO) and H_pp at the current
+ * orbitals, then the ON optimisation (rif_on_optimize's L-BFGS, from the
+ * current gamma); then inner iterations at the new ONs, each one build
+ * (rif_build) followed, unless max|G| <= tol_grad, by one rif_orbital_step.
+ * Converged when an outer iteration after the first ends with a converged
+ * inner loop and an energy within tol_energy of the previous one.
+ *   init_gamma 0: the first ON step starts from the ONs in occ (mapped to
+ *   gamma through the warm-start map, in FP32); 1: from gamma as given. */
+typedef struct rif_opt_params {
+  int max_outer, max_inner, on_max_it, init_gamma;
+  double tol_grad, tol_energy, on_tol;
+} rif_opt_params;
+/* status 0 converged, 1 iteration limit, 2 eigensolver failure (also an
+ * RIF_EHIP return), 3 non-finite energy or gradient.  Times are HIP-event
+ * milliseconds of the ON steps (J/K, H_pp, L-BFGS), the builds (with max|G|)
+ * and the orbital steps. */
+typedef struct rif_opt_result {
+  int outer, inner_total, on_iters_total, on_status, status;
+  double energy, max_grad, ms_on, ms_build, ms_orbital;
+} rif_opt_result;
+/* inst: buffers and inputs as for rif_build; inst->C and inst->occ are
+ * ignored and C, occ used instead.  Device pointers: C [n_bf][n_mo] in/out,
+ * occ [n_omega] in/out, gamma [n_pairs*n_cwo] in/out.  Host pointers: res,
+ * and optionally hist_energy / hist_grad, which receive the energy and
+ * max|G| of each inner iteration (first hist_len of them).  Blocks until the
+ * loop ends (one stream synchronisation per inner iteration). */
+rif_status rif_pnof_optimize(rif_ctx *ctx, const rif_instance *inst, rif_prec prec, rif_functional functional,
+                             const rif_opt_params *par, double *C, double *occ, double *gamma,
+                             rif_opt_result *res, double *hist_energy, double *hist_grad, int hist_len);
+
 /* Tile-shape selection for the MFMA kernels.  Each GEMM-shaped kernel has up
  * to four tile variants (0: 128x128, 1: 64x64, 2: 128x64, 3: 64x128 outputs
  * per workgroup).  mode 0 picks one per shape with a wave-quantisation

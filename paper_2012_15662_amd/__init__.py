@@ -15,7 +15,7 @@ import ctypes
 import os
 
 __all__ = [
-    "Context", "Batch", "Instance", "OnProblem", "OnSet", "RifError", "load_library", "LIB_PATH", "FP64", "FP32", "BF16X3", "BF16X6",
+    "Context", "Batch", "Instance", "OnProblem", "OnSet", "OptParams", "OptResult", "RifError", "load_library", "LIB_PATH", "FP64", "FP32", "BF16X3", "BF16X6",
     "FP16X3", "PNOF7", "PNOF5", "EXPORTS",
 ]
 
@@ -40,6 +40,21 @@ class OnProblem(ctypes.Structure):
                [("tol", ctypes.c_double)] + \
                [(n, ctypes.c_void_p) for n in ("Hpp", "J", "K", "pair_of", "gamma", "occ", "energy", "iters",
                                                "status", "work")]
+
+
+class OptParams(ctypes.Structure):
+    """struct rif_opt_params (include/rif.h)."""
+    _fields_ = [(n, ctypes.c_int) for n in ("max_outer", "max_inner", "on_max_it", "init_gamma")] + \
+               [(n, ctypes.c_double) for n in ("tol_grad", "tol_energy", "on_tol")]
+
+
+class OptResult(ctypes.Structure):
+    """struct rif_opt_result (include/rif.h)."""
+    _fields_ = [(n, ctypes.c_int) for n in ("outer", "inner_total", "on_iters_total", "on_status", "status")] + \
+               [(n, ctypes.c_double) for n in ("energy", "max_grad", "ms_on", "ms_build", "ms_orbital")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
 
 
 # name -> (restype, argtypes); mirrors include/rif.h
@@ -71,6 +86,9 @@ EXPORTS = {
     "rif_mlp_backward": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "rif_adam": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _i, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                       ctypes.c_float]),
+    "rif_orbital_step": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]),
+    "rif_pnof_optimize": (_i, [_vp, ctypes.POINTER(Instance), _i, _i, ctypes.POINTER(OptParams), _vp, _vp, _vp,
+                               ctypes.POINTER(OptResult), _vp, _vp, _i]),
     "rif_autotune": (_i, [_vp, _i]),
     "rif_set_tile_variant": (_i, [_vp, _i]),
     "rif_tune_report": (_i, [_vp, ctypes.c_char_p, _i]),
@@ -339,6 +357,42 @@ class Context:
         import torch
         self._chk(self.lib.rif_on_warmstart(self.h, len(onset.arr), onset.arr,
                                             _ptr(P, "P", torch.float32, onset.rows * 7)))
+
+    # ---- orbital optimisation and the outer/inner loop ----------------------
+    def orbital_step(self, lam, C, n_omega, eps_in=None, eps_out=None, info=None):
+        """One rif_orbital_step: C (in place) <- C V; returns eps_out."""
+        import torch
+        n_bf, n_mo = C.shape
+        if eps_out is None:
+            eps_out = torch.empty(n_mo, dtype=torch.float64, device=C.device)
+        self._chk(self.lib.rif_orbital_step(
+            self.h, n_bf, n_mo, n_omega, _ptr(lam, "lambda", torch.float64, n_mo * n_omega),
+            _ptr(eps_in, "eps_in", torch.float64, n_mo), _ptr(C, "C", torch.float64, n_bf * n_mo),
+            _ptr(eps_out, "eps_out", torch.float64, n_mo), _ptr(info, "info", torch.int32, 1)))
+        return eps_out
+
+    def optimize(self, b, C, H, occ, gamma, pair_of, n_pairs, n_cwo, prec=FP64, functional=PNOF7,
+                 max_outer=50, max_inner=500, on_max_it=2000, tol_grad=1e-8, tol_energy=1e-10, on_tol=1e-10,
+                 init_gamma=0, hist_len=0, out=None):
+        """rif_pnof_optimize: C, occ and gamma are updated in place.  Returns
+        (result dict, per-inner-iteration energies, max|G|) with the histories
+        as lists of at most hist_len entries."""
+        n_aux, n_bf, _ = b.shape
+        if out is None:
+            out = self.outputs(n_bf, n_aux, n_pairs, n_cwo, C.shape[1], prec, b.device)
+        inp = {"b": b, "C": C, "H": H, "occ": occ, "pair_of": pair_of}
+        inst = self.instance(inp, n_pairs, n_cwo, out, prec)
+        import torch
+        _ptr(gamma, "gamma", torch.float64, n_pairs * n_cwo)
+        par = OptParams(max_outer, max_inner, on_max_it, init_gamma, tol_grad, tol_energy, on_tol)
+        res = OptResult()
+        he = (ctypes.c_double * max(hist_len, 1))()
+        hg = (ctypes.c_double * max(hist_len, 1))()
+        self._chk(self.lib.rif_pnof_optimize(
+            self.h, ctypes.byref(inst), prec, functional, ctypes.byref(par), inst.C, inst.occ,
+            ctypes.c_void_p(gamma.data_ptr()), ctypes.byref(res), he, hg, hist_len))
+        n = min(hist_len, res.inner_total)
+        return res.as_dict(), list(he[:n]), list(hg[:n])
 
     def mlp_n_params(self) -> int:
         return int(self.lib.rif_mlp_n_params())

@@ -45,7 +45,9 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         if p.returncode:
             raise RuntimeError("hipcc failed: " + " ".join(cmd))
     tmp = LIB + ".tmp"
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    # rocSOLVER (the orbital step's eigensolver) and the rocBLAS it runs on
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp,
+           "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

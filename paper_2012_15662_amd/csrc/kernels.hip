@@ -862,6 +862,11 @@ RIF_FIXED_STEP(coef, CoefArgs, "coef", kF64, Cfg256)
 RIF_FIXED_STEP(energy, EnergyArgs, "energy", kF64, CfgEnergy)
 RIF_FIXED_STEP(fred, FockRedArgs, "fock_reduce", kF64, Cfg256)
 RIF_FIXED_STEP(grad, GradArgs, "grad", kF64, Cfg256)
+
+rif_status op_gemm_kn(rif_ctx* c, int M, int N, int K, const double* A, long lda, const double* B, long ldb,
+                      double* out, long ldo) {
+  return step1_gemm(c, GemmArgs{M, N, K, A, lda, B, ldb, out, ldo, 1, K, 0});
+}
 template <int P>
 static rif_status step_psplit(rif_ctx* c, const PSplitArgs& a) {
   if constexpr (kPieces<P> == 0) {

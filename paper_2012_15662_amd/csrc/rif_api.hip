@@ -160,6 +160,7 @@ void rif_destroy(rif_ctx* c) {
   }
   for (auto e : c->ev)
     if (e) hipEventDestroy(e);
+  op_orbital_release(c);
   if (c->own_stream) hipStreamDestroy(c->own_stream);
   delete c;
 }
@@ -266,6 +267,38 @@ rif_status rif_build(rif_ctx* c, const rif_instance* in, rif_prec prec, rif_func
   if (fn != RIF_PNOF7 && fn != RIF_PNOF5) return fail(c, RIF_EINVAL, "rif_build: unknown functional");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
   return op_build(c, (int)prec, (int)fn, *in);
+}
+
+rif_status rif_orbital_step(rif_ctx* c, int nb, int nmo, int nw, const double* lam, const double* eps_in,
+                            double* C, double* eps_out, int* info) {
+  if (!c) return RIF_EINVAL;
+  if (!dims_ok(nb) || !dims_ok(nmo) || !dims_ok(nw) || nw > nmo || nmo > nb)
+    return fail(c, RIF_EINVAL, "rif_orbital_step: need 0 < n_omega <= n_mo <= n_bf");
+  if (!lam || !C || !eps_out) return fail(c, RIF_EINVAL, "rif_orbital_step: NULL pointer");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  return op_orbital_step(c, nb, nmo, nw, lam, eps_in, C, eps_out, info);
+}
+
+rif_status rif_pnof_optimize(rif_ctx* c, const rif_instance* in, rif_prec prec, rif_functional fn,
+                             const rif_opt_params* par, double* C, double* occ, double* gamma, rif_opt_result* res,
+                             double* hist_e, double* hist_g, int hist_len) {
+  if (!c) return RIF_EINVAL;
+  if (!in || !par || !C || !occ || !gamma || !res)
+    return fail(c, RIF_EINVAL, "rif_pnof_optimize: NULL instance, params, C, occ, gamma or result");
+  rif_instance w = *in;
+  w.C = C;
+  w.occ = occ;
+  rif_status st = check_instance(c, &w, "rif_pnof_optimize");
+  if (st) return st;
+  if (fn != RIF_PNOF7 && fn != RIF_PNOF5) return fail(c, RIF_EINVAL, "rif_pnof_optimize: unknown functional");
+  if (in->n_cwo > 14) return fail(c, RIF_EINVAL, "rif_pnof_optimize: the ON optimiser takes n_cwo <= 14");
+  if (par->max_outer < 1 || par->max_inner < 1 || par->on_max_it < 0 || !(par->tol_grad > 0.0) ||
+      !(par->tol_energy >= 0.0) || !(par->on_tol > 0.0) || (par->init_gamma != 0 && par->init_gamma != 1) ||
+      hist_len < 0)
+    return fail(c, RIF_EINVAL, "rif_pnof_optimize: need max_outer, max_inner >= 1, on_max_it >= 0, tolerances > 0, "
+                               "init_gamma 0 or 1, hist_len >= 0");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  return op_optimize(c, (int)prec, (int)fn, w, *par, C, occ, gamma, res, hist_e, hist_g, hist_len);
 }
 
 struct rif_batch {

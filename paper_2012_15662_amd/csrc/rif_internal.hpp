@@ -35,6 +35,8 @@ struct rif_ctx {
   // (default priority; created on first use) and the fork/join events
   hipStream_t side = nullptr;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  // rocBLAS handle of the orbital step's eigensolver (created on first use)
+  void* blas = nullptr;
 };
 
 namespace rif {
@@ -108,6 +110,19 @@ rif_status op_adam(rif_ctx* c, int n, float* theta, const float* grad, float* m,
 // a2..a8 of one molecule in one call (inst already validated), with the small
 // independent steps on the context's side stream.
 rif_status op_build(rif_ctx* c, int prec, int functional, const rif_instance& in);
+
+// FP64 GEMM out[m][n] = sum_k A[k][m] B[k][n] (row strides lda, ldb, ldo), one pass over k.
+rif_status op_gemm_kn(rif_ctx* c, int M, int N, int K, const double* A, long lda, const double* B, long ldb,
+                      double* out, long ldo);
+
+// Orbital optimisation (orbital.hip)
+rif_status op_maxabs(rif_ctx* c, long n, const double* x, double* out);
+rif_status op_orbital_step(rif_ctx* c, int nb, int nmo, int nw, const double* lam, const double* eps_in,
+                           double* C, double* eps_out, int* info);
+rif_status op_optimize(rif_ctx* c, int prec, int fn, const rif_instance& in, const rif_opt_params& par, double* C,
+                       double* occ, double* gamma, rif_opt_result* res, double* hist_e, double* hist_g,
+                       int hist_len);
+void op_orbital_release(rif_ctx* c);
 
 // Batched builds (inst already validated); the handle is opaque to the ABI layer.
 rif_status op_batch_create(rif_ctx* c, int prec, int functional, int n, const rif_instance* inst, void** out);

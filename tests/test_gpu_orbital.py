@@ -1,0 +1,189 @@
+"""Orbital optimisation on the GPU (rif_orbital_step, rif_pnof_optimize)
+against the FP64 oracle (oracle/orbital.py) and against two-electron full CI.
+
+What is unique is compared: eigenvalues, the energy of every inner iteration,
+and the orbitals up to the sign of each eigenvector.  Eigenvectors of a
+degenerate eigenvalue are not unique (at the first step of an inner loop the
+block outside Omega has a zero diagonal); those are checked for
+orthonormality only, and the energy, which does not depend on them, is
+compared at every iteration.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import orbital as orb
+from oracle import pnof7_ri as ri
+from tests.gpu_util import host, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2012_15662_amd as rif
+    c = rif.Context()
+    yield c
+    c.close()
+
+
+def sign_aligned(got, ref):
+    """Flip each column of got to the sign of the matching column of ref."""
+    s = np.sign(np.sum(got * ref, axis=0))
+    s[s == 0] = 1
+    return got * s
+
+
+@pytest.mark.parametrize("shape", [(48, 192, 5, 1, 0), (37, 101, 3, 2, 11), (130, 259, 7, 3, 12)])
+def test_orbital_step_matches_oracle(ctx, shape):
+    import torch
+    nb, na, npair, ncwo, seed = shape
+    print("case orbital step", shape, flush=True)
+    inst = synth.make_instance(nb, na, npair, ncwo, seed)
+    t = to_dev(inst)
+    out = ctx.build(t["b"], t["C"], t["H"], t["occ"], t["pair_of"], npair, ncwo)
+    lam = host(out["lam"])
+    # distinct ascending diagonal: every eigenvector unique up to sign
+    eps = np.sort(np.random.default_rng(seed).uniform(-5, 5, inst.n_mo))
+    C_ref, w_ref = orb.orbital_step(inst.C, lam, eps)
+    C = t["C"].clone()
+    w = ctx.orbital_step(out["lam"], C, inst.occ.size, eps_in=torch.from_numpy(eps).cuda())
+    ctx.sync()
+    assert np.max(np.abs(host(w) - w_ref)) <= 1e-12 * np.max(np.abs(w_ref))
+    Cg = sign_aligned(host(C), C_ref)
+    assert np.max(np.abs(Cg - C_ref)) <= 1e-10
+    assert np.allclose(host(C).T @ host(C), np.eye(inst.n_mo), atol=1e-12)
+
+
+def test_inner_loop_matches_oracle(ctx):
+    """30 inner iterations (first step from lambda_pp, then the eigenvalues)."""
+    import torch
+    inst = synth.workload("tiny")
+    W = inst.occ.size
+    print("case inner loop tiny 30 iterations", flush=True)
+    ref = orb.inner_loop(inst.b, inst.C, inst.H, inst.occ, inst.pair_of, inst.n_pairs, 30, 1e-14)
+    t = to_dev(inst)
+    C = t["C"].clone()
+    eps = torch.empty(inst.n_mo, dtype=torch.float64, device="cuda")
+    out = None
+    for it in range(30):
+        out = ctx.build(t["b"], C, t["H"], t["occ"], t["pair_of"], inst.n_pairs, inst.n_cwo, out=out)
+        ctx.sync()
+        e = float(host(out["energy"])[0])
+        assert abs(e - ref["energies"][it]) <= 1e-10 * abs(ref["energies"][it]), (it, e, ref["energies"][it])
+        ctx.orbital_step(out["lam"], C, W, eps_in=eps if it else None, eps_out=eps)
+    ctx.sync()
+    Cg = host(C)
+    assert np.allclose(Cg.T @ Cg, np.eye(inst.n_mo), atol=1e-12)
+    # the Omega orbitals of the final set: equal to the oracle's up to sign
+    Cw = sign_aligned(Cg[:, :W], ref["C"][:, :W])
+    assert np.max(np.abs(Cw - ref["C"][:, :W])) <= 1e-8
+
+
+def test_orbital_step_full_size(ctx):
+    """Cyclohexane-like workload (n_bf = n_mo = 348): five inner iterations,
+    energies against the oracle's."""
+    import torch
+    inst = synth.workload("c6h12")
+    print("case inner loop c6h12 5 iterations", flush=True)
+    ref = orb.inner_loop(inst.b, inst.C, inst.H, inst.occ, inst.pair_of, inst.n_pairs, 5, 1e-14)
+    t = to_dev(inst)
+    C = t["C"].clone()
+    eps = torch.empty(inst.n_mo, dtype=torch.float64, device="cuda")
+    out = None
+    for it in range(5):
+        out = ctx.build(t["b"], C, t["H"], t["occ"], t["pair_of"], inst.n_pairs, inst.n_cwo, out=out)
+        ctx.sync()
+        e = float(host(out["energy"])[0])
+        assert abs(e - ref["energies"][it]) <= 1e-10 * abs(ref["energies"][it]), (it, e, ref["energies"][it])
+        ctx.orbital_step(out["lam"], C, inst.occ.size, eps_in=eps if it else None, eps_out=eps)
+    ctx.sync()
+    Cg = host(C)
+    assert np.allclose(Cg.T @ Cg, np.eye(inst.n_mo), atol=1e-11)
+
+
+def run_loop(ctx, inst, C0, occ0, **kw):
+    import torch
+    t = to_dev(inst, C=C0)
+    occ = torch.from_numpy(np.ascontiguousarray(occ0)).cuda()
+    gamma = torch.zeros(inst.n_pairs * inst.n_cwo, dtype=torch.float64, device="cuda")
+    res, he, hg = ctx.optimize(t["b"], t["C"], t["H"], occ, gamma, t["pair_of"], inst.n_pairs, inst.n_cwo,
+                               hist_len=100000, **kw)
+    ctx.sync()
+    return res, he, hg, host(t["C"]), host(occ)
+
+
+def test_full_loop_converges_to_a_stationary_point(ctx):
+    """Fig. 1 loop (n_bf=20, n_aux=40, 2 pairs, Ncwo=1; about 2e4 inner
+    iterations); the oracle checks the GPU's final point (energy, gradient,
+    ON optimality) and runs the same loop."""
+    from oracle import on_opt
+    inst = synth.make_instance(20, 40, 2, 1, 31)
+    print("case full loop n_bf=20 n_aux=40 pairs=2 ncwo=1 seed=31", flush=True)
+    kw = dict(max_outer=40, max_inner=4000, tol_grad=1e-6, tol_energy=1e-9, on_tol=1e-10)
+    res, he, hg, C, occ = run_loop(ctx, inst, inst.C, inst.occ, **kw)
+    print("gpu loop", res, flush=True)
+    assert res["status"] == 0 and res["on_status"] == 0
+    assert np.allclose(C.T @ C, np.eye(inst.n_mo), atol=1e-11)
+    # the oracle at the GPU's final point
+    r = ri.build(inst.b, C, inst.H, occ, inst.pair_of, inst.n_pairs)
+    assert abs(r["energy"] - res["energy"]) <= 1e-10 * abs(r["energy"])
+    assert np.max(np.abs(r["grad"])) <= 1e-6 * 1.01
+    # the ONs were optimised at the orbitals the last inner loop started from;
+    # the energy change that loop made is below tol_energy, so they are close
+    # to, not exactly at, the ON optimum of the final orbitals
+    gam = on_opt.n_to_gamma(occ, inst.pair_of, inst.n_pairs, inst.n_cwo)
+    g_on = on_opt.grad_gamma(gam, r["Hpp"], r["J"], r["K"], inst.pair_of, inst.n_pairs, inst.n_cwo)
+    assert np.max(np.abs(g_on)) <= 1e-4
+    assert len(he) == res["inner_total"] and he[-1] == res["energy"]
+    # the oracle's own loop from the same start reaches the same energy
+    ref = orb.outer_loop(inst.b, inst.C, inst.H, inst.occ, inst.pair_of, inst.n_pairs, inst.n_cwo,
+                         kw["max_outer"], kw["max_inner"], kw["tol_grad"], kw["tol_energy"], kw["on_tol"])
+    print("oracle loop", ref["energies"][-1], len(ref["energies"]), sum(ref["inner"]), flush=True)
+    assert ref["converged"]
+    assert abs(ref["energies"][-1] - res["energy"]) <= 1e-8 * abs(res["energy"])
+    assert res["outer"] == len(ref["energies"])
+
+
+def fci_two_electrons(h, eri):
+    n = h.shape[0]
+    I = np.eye(n)
+    M = (np.einsum("pr,qs->pqrs", h, I) + np.einsum("pr,qs->pqrs", I, h)
+         + np.einsum("prqs->pqrs", eri)).reshape(n * n, n * n)
+    basis = []
+    for p in range(n):
+        for q in range(p, n):
+            v = np.zeros((n, n))
+            v[p, q] = v[q, p] = 1.0
+            basis.append(v.ravel() / np.linalg.norm(v))
+    S = np.array(basis).T
+    w, U = np.linalg.eigh(S.T @ M @ S)
+    return w[0], (S @ U[:, 0]).reshape(n, n)
+
+
+@pytest.mark.parametrize("seed", [103, 104])
+def test_full_loop_holds_two_electron_full_ci(ctx, seed):
+    """One pair over all 5 orbitals, started at the FCI natural orbitals and
+    ONs: the GPU loop stays at the full-CI energy."""
+    nb = 5
+    inst = synth.make_instance(nb, 3 * nb, 1, nb - 1, seed)
+    print("case two-electron FCI seed", seed, flush=True)
+    h = inst.C.T @ inst.H @ inst.C
+    bm = np.einsum("mp,lmn,nq->lpq", inst.C, inst.b, inst.C)
+    e_fci, X = fci_two_electrons(h, np.einsum("lpq,lrs->pqrs", bm, bm))
+    c, U = np.linalg.eigh(X)
+    order = np.argsort(-np.abs(c))
+    c, U = c[order], U[:, order]
+    c = c if c[0] > 0 else -c
+    assert np.all(c[1:] < 0)
+    occ0 = c ** 2
+    occ0[0] = 1.0 - np.sum(occ0[1:])
+    res, he, hg, C, occ = run_loop(ctx, inst, np.ascontiguousarray(inst.C @ U), occ0, max_outer=5,
+                                   max_inner=50, tol_grad=1e-8, tol_energy=1e-11, on_tol=1e-10)
+    print("gpu loop", res, "fci", e_fci, flush=True)
+    assert res["status"] == 0
+    assert abs(res["energy"] - e_fci) <= 1e-11 * abs(e_fci)
+    assert min(he) >= e_fci - 1e-11 * abs(e_fci)
