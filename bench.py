@@ -288,12 +288,91 @@ def bench_onwarm(args):
     print(json.dumps(line))
 
 
+def bench_orbopt(args):
+    """Orbital optimisation by iterative diagonalisation of F^lambda (the inner
+    iterations of Fig. 1) on the cyclohexane-like workload: one ON step, then
+    `steps` inner iterations (build, max|G|, F^lambda, eigen-decomposition,
+    rotation), timed as one rif_pnof_optimize call; plus a small molecule
+    (n_bf=20, n_aux=40, 2 pairs, Ncwo=1) run to convergence."""
+    import numpy as np
+    import torch
+
+    import paper_2012_15662_amd as rif
+    import synth
+
+    ctx = rif.Context(0)
+    if not args.no_tune:
+        ctx.autotune(True)
+
+    def upload(inst):
+        d = {k: torch.from_numpy(np.ascontiguousarray(getattr(inst, k))).cuda() for k in ("b", "C", "H", "occ")}
+        d["pair_of"] = torch.from_numpy(inst.pair_of.astype(np.int32)).cuda()
+        d["gamma"] = torch.zeros(inst.n_pairs * inst.n_cwo, dtype=torch.float64, device="cuda")
+        return d
+
+    def run(inst, d, **kw):
+        C, occ, gamma = d["C"].clone(), d["occ"].clone(), d["gamma"].clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, he, hg = ctx.optimize(d["b"], C, d["H"], occ, gamma, d["pair_of"], inst.n_pairs, inst.n_cwo,
+                                   hist_len=100000, **kw)
+        torch.cuda.synchronize()
+        return res, he, hg, time.perf_counter() - t0
+
+    inst = synth.workload("c6h12")
+    d = upload(inst)
+    run(inst, d, max_outer=1, max_inner=3, tol_grad=1e-14)          # tile tuning, solver set-up
+    res, he, hg, wall = run(inst, d, max_outer=1, max_inner=args.steps, tol_grad=1e-14)
+    n = res["inner_total"]
+    per_ms = (res["ms_build"] + res["ms_orbital"]) / n
+    print(f"c6h12: {n} inner iterations, build {res['ms_build'] / n:.3f} ms, orbital step "
+          f"{res['ms_orbital'] / max(1, n - 1):.3f} ms, ON step {res['ms_on']:.2f} ms; E {he[0]:.6f} -> {he[-1]:.6f}, "
+          f"max|G| {hg[0]:.2e} -> {hg[-1]:.2e}", file=sys.stderr, flush=True)
+
+    small_line = None
+    if not args.no_small:
+        small = synth.make_instance(20, 40, 2, 1, 31)
+        ds = upload(small)
+        rs, hes, _, wall_s = run(small, ds, max_outer=40, max_inner=4000, tol_grad=1e-6, tol_energy=1e-9)
+        print(f"small: status {rs['status']} after {rs['outer']} outer / {rs['inner_total']} inner iterations, "
+              f"{wall_s:.2f} s, E {rs['energy']:.10f}", file=sys.stderr, flush=True)
+        small_line = {"status": rs["status"], "outer": rs["outer"], "inner": rs["inner_total"],
+                      "wall_s": round(wall_s, 3), "energy": rs["energy"], "max_grad": rs["max_grad"],
+                      "ms_build": round(rs["ms_build"], 1), "ms_orbital": round(rs["ms_orbital"], 1)}
+
+    cpu = None
+    if not args.no_cpu:
+        from oracle import orbital as orb
+        ts = time.perf_counter()
+        k = orb.inner_loop(inst.b, inst.C, inst.H, inst.occ, inst.pair_of, inst.n_pairs, 3, 1e-14)
+        tc = time.perf_counter() - ts
+        cpu = {"value": round(len(k["energies"]) / tc, 3), "unit": "inner iterations/s",
+               "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), "kind": "oracle",
+               "sample": f"3 inner iterations of the same workload at fixed ONs (numpy build + eigh), {tc:.1f} s"}
+
+    line = {
+        "metric": "orbital-optimisation inner iterations/s (build + F^lambda eigen-decomposition + rotation)",
+        "value": round(1e3 / per_ms, 3), "unit": "inner iterations/s", "n_gpus": 1, "steps": n,
+        "warmup": 3, "ms_per_step": round(per_ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "orbopt: c6h12 n_bf=348 n_aux=1044 pairs=24 ncwo=4 n_mo=348, fixed ONs after one ON step"},
+        "split_ms": {"build_with_maxG": round(res["ms_build"] / n, 4),
+                     "orbital_step": round(res["ms_orbital"] / max(1, n - 1), 4),
+                     "on_step_once": round(res["ms_on"], 3)},
+        "wall_s": round(wall, 3), "energy_first": he[0], "energy_last": he[-1], "max_grad_first": hg[0],
+        "max_grad_last": hg[-1],
+        "small_to_convergence": small_line,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c6h12", choices=["tiny", "c6h12", "c10h20", "batch64", "onwarm"])
+    ap.add_argument("--workload", default="c6h12", choices=["tiny", "c6h12", "c10h20", "batch64", "onwarm", "orbopt"])
     ap.add_argument("--n-train", type=int, default=2000)
     ap.add_argument("--n-test", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=2000)
@@ -306,6 +385,8 @@ def main():
     ap.add_argument("--calib", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM counters)")
     ap.add_argument("--no-modes", action="store_true", help="skip timing the other precision modes")
+    ap.add_argument("--no-small", action="store_true",
+                    help="orbopt: skip the small molecule run to convergence")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -316,6 +397,8 @@ def main():
         return bench_batch(args)
     if args.workload == "onwarm":
         return bench_onwarm(args)
+    if args.workload == "orbopt":
+        return bench_orbopt(args)
 
     import numpy as np
     import torch

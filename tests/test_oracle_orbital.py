@@ -15,7 +15,8 @@ not come from the oracle itself:
     energy of a normalised two-electron singlet, so it never goes below full
     CI, and at the FCI natural orbitals and ONs it equals full CI (when the
     FCI natural-orbital coefficients have one sign for the strong orbital and
-    the other for all weak ones), with a zero orbital gradient.  Full CI here
+    the other for all weak ones), with a zero orbital gradient; from those
+    orbitals with other ONs the loop's ON step returns to full CI.  Full CI here
     is brute-force diagonalisation in the space of symmetric two-electron
     spatial functions.
 """
@@ -130,6 +131,12 @@ def test_two_electron_full_ci(seed):
         assert abs(r["energy"] - e_fci) <= 1e-12 * abs(e_fci)
         assert np.max(np.abs(r["grad"])) <= 1e-12
         assert loop["converged"] and abs(loop["energies"][-1] - e_fci) <= 1e-12 * abs(e_fci)
+        # same orbitals, wrong ONs: the ON step of the first outer iteration
+        # must bring the energy back to full CI
+        bad = np.full(nb, 0.1 / (nb - 1))
+        bad[0] = 0.9
+        loop2 = orb.outer_loop(inst.b, C0, inst.H, bad, inst.pair_of, 1, nb - 1, 5, 50, 1e-8, 1e-11)
+        assert abs(loop2["energies"][-1] - e_fci) <= 1e-10 * abs(e_fci)
     else:
         assert r["energy"] > e_fci + 1e-6
     assert min(loop["energies"]) >= e_fci - 1e-12 * abs(e_fci)
