@@ -30,7 +30,7 @@ import numpy as np
 __all__ = [
     "half_transform", "mo_transform", "diag_of", "jk_mo", "jk_ao_per_mo",
     "delta_pi", "coefficients", "hpp", "energy", "energy_from_coefficients",
-    "lagrangian", "build",
+    "lagrangian", "lagrangian_direct", "build",
 ]
 
 
@@ -152,6 +152,28 @@ def lagrangian(H, C, occ, Jn, Kn, A, B):
     full[:, :W] = lam
     G = 4.0 * (full - full.T)
     return lam, G
+
+
+def lagrangian_direct(H, C, occ, b_half, b_mo, d, A, B):
+    """The same lambda and G without the per-MO AO matrices.  Since b is
+    symmetric, J^(r) c_q = sum_l d_lr b_half[q][l] and
+    K^(r) c_q = sum_l b_mo[l][r][q] b_half[r][l], so
+
+      Y[:, q] = n_q H c_q + sum_l a_lq b_half[q][l] + sum_{r,l} B_qr b_mo[l][r][q] b_half[r][l]
+      with a_lq = sum_r A_qr d_lr,
+
+    a contraction over (r, l) that never forms an n_bf x n_bf matrix per orbital.
+    """
+    W = occ.shape[0]
+    n_mo = C.shape[1]
+    a = d @ A.T                                              # a[l][q] = sum_r A_qr d_lr
+    YJ = np.einsum("lq,qlm->mq", a, b_half)
+    YK = np.einsum("qr,lrq,rlm->mq", B, b_mo, b_half)
+    Y = occ[None, :] * (H @ C[:, :W]) + YJ + YK
+    lam = C.T @ Y
+    full = np.zeros((n_mo, n_mo))
+    full[:, :W] = lam
+    return lam, 4.0 * (full - full.T)
 
 
 def build(b, C, H, occ, pair_of, n_pairs, functional="pnof7"):

@@ -215,3 +215,25 @@ def test_pnof7_phi_term_vanishes_at_integer_occupations():
     o7 = ri.build(inst.b, inst.C, inst.H, occ, inst.pair_of, inst.n_pairs, "pnof7")
     o5 = ri.build(inst.b, inst.C, inst.H, occ, inst.pair_of, inst.n_pairs, "pnof5")
     assert o7["energy"] == pytest.approx(o5["energy"], rel=1e-15)
+
+
+@pytest.mark.parametrize("shape", [(15, 34, 2, 2, 12), (20, 17, 3, 1, 41), (9, 40, 1, 3, 42)])
+def test_direct_lagrangian_equals_per_mo_route_and_finite_differences(shape):
+    """The gradient path without per-MO AO matrices gives the lambda and G of
+    the J^(n)/K^(n) route, and its G matches finite differences of the energy
+    along orbital rotations (n_mo > n_omega rows included)."""
+    inst = small(*shape)
+    o = ri.build_instance(inst)
+    lam, G = ri.lagrangian_direct(inst.H, inst.C, inst.occ, o["b_half"], o["b_mo"], o["d"], o["A"], o["B"])
+    assert np.max(np.abs(lam - o["lam"])) <= 1e-12 * np.max(np.abs(o["lam"]))
+    assert np.max(np.abs(G - o["grad"])) <= 1e-12 * np.max(np.abs(o["grad"]))
+    n = inst.n_mo
+    rng = np.random.default_rng(shape[-1])
+    for _ in range(3):
+        a, b_ = sorted(rng.choice(n, 2, replace=False))
+        def E(theta):
+            X = np.zeros((n, n)); X[a, b_] = theta; X[b_, a] = -theta
+            return ri.build_instance(inst, C=inst.C @ expm(X))["energy"]
+        h = 1e-4
+        fd = (8 * (E(h) - E(-h)) - (E(2 * h) - E(-2 * h))) / (12 * h)
+        assert abs(fd - G[a, b_]) < 1e-8 * max(1.0, np.max(np.abs(G)))
