@@ -106,19 +106,21 @@ def cpu_baseline(inst, Cs, budget_s=20.0):
             "sample": f"{n} full FP64 builds of the same workload (numpy oracle, rotated C), {el:.1f} s"}
 
 
-def time_builds(ctx, b, Cd, H, occ, pm, inst, prec, steps, warmup, profile=False):
-    """Warm up (autotunes tiles on first use), then time `steps` builds."""
+def time_builds(ctx, b, Cd, H, occ, pm, inst, prec, steps, warmup, profile=False, direct=False):
+    """Warm up (autotunes tiles on first use), then time `steps` builds
+    (rif_build, or rif_build_direct with direct=True)."""
     import torch
+    build = ctx.build_direct if direct else ctx.build
     out = None
     for i in range(max(warmup, 1)):
-        out = ctx.build(b, Cd[i % len(Cd)], H, occ, pm, inst.n_pairs, inst.n_cwo, prec=prec, out=out)
+        out = build(b, Cd[i % len(Cd)], H, occ, pm, inst.n_pairs, inst.n_cwo, prec=prec, out=out)
     ctx.sync()
     if profile:
         ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        out = ctx.build(b, Cd[i % len(Cd)], H, occ, pm, inst.n_pairs, inst.n_cwo, prec=prec, out=out)
+        out = build(b, Cd[i % len(Cd)], H, occ, pm, inst.n_pairs, inst.n_cwo, prec=prec, out=out)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ctx.sync()
@@ -385,6 +387,7 @@ def main():
     ap.add_argument("--calib", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM counters)")
     ap.add_argument("--no-modes", action="store_true", help="skip timing the other precision modes")
+    ap.add_argument("--no-direct", action="store_true", help="skip timing rif_build_direct")
     ap.add_argument("--no-small", action="store_true",
                     help="orbopt: skip the small molecule run to convergence")
     args = ap.parse_args()
@@ -489,6 +492,23 @@ def main():
                            "tflops": round(flops * n2 / el2 / 1e12, 2),
                            "dE_vs_" + args.prec: float(o2["energy"].cpu()[0]) - e_main}
         line["modes"] = modes
+    if not args.no_direct:
+        # the same energy, lambda and G without the per-MO AO matrices
+        el3, o3, prof3 = time_builds(ctx, b, Cd, H, occ, pm, inst, MODES[args.prec], args.steps, args.warmup,
+                                     profile=True, direct=True)
+        od = ctx.build_direct(b, Cd[0], H, occ, pm, inst.n_pairs, inst.n_cwo, prec=MODES[args.prec])
+        om = ctx.build(b, Cd[0], H, occ, pm, inst.n_pairs, inst.n_cwo, prec=MODES[args.prec])
+        ctx.sync()
+        g_m = om["grad"].cpu().numpy()
+        yd = prof3.get("direct_gradient")
+        line["direct_gradient"] = {
+            "builds_s": round(args.steps / el3, 2), "ms_per_build": round(1e3 * el3 / args.steps, 4),
+            "speedup_vs_build": round((args.steps / el3) / builds_s, 3),
+            "dE_vs_build": float(od["energy"].cpu()[0]) - float(om["energy"].cpu()[0]),
+            "grad_rel_vs_build": float(abs(od["grad"].cpu().numpy() - g_m).max() / abs(g_m).max()),
+            "contraction_ms": round(yd[1] / yd[0], 5) if yd else None,
+            "contraction_tflops": round(2.0 * nb * nw * na * nw / (yd[1] / yd[0] * 1e-3) / 1e12, 2) if yd else None,
+        }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(inst, Cs, args.cpu_budget)
     ctx.close()

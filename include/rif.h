@@ -158,6 +158,18 @@ typedef struct rif_instance {
  * in sequence for one molecule (same checks and errors as those calls). */
 rif_status rif_build(rif_ctx *ctx, const rif_instance *inst, rif_prec prec, rif_functional functional);
 
+/* The energy, lambda and G of rif_build without forming the per-MO AO
+ * matrices J^q, K^q (inst->Jn, inst->Kn are not used and may be NULL).  Since
+ * b is symmetric, J^(r) c_q = sum_l d_lr b_half[q][l] and
+ * K^(r) c_q = sum_l b_mo[l][r][q] b_half[r][l], so F^(q) c_q (Sec. II, the
+ * orbital gradient) becomes one contraction over (r, l) of b_half with
+ * coefficients B_qr b_mo[l][r][q], plus sum_l a_lq b_half[q][l] with
+ * a_lq = sum_r A_qr d_lr on its r = q terms: 2 n_aux n_omega^2 n_bf flops in
+ * place of the J^q/K^q build and the F^(q) c_q products.  b_half, b_mo, d,
+ * J, K are written as by rif_build.  Same checks and errors as rif_build,
+ * and RIF_EINVAL unless n_aux * n_omega < 2^31. */
+rif_status rif_build_direct(rif_ctx *ctx, const rif_instance *inst, rif_prec prec, rif_functional functional);
+
 /* Batched builds of many molecules of uneven size.  rif_batch_create checks
  * every instance (as rif_build would), orders them largest first, allocates
  * the batch's own workspace and uploads a work-list per step; it chooses

@@ -73,6 +73,7 @@ EXPORTS = {
     "pnof_energy_grad": (_i, [_vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                               _i, _vp, _vp, _vp]),
     "rif_build": (_i, [_vp, ctypes.POINTER(Instance), _i, _i]),
+    "rif_build_direct": (_i, [_vp, ctypes.POINTER(Instance), _i, _i]),
     "rif_batch_create": (_i, [_vp, _i, ctypes.POINTER(Instance), _i, _i, ctypes.POINTER(_vp)]),
     "rif_batch_run": (_i, [_vp, _i]),
     "rif_batch_destroy": (None, [_vp]),
@@ -268,6 +269,17 @@ class Context:
         self._chk(self.lib.rif_build(self.h, ctypes.byref(inst), prec, functional))
         return out
 
+    def build_direct(self, b, C, H, occ, pair_of, n_pairs, n_cwo, prec=FP64, functional=PNOF7, out=None):
+        """rif_build_direct: energy, lambda and G without the per-MO AO
+        matrices (out has no Jn/Kn)."""
+        n_aux, n_bf, _ = b.shape
+        if out is None:
+            out = self.outputs(n_bf, n_aux, n_pairs, n_cwo, C.shape[1], prec, b.device, per_mo_ao=False)
+        inp = {"b": b, "C": C, "H": H, "occ": occ, "pair_of": pair_of}
+        inst = self.instance(inp, n_pairs, n_cwo, out, prec)
+        self._chk(self.lib.rif_build_direct(self.h, ctypes.byref(inst), prec, functional))
+        return out
+
     def build_steps(self, b, C, H, occ, pair_of, n_pairs, n_cwo, prec=FP64, functional=PNOF7, out=None):
         """The same build as four ABI calls (rif_transform, rif_jk_mo,
         rif_jk_ao_per_mo, pnof_energy_grad) on one stream."""
@@ -283,8 +295,9 @@ class Context:
         return o
 
     # ---- instances and batches ---------------------------------------------
-    def outputs(self, n_bf, n_aux, n_pairs, n_cwo, n_mo, prec=FP64, device="cuda"):
-        """Allocate every output array of one build."""
+    def outputs(self, n_bf, n_aux, n_pairs, n_cwo, n_mo, prec=FP64, device="cuda", per_mo_ao=True):
+        """Allocate every output array of one build (without Jn/Kn if not
+        per_mo_ao)."""
         import torch
         w = n_pairs * (1 + n_cwo)
         dt = torch.float64 if prec == FP64 else torch.float32
@@ -294,8 +307,8 @@ class Context:
                 "d": torch.empty((n_aux, w), dtype=f64, device=device),
                 "J": torch.empty((w, w), dtype=f64, device=device),
                 "K": torch.empty((w, w), dtype=f64, device=device),
-                "Jn": torch.empty((w, n_bf, n_bf), dtype=dt, device=device),
-                "Kn": torch.empty((w, n_bf, n_bf), dtype=dt, device=device),
+                "Jn": torch.empty((w, n_bf, n_bf), dtype=dt, device=device) if per_mo_ao else None,
+                "Kn": torch.empty((w, n_bf, n_bf), dtype=dt, device=device) if per_mo_ao else None,
                 "energy": torch.empty((1,), dtype=f64, device=device),
                 "lam": torch.empty((n_mo, w), dtype=f64, device=device),
                 "grad": torch.empty((n_mo, n_mo), dtype=f64, device=device)}
@@ -316,7 +329,7 @@ class Context:
             _ptr(inp.get("pair_of"), "pair_of", torch.int32, w),
             _ptr(out["b_half"], "b_half", dt, w * n_aux * n_bf), _ptr(out["b_mo"], "b_mo", dt, n_aux * w * w),
             _ptr(out["d"], "d", f64, n_aux * w), _ptr(out["J"], "J", f64, w * w), _ptr(out["K"], "K", f64, w * w),
-            _ptr(out["Jn"], "Jn", dt, w * n_bf * n_bf), _ptr(out["Kn"], "Kn", dt, w * n_bf * n_bf),
+            _ptr(out.get("Jn"), "Jn", dt, w * n_bf * n_bf), _ptr(out.get("Kn"), "Kn", dt, w * n_bf * n_bf),
             _ptr(out["energy"], "energy", f64, 1), _ptr(out["lam"], "lambda", f64, n_mo * w),
             _ptr(out["grad"], "grad", f64, n_mo * n_mo))
 

@@ -113,6 +113,11 @@ struct EnergyArgs {
   int* flag;
 };
 struct FockRedArgs { int nb, nw, nsplit; const double *Yp, *occ, *HC; double* Y; };
+// Gradient without per-MO AO matrices: Y[nu][q] = sum_{k=(r,l)} bh[r][l][nu] X[k][q] with
+// X = Bt[q][r] * (r == q ? Zt[l][q] : bmo[l][r][q]), k = r*n_aux + l, split over k
+// into nsplit ranges of kc; Zt, Bt (the mode's storage type) from k_ydz.
+struct YdzArgs { int na, nw; const double *Ac, *Bc, *d; void *Zt, *Bt; };
+struct YdArgs { int nb, na, nw, nsplit; long kc; const void *bh, *bmo, *Zt, *Bt; double* Yp; };
 struct GradArgs { int nmo, nw, lsplit; const double* lp; double *lam, *G; };
 
 // Half transform, Eq. (12): bh[q][r] = sum_mu C[mu][q] b[l][mu][nu] with the
@@ -455,6 +460,115 @@ __device__ void fock_tile(const FockArgs& a, long t, char* smem) {
   });
 }
 
+// ---- gradient without per-MO AO matrices ---------------------------------------
+// Since b is symmetric, J^(r) c_q = sum_l d_lr bh[q][l] and
+// K^(r) c_q = sum_l bmo[l][r][q] bh[r][l], so
+//   Y[:, q] - n_q H c_q = sum_l a_lq bh[q][l] + sum_{r,l} B_qr bmo[l][r][q] bh[r][l],
+// a_lq = sum_r A_qr d_lr: one contraction over k = (r, l) of b_half with
+// coefficients built from b_mo, with the Coulomb part on the r = q terms:
+//   Zt[l][q] = B_qq d_lq + a_lq,  Bt[q][r] = B_qr (r != q), 1 (r == q).
+// Tiles 0 .. n_aux-1: one per l, d[l][:] staged in LDS, threads over q;
+// then the Bt tiles, 256 entries each.
+constexpr int kYdzLds = 4096;   // n_omega up to this many read d from LDS
+template <int P, class Cfg>
+__host__ __device__ inline long ydz_tiles(const YdzArgs& a) {
+  return (long)a.na + cdiv((long)a.nw * a.nw, 256);
+}
+template <int P, class Cfg>
+__device__ void ydz_tile(const YdzArgs& a, long t, char* smem) {
+  const int nw = a.nw;
+  if (t < a.na) {
+    const int l = (int)t;
+    const double* dl = a.d + (long)l * nw;
+    double* ds = (double*)smem;
+    const bool in_lds = nw <= kYdzLds;
+    if (in_lds)
+      for (int r = threadIdx.x; r < nw; r += 256) ds[r] = dl[r];
+    __syncthreads();
+    const double* dr = in_lds ? ds : dl;
+    for (int q = threadIdx.x; q < nw; q += 256) {
+      // A is symmetric (bitwise: its entries are products of commuting
+      // factors), so row r read along q is coalesced
+      double s = a.Bc[(long)q * nw + q] * dr[q];
+#pragma unroll 8
+      for (int r = 0; r < nw; ++r) s = fma(a.Ac[(long)r * nw + q], dr[r], s);
+      ((IOT<P>*)a.Zt)[(long)l * nw + q] = (IOT<P>)s;
+    }
+  } else {
+    const long j = (t - a.na) * 256 + threadIdx.x;
+    if (j < (long)nw * nw) {
+      const int q = (int)(j / nw), r = (int)(j - (long)q * nw);
+      ((IOT<P>*)a.Bt)[j] = (IOT<P>)(q == r ? 1.0 : a.Bc[j]);
+    }
+  }
+}
+
+template <int P, class Cfg>
+struct YdB {  // element (q, k): value in r[i], coefficient Bt[q][r] in r[R + i]
+  using E = typename EngineOf<P>::type;
+  using T = IOT<P>;
+  using G = XCS<P, T, Cfg::BN, Cfg::NT>;
+  static constexpr int NP = G::NP, R = G::R, RR = 2 * G::R, KV = E::KV, BK = E::BK;
+  using type = T;
+  G g;
+  const T *bmo, *Zt, *Bt;
+  int na, nw, q;
+  long k0, kend;
+  __device__ void init(const T* bmo_, const T* Zt_, const T* Bt_, int na_, int nw_, long k0_, long kend_, int q0) {
+    bmo = bmo_; Zt = Zt_; Bt = Bt_; na = na_; nw = nw_; k0 = k0_; kend = kend_;
+    g.x = threadIdx.x % Cfg::BN; g.kg = threadIdx.x / Cfg::BN;
+    q = q0 + g.x; g.ok = q < nw;
+  }
+  __device__ int xl(int p) const { return g.xl(p); }
+  __device__ int kl(int p) const { return g.kl(p); }
+  __device__ bool valid(int p, int i, int kt) const { return g.ok && k0 + (long)kt * BK + g.kl(p) + i < kend; }
+  __device__ void fetch(int kt, T (&r)[RR]) const {
+    const int qc = g.ok ? q : 0;
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int i = 0; i < KV; ++i) {
+        long k = k0 + (long)kt * BK + g.kl(p) + i;
+        k = k < kend ? k : kend - 1;
+        const int kk = (int)k;   // k < n_aux * n_omega < 2^31
+        const int rr = kk / na, l = kk - rr * na;
+        const T* src = rr == qc ? Zt + (long)l * nw + qc : bmo + ((long)l * nw + rr) * nw + qc;
+        r[p * KV + i] = *src;
+        r[R + p * KV + i] = Bt[(long)qc * nw + rr];
+      }
+  }
+  __device__ double val(const T (&r)[RR], int p, int i) const {
+    return (double)r[R + p * KV + i] * (double)r[p * KV + i];
+  }
+};
+
+template <int P, class Cfg>
+__host__ __device__ inline long yd_tiles(const YdArgs& a) {
+  return (long)cdiv(a.nb, Cfg::BM) * cdiv(a.nw, Cfg::BN) * a.nsplit;
+}
+template <int P, class Cfg>
+__device__ void yd_tile(const YdArgs& a, long t, char* smem) {
+  using E = typename EngineOf<P>::type;
+  using T = IOT<P>;
+  const int nb = a.nb, nw = a.nw;
+  const int nmt = cdiv(nb, Cfg::BM), nnt = cdiv(nw, Cfg::BN);
+  const int mu0 = (int)(t % nmt) * Cfg::BM;
+  const int q0 = (int)((t / nmt) % nnt) * Cfg::BN;
+  const int s = (int)(t / ((long)nmt * nnt));
+  const long K = (long)a.na * nw, k0 = (long)s * a.kc, k1 = min(K, k0 + a.kc);
+  // A: b_half as [(r, l)][nu] (x = nu), rows k0 .. k1 of this split
+  XCS<P, T, Cfg::BM, Cfg::NT> la;
+  la.init((const T*)a.bh + k0 * nb, nb, (int)(k1 - k0), [&](int x, long& o) { o = mu0 + x; return mu0 + x < nb; });
+  YdB<P, Cfg> lb;
+  lb.init((const T*)a.bmo, (const T*)a.Zt, (const T*)a.Bt, a.na, nw, k0, k1, q0);
+  typename E::template Acc<Cfg> acc;
+  gemm_mainloop<E, Cfg>(la, lb, (int)cdiv(k1 - k0, (long)E::BK), acc, smem);
+  double* Y = a.Yp + (long)s * nb * nw;
+  acc.for_each([&](int m, int n, double v) {
+    if (mu0 + m < nb && q0 + n < nw) Y[(long)(mu0 + m) * nw + q0 + n] = v;
+  });
+}
+
 // ---- pre-split of the small reused operands (split-BF16 modes) --------------
 // One thread per pair of k of one row; same split arithmetic as the staging
 // path (split_pair), so a pre-split operand gives the same pieces.
@@ -734,6 +848,8 @@ RIF_STEP_KERNELS(jao, JaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE)
 RIF_STEP_KERNELS(kao, KaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE)
 RIF_STEP_KERNELS(gemm, GemmArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
 RIF_STEP_KERNELS(fock, FockArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
+RIF_STEP_KERNELS(yd, YdArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
+RIF_STEP_KERNELS(ydz, YdzArgs, kYdzLds * 8, 256, false, 1)
 RIF_STEP_KERNELS(jkp, JkArgs, 16, 256, false, 1)
 RIF_STEP_KERNELS(jkr, JkArgs, 16, 256, false, 1)
 RIF_STEP_KERNELS(coef, CoefArgs, 256 * 8, 256, false, 1)
@@ -809,6 +925,9 @@ template <class Cfg> static double useful_kao(const KaoArgs& a) {
   const long nbk = cdiv(a.nb, Cfg::BM);
   return (double)a.nb * (a.nb + 1) / 2 / (nbk * (nbk + 1) / 2 * (double)Cfg::BM * Cfg::BM);
 }
+template <class Cfg> static double useful_yd(const YdArgs& a) {
+  return (double)a.nb * a.nw / ((double)cdiv(a.nb, Cfg::BM) * Cfg::BM * cdiv(a.nw, Cfg::BN) * Cfg::BN);
+}
 template <class Cfg> static double useful_fock(const FockArgs& a) {
   return (double)a.nb * a.nw / ((double)cdiv(a.nb, Cfg::BM) * Cfg::BM * cdiv(a.nw, Cfg::BN) * Cfg::BN);
 }
@@ -847,6 +966,48 @@ RIF_GEMM_STEP(mo, MoArgs, "mo_transform", 4, a.nb, a.na, a.nw, a.nmo)
 RIF_GEMM_STEP(jao, JaoArgs, "jao", 4, a.nb, a.na, a.nw)
 RIF_GEMM_STEP(kao, KaoArgs, "kao", 2, a.nb, a.na, a.nw)
 RIF_GEMM_STEP(fock, FockArgs, "fock", 4, a.nb, a.nw, a.nmo, a.nsplit)
+// The direct contraction has few q (n_omega) and many nu (n_bf) columns: its
+// first variant for the FP64/FP32 engines is a 256x128 16-wave tile, so one
+// tile spans all q of a split (b_half read once) and the b_mo coefficients are
+// re-read only once per 256 nu.
+template <int P>
+struct YdVars {
+  using VS = Vars<EngineOf<P>::type::BK>;
+  using V0 = typename std::conditional<EngineOf<P>::type::BK == 16, TileCfg<256, 128, 16, 64, 32>,
+                                       typename VS::V0>::type;
+  using V1 = typename VS::V1;
+  using V2 = typename VS::V2;
+  using V3 = typename VS::V3;
+};
+template <int P>
+static rif_status step_yd(rif_ctx* c, const YdArgs& a) {
+  auto with = [&](int v, auto&& f) {
+    using YV = YdVars<P>;
+    switch (v) {
+      case 0: return f(typename YV::V0());
+      case 1: return f(typename YV::V1());
+      case 2: return f(typename YV::V2());
+      default: return f(typename YV::V3());
+    }
+  };
+  auto run = [&](int v) {
+    return with(v, [&](auto cfg) {
+      using Cfg = decltype(cfg);
+      hipLaunchKernelGGL((k_yd<P, Cfg>), dim3((unsigned)yd_tiles<P, Cfg>(a)), dim3(Cfg::NT), 0, c->stream, a);
+      return check_launch(c, "direct_gradient");
+    });
+  };
+  const int hv = best_of(4, [&](int v) {
+    return with(v, [&](auto cfg) {
+      using Cfg = decltype(cfg);
+      return est_cost(yd_tiles<P, Cfg>(a), wg_per_cu<P, Cfg>(), Cfg::BM * Cfg::BN, useful_yd<Cfg>(a));
+    });
+  });
+  const int v = pick_variant(c, "direct_gradient", {P, a.nb, a.na, a.nw, a.nsplit}, 4, hv, run);
+  if (v < 0) return RIF_EHIP;
+  ProfScope ps(c, "direct_gradient");
+  return run(v);
+}
 
 // Fixed-shape steps (64x64 FP64 GEMM tiles, 256-thread element-wise tiles).
 using CfgSmall = TileCfg<64, 64, 16, 32, 32>;
@@ -862,6 +1023,12 @@ RIF_FIXED_STEP(coef, CoefArgs, "coef", kF64, Cfg256)
 RIF_FIXED_STEP(energy, EnergyArgs, "energy", kF64, CfgEnergy)
 RIF_FIXED_STEP(fred, FockRedArgs, "fock_reduce", kF64, Cfg256)
 RIF_FIXED_STEP(grad, GradArgs, "grad", kF64, Cfg256)
+template <int P>
+static rif_status step_ydz(rif_ctx* c, const YdzArgs& a) {
+  ProfScope ps(c, "direct_coef");
+  hipLaunchKernelGGL((k_ydz<P, Cfg256>), dim3((unsigned)ydz_tiles<P, Cfg256>(a)), dim3(256), 0, c->stream, a);
+  return check_launch(c, "direct_coef");
+}
 
 rif_status op_gemm_kn(rif_ctx* c, int M, int N, int K, const double* A, long lda, const double* B, long ldb,
                       double* out, long ldo) {
@@ -893,8 +1060,10 @@ static rif_status step1_jk(rif_ctx* c, const JkArgs& a) {
 // ---- workspace plan of one molecule (shared by the single and batched paths)
 struct Plan {
   int nb, na, nw, nmo, npairs, ncwo;
-  int jk_nsplit, fock_nsplit, fock_per, nparts, hc_split, lam_split, small_kc;
+  int jk_nsplit, fock_nsplit, fock_per, nparts, hc_split, lam_split, small_kc, yd_nsplit;
+  long yd_kc;
   size_t o_part, o_hcp, o_hc, o_a, o_b, o_yp, o_y, o_ep, o_lp, o_cs, o_ds, bytes;
+  size_t o_ydp, o_zt, o_bt, bytes_direct;   // the gradient without per-MO AO matrices
   Plan(int nb_, int na_, int npairs_, int ncwo_, int nmo_) {
     nb = nb_; na = na_; npairs = npairs_; ncwo = ncwo_; nmo = nmo_;
     nw = npairs * (1 + ncwo);
@@ -931,6 +1100,19 @@ struct Plan {
     o_cs = cv.take<unsigned short>((size_t)3 * nw * round32(nb));   // C_Omega^T pieces (split modes)
     o_ds = cv.take<unsigned short>((size_t)3 * nw * round32(na));   // d^T pieces (split modes)
     bytes = cv.off;
+    // direct gradient: split-K over (r, l), sized so a 64x64-tile launch has
+    // about 2048 tiles; each split a multiple of 32 deep
+    {
+      const long K = (long)na * nw, t64 = cdiv(nb, 64) * cdiv(nw, 64);
+      const long slices = cdiv(K, 32L);
+      const long ns = std::max(1L, std::min(slices, (long)cdiv(2048L, t64)));
+      yd_kc = 32L * cdiv(slices, ns);
+      yd_nsplit = (int)cdiv(K, yd_kc);
+    }
+    o_ydp = cv.take<double>((size_t)yd_nsplit * nb * nw);
+    o_zt = cv.take<double>((size_t)na * nw);
+    o_bt = cv.take<double>((size_t)w2);
+    bytes_direct = cv.off;
   }
 };
 
@@ -939,6 +1121,7 @@ struct BuildArgs {
   PSplitArgs psc, psd;
   HalfArgs half; MoArgs mo; JkArgs jk; JaoArgs jao; KaoArgs kao;
   GemmArgs hc; CoefArgs coef; EnergyArgs energy; FockArgs fock; FockRedArgs fred; GemmArgs lam; GradArgs grad;
+  YdzArgs ydz; YdArgs yd; FockRedArgs ydred;
 };
 static BuildArgs make_build_args(const Plan& pl, const rif_instance& in, int functional, char* ws, int* flag) {
   BuildArgs A;
@@ -974,6 +1157,12 @@ static BuildArgs make_build_args(const Plan& pl, const rif_instance& in, int fun
   A.lam = GemmArgs{nmo, nw, nb, in.C, (long)nmo, Y, (long)nw, Lp, (long)nw, pl.lam_split, pl.small_kc,
                    (long)nmo * nw};
   A.grad = GradArgs{nmo, nw, pl.lam_split, Lp, in.lambda, in.grad};
+  void* Zt = ws + pl.o_zt;
+  void* Bt = ws + pl.o_bt;
+  double* Ydp = (double*)(ws + pl.o_ydp);
+  A.ydz = YdzArgs{na, nw, Ac, Bc, in.d, Zt, Bt};
+  A.yd = YdArgs{nb, na, nw, pl.yd_nsplit, pl.yd_kc, in.b_half, in.b_mo, Zt, Bt, Ydp};
+  A.ydred = FockRedArgs{nb, nw, pl.yd_nsplit, Ydp, in.occ, HC, Y};
   return A;
 }
 
@@ -1124,20 +1313,72 @@ static rif_status run_build(rif_ctx* c, const BuildArgs& A) {
   return hip(hipStreamWaitEvent(main, e_energy, 0));
 }
 
+// The same energy, lambda and G without J^q/K^q: after the transforms, the
+// coefficients (side stream: H C_Omega, J/K, energy as in run_build), then
+// Zt/Bt, the contraction over (r, l), the fixed-order sum with n_q H c_q,
+// lambda = C^T Y and G.
+template <int P>
+static rif_status run_build_direct(rif_ctx* c, const BuildArgs& A) {
+  hipStream_t main = c->stream, side = c->side;
+  hipEvent_t e_fork = c->ev[0], e_mo = c->ev[1], e_side = c->ev[2], e_coef = c->ev[3], e_energy = c->ev[4];
+  rif_status st;
+  auto hip = [&](hipError_t e) { return e == hipSuccess ? RIF_OK : fail(c, RIF_EHIP, "stream fork/join failed"); };
+  if ((st = hip(hipEventRecord(e_fork, main))) || (st = hip(hipStreamWaitEvent(side, e_fork, 0)))) return st;
+  {
+    OnStream on(c, side);
+    if ((st = step1_gemm(c, A.hc))) return st;
+  }
+  if ((st = step_psplit<P>(c, A.psc)) || (st = step_half<P>(c, A.half)) || (st = step_mo<P>(c, A.mo))) return st;
+  if ((st = hip(hipEventRecord(e_mo, main)))) return st;
+  {
+    OnStream on(c, side);
+    if ((st = hip(hipStreamWaitEvent(side, e_mo, 0))) || (st = step1_jk<P>(c, A.jk)) ||
+        (st = hip(hipEventRecord(e_side, side))))
+      return st;
+  }
+  if ((st = hip(hipStreamWaitEvent(main, e_side, 0))) || (st = step1_coef(c, A.coef)) ||
+      (st = hip(hipEventRecord(e_coef, main))))
+    return st;
+  {
+    OnStream on(c, side);
+    if ((st = hip(hipStreamWaitEvent(side, e_coef, 0))) || (st = step1_energy(c, A.energy)) ||
+        (st = hip(hipEventRecord(e_energy, side))))
+      return st;
+  }
+  if ((st = step_ydz<P>(c, A.ydz)) || (st = step_yd<P>(c, A.yd)) || (st = step1_fred(c, A.ydred)) ||
+      (st = step1_gemm(c, A.lam)) || (st = step1_grad(c, A.grad)))
+    return st;
+  return hip(hipStreamWaitEvent(main, e_energy, 0));
+}
+
+static rif_status ensure_side(rif_ctx* c) {
+  if (c->side) return RIF_OK;
+  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess)
+    return fail(c, RIF_EHIP, "side stream creation failed");
+  for (auto& e : c->ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+      return fail(c, RIF_EHIP, "event creation failed");
+  return RIF_OK;
+}
+
 rif_status op_build(rif_ctx* c, int prec, int functional, const rif_instance& in) {
   if (!prec_ok(prec)) return fail(c, RIF_ENOTSUP, "precision mode not available");
-  if (!c->side) {
-    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess)
-      return fail(c, RIF_EHIP, "side stream creation failed");
-    for (auto& e : c->ev)
-      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
-        return fail(c, RIF_EHIP, "event creation failed");
-  }
-  const Plan pl(in.n_bf, in.n_aux, in.n_pairs, in.n_cwo, in.n_mo);
-  rif_status st = ws_reserve(c, pl.bytes);
+  rif_status st = ensure_side(c);
   if (st) return st;
+  const Plan pl(in.n_bf, in.n_aux, in.n_pairs, in.n_cwo, in.n_mo);
+  if ((st = ws_reserve(c, pl.bytes))) return st;
   const BuildArgs A = make_build_args(pl, in, functional, (char*)c->ws, c->dflag);
   RIF_PREC_SWITCH(prec, run_build<P>(c, A))
+}
+
+rif_status op_build_direct(rif_ctx* c, int prec, int functional, const rif_instance& in) {
+  if (!prec_ok(prec)) return fail(c, RIF_ENOTSUP, "precision mode not available");
+  rif_status st = ensure_side(c);
+  if (st) return st;
+  const Plan pl(in.n_bf, in.n_aux, in.n_pairs, in.n_cwo, in.n_mo);
+  if ((st = ws_reserve(c, pl.bytes_direct))) return st;
+  const BuildArgs A = make_build_args(pl, in, functional, (char*)c->ws, c->dflag);
+  RIF_PREC_SWITCH(prec, run_build_direct<P>(c, A))
 }
 
 // ---------------------------------------------------------------------------

@@ -248,14 +248,14 @@ rif_status pnof_energy_grad(rif_ctx* c, rif_functional fn, int nb, int nmo, int 
                         lambda, grad);
 }
 
-static rif_status check_instance(rif_ctx* c, const rif_instance* in, const char* who) {
+static rif_status check_instance(rif_ctx* c, const rif_instance* in, const char* who, bool need_ao = true) {
   if (!in) return fail(c, RIF_EINVAL, std::string(who) + ": NULL instance");
   const long nw = (long)in->n_pairs * (1 + in->n_cwo);
   if (!dims_ok(in->n_bf) || !dims_ok(in->n_aux) || !dims_ok(in->n_mo) || !dims_ok(in->n_pairs) || in->n_cwo < 1 ||
       nw > in->n_mo || in->n_mo > in->n_bf)
     return fail(c, RIF_EINVAL, std::string(who) + ": need n_pairs (1 + n_cwo) <= n_mo <= n_bf, n_aux > 0");
   if (!in->b || !in->C || !in->H || !in->occ || !in->b_half || !in->b_mo || !in->d || !in->J || !in->K ||
-      !in->Jn || !in->Kn || !in->energy || !in->lambda || !in->grad)
+      (need_ao && (!in->Jn || !in->Kn)) || !in->energy || !in->lambda || !in->grad)
     return fail(c, RIF_EINVAL, std::string(who) + ": NULL pointer");
   return RIF_OK;
 }
@@ -299,6 +299,17 @@ rif_status rif_pnof_optimize(rif_ctx* c, const rif_instance* in, rif_prec prec, 
                                "init_gamma 0 or 1, hist_len >= 0");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
   return op_optimize(c, (int)prec, (int)fn, w, *par, C, occ, gamma, res, hist_e, hist_g, hist_len);
+}
+
+rif_status rif_build_direct(rif_ctx* c, const rif_instance* in, rif_prec prec, rif_functional fn) {
+  if (!c) return RIF_EINVAL;
+  rif_status st = check_instance(c, in, "rif_build_direct", false);
+  if (st) return st;
+  if ((long)in->n_aux * in->n_pairs * (1 + in->n_cwo) >= (1L << 31))
+    return fail(c, RIF_EINVAL, "rif_build_direct: need n_aux * n_omega < 2^31");
+  if (fn != RIF_PNOF7 && fn != RIF_PNOF5) return fail(c, RIF_EINVAL, "rif_build_direct: unknown functional");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  return op_build_direct(c, (int)prec, (int)fn, *in);
 }
 
 struct rif_batch {

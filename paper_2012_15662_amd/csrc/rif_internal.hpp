@@ -110,6 +110,8 @@ rif_status op_adam(rif_ctx* c, int n, float* theta, const float* grad, float* m,
 // a2..a8 of one molecule in one call (inst already validated), with the small
 // independent steps on the context's side stream.
 rif_status op_build(rif_ctx* c, int prec, int functional, const rif_instance& in);
+// The same energy, lambda and G without forming J^q/K^q (in.Jn/in.Kn unused).
+rif_status op_build_direct(rif_ctx* c, int prec, int functional, const rif_instance& in);
 
 // FP64 GEMM out[m][n] = sum_k A[k][m] B[k][n] (row strides lda, ldb, ldo), one pass over k.
 rif_status op_gemm_kn(rif_ctx* c, int M, int N, int K, const double* A, long lda, const double* B, long ldb,
