@@ -2,7 +2,7 @@
 //
 //   k_flam       F^lambda from the Lagrange multipliers (reading below)
 //   k_transpose  64x64 LDS-tiled transpose (FP64)
-//   k_maxabs     max |x| over an array, NaN counted as +inf (one workgroup)
+//   k_maxabs     max |x| over an array, NaN counted as +inf (two passes)
 //   op_orbital_step   F^lambda -> eigenvectors (rocSOLVER dsyevd) -> C <- C V
 //   op_optimize       ON optimisation at fixed orbitals, then inner iterations
 //                     (build -> max|G| -> orbital step) at fixed ONs, repeated
@@ -18,6 +18,7 @@
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -59,20 +60,28 @@ __global__ __launch_bounds__(256) void k_transpose(int R, int Cn, const double* 
   }
 }
 
-__global__ __launch_bounds__(1024) void k_maxabs(long n, const double* __restrict__ x, double* __restrict__ out) {
-  __shared__ double red[1024];
+// max |x|: each of up to kMaxBlocks workgroups writes the max of its strided
+// share, then one workgroup takes the max of those (max is order-free).
+constexpr int kMaxBlocks = 256;
+__global__ __launch_bounds__(256) void k_maxabs(long n, const double* __restrict__ x, double* __restrict__ part,
+                                                double* __restrict__ out) {
+  __shared__ double red[256];
   double m = 0.0;
-  for (long i = threadIdx.x; i < n; i += 1024) {
-    const double v = x[i];
-    m = (v != v) ? INFINITY : fmax(m, fabs(v));
+  if (x) {
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+      const double v = x[i];
+      m = (v != v) ? INFINITY : fmax(m, fabs(v));
+    }
+  } else {
+    for (int i = threadIdx.x; i < (int)n; i += 256) m = fmax(m, part[i]);
   }
   red[threadIdx.x] = m;
   __syncthreads();
-  for (int s = 512; s > 0; s >>= 1) {
+  for (int s = 128; s > 0; s >>= 1) {
     if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = red[0];
+  if (threadIdx.x == 0) (x ? part[blockIdx.x] : out[0]) = red[0];
 }
 
 static rif_status blas_handle(rif_ctx* c, rocblas_handle* h) {
@@ -99,8 +108,10 @@ static rif_status transpose(rif_ctx* c, int R, int Cn, const double* in, long ld
   return check_launch(c, "transpose");
 }
 
-rif_status op_maxabs(rif_ctx* c, long n, const double* x, double* out) {
-  hipLaunchKernelGGL(k_maxabs, dim3(1), dim3(1024), 0, c->stream, n, x, out);
+rif_status op_maxabs(rif_ctx* c, long n, const double* x, double* part, double* out) {
+  const int nblk = (int)std::min((long)kMaxBlocks, std::max(1L, (n + 2047) / 2048));
+  hipLaunchKernelGGL(k_maxabs, dim3(nblk), dim3(256), 0, c->stream, n, x, part, out);
+  hipLaunchKernelGGL(k_maxabs, dim3(1), dim3(256), 0, c->stream, (long)nblk, (const double*)nullptr, part, out);
   return check_launch(c, "maxabs");
 }
 
@@ -193,6 +204,7 @@ rif_status op_optimize(rif_ctx* c, int prec, int fn, const rif_instance& in0, co
   const size_t oWork = cv.take<double>((size_t)on_work_doubles(nw, np_, nc));
   const size_t oX = cv.take<float>((size_t)np_ * 39), oT = cv.take<float>((size_t)np_ * 7);
   const size_t oGmax = cv.take<double>(1), oInfo = cv.take<int>(1), oIt = cv.take<int>(1), oSt = cv.take<int>(1);
+  const size_t oPart = cv.take<double>(kMaxBlocks);
   DevBlock dev;
   if (hipMalloc(&dev.p, cv.off) != hipSuccess) {
     (void)hipGetLastError();
@@ -258,7 +270,7 @@ rif_status op_optimize(rif_ctx* c, int prec, int fn, const rif_instance& in0, co
     for (int inner = 0; inner < par.max_inner; ++inner) {
       hipEventRecord(ev.e[2], c->stream);
       if ((st = op_build(c, prec, fn, in))) return st;
-      if ((st = op_maxabs(c, (long)nmo * nmo, in.grad, gmax))) return st;
+      if ((st = op_maxabs(c, (long)nmo * nmo, in.grad, (double*)D(oPart), gmax))) return st;
       hipEventRecord(ev.e[3], c->stream);
       if ((st = pull(in.energy))) return st;
       res->ms_build += lap(ev.e[2], ev.e[3]);

@@ -118,7 +118,7 @@ rif_status op_gemm_kn(rif_ctx* c, int M, int N, int K, const double* A, long lda
                       double* out, long ldo);
 
 // Orbital optimisation (orbital.hip)
-rif_status op_maxabs(rif_ctx* c, long n, const double* x, double* out);
+rif_status op_maxabs(rif_ctx* c, long n, const double* x, double* part, double* out);
 rif_status op_orbital_step(rif_ctx* c, int nb, int nmo, int nw, const double* lam, const double* eps_in,
                            double* C, double* eps_out, int* info);
 rif_status op_optimize(rif_ctx* c, int prec, int fn, const rif_instance& in, const rif_opt_params& par, double* C,
