@@ -106,21 +106,22 @@ def cpu_baseline(inst, Cs, budget_s=20.0):
             "sample": f"{n} full FP64 builds of the same workload (numpy oracle, rotated C), {el:.1f} s"}
 
 
-def time_builds(ctx, b, Cd, H, occ, pm, inst, prec, steps, warmup, profile=False, direct=False):
+def time_builds(ctx, b, Cd, H, occ, pm, inst, prec, steps, warmup, profile=False, direct=False, b_split=None):
     """Warm up (autotunes tiles on first use), then time `steps` builds
-    (rif_build, or rif_build_direct with direct=True)."""
+    (rif_build, or rif_build_direct with direct=True; b_split: b stored
+    pre-split for this precision)."""
     import torch
     build = ctx.build_direct if direct else ctx.build
     out = None
     for i in range(max(warmup, 1)):
-        out = build(b, Cd[i % len(Cd)], H, occ, pm, inst.n_pairs, inst.n_cwo, prec=prec, out=out)
+        out = build(b, Cd[i % len(Cd)], H, occ, pm, inst.n_pairs, inst.n_cwo, prec=prec, out=out, b_split=b_split)
     ctx.sync()
     if profile:
         ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        out = build(b, Cd[i % len(Cd)], H, occ, pm, inst.n_pairs, inst.n_cwo, prec=prec, out=out)
+        out = build(b, Cd[i % len(Cd)], H, occ, pm, inst.n_pairs, inst.n_cwo, prec=prec, out=out, b_split=b_split)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ctx.sync()
@@ -491,6 +492,14 @@ def main():
             modes[name] = {"builds_s": round(n2 / el2, 2), "speedup": round((n2 / el2) / builds_s, 3),
                            "tflops": round(flops * n2 / el2 / 1e12, 2),
                            "dE_vs_" + args.prec: float(o2["energy"].cpu()[0]) - e_main}
+            if name != "fp64" and MODES[args.prec] == MODES["fp64"]:
+                # b stored once in this mode's pieces (rif_presplit_b); same results
+                bs = ctx.presplit_b(b, pv)
+                el4, _, _ = time_builds(ctx, b, Cd, H, occ, pm, inst, pv, n2, 2, b_split=bs)
+                modes[name]["presplit_b"] = {"builds_s": round(n2 / el4, 2),
+                                             "speedup": round((n2 / el4) / builds_s, 3),
+                                             "bytes": int(bs.numel())}
+                del bs
         line["modes"] = modes
     if not args.no_direct:
         # the same energy, lambda and G without the per-MO AO matrices

@@ -143,7 +143,10 @@ rif_status pnof_energy_grad(rif_ctx *ctx, rif_functional functional, int n_bf, i
 /* One molecule's inputs and outputs for rif_build / rif_batch_create.  Every
  * pointer is a device pointer owned by the caller, with the layouts and
  * element types of the four calls above (b_half, b_mo, Jn, Kn: double for
- * RIF_FP64, float otherwise); pair_of may be NULL (default map). */
+ * RIF_FP64, float otherwise); pair_of may be NULL (default map).
+ * b_split: NULL, or b already split for the precision the build runs in
+ * (rif_presplit_b with that precision); the half transform then reads it in
+ * place of b.  Ignored for RIF_FP64. */
 typedef struct rif_instance {
   int n_bf, n_aux, n_pairs, n_cwo, n_mo;
   const double *b, *C, *H, *occ;
@@ -152,7 +155,20 @@ typedef struct rif_instance {
   double *d, *J, *K;
   void *Jn, *Kn;
   double *energy, *lambda, *grad;
+  const void *b_split;
 } rif_instance;
+
+/* b stored once for a reduced-precision mode (Sec. III: b is computed once
+ * and kept in memory).  RIF_FP32: a float copy in b's layout.  RIF_BF16X3 /
+ * RIF_BF16X6: 2 / 3 bf16 piece planes (the same split arithmetic as the
+ * kernels' staging), plane s at out + s * n_aux * n_bf * ld with
+ * ld = n_bf rounded up to a multiple of 32; element (l*n_bf + nu, mu) of a
+ * plane holds piece s of b[l][nu][mu] (b symmetric in mu, nu), zero from mu =
+ * n_bf up to ld.  rif_presplit_b_bytes gives the size of out (host function,
+ * no GPU call; 0 for RIF_FP64 or bad sizes).  Asynchronous.  RIF_EINVAL for
+ * sizes or NULL pointers, RIF_ENOTSUP for RIF_FP64 and RIF_FP16X3. */
+unsigned long long rif_presplit_b_bytes(int n_bf, int n_aux, rif_prec prec);
+rif_status rif_presplit_b(rif_ctx *ctx, int n_bf, int n_aux, const double *b, rif_prec prec, void *out);
 
 /* One build: rif_transform, rif_jk_mo, rif_jk_ao_per_mo and pnof_energy_grad
  * in sequence for one molecule (same checks and errors as those calls). */

@@ -31,7 +31,7 @@ class Instance(ctypes.Structure):
     """struct rif_instance (include/rif.h)."""
     _fields_ = [(n, ctypes.c_int) for n in ("n_bf", "n_aux", "n_pairs", "n_cwo", "n_mo")] + \
                [(n, ctypes.c_void_p) for n in ("b", "C", "H", "occ", "pair_of", "b_half", "b_mo", "d", "J",
-                                               "K", "Jn", "Kn", "energy", "lambda_", "grad")]
+                                               "K", "Jn", "Kn", "energy", "lambda_", "grad", "b_split")]
 
 
 class OnProblem(ctypes.Structure):
@@ -74,6 +74,8 @@ EXPORTS = {
                               _i, _vp, _vp, _vp]),
     "rif_build": (_i, [_vp, ctypes.POINTER(Instance), _i, _i]),
     "rif_build_direct": (_i, [_vp, ctypes.POINTER(Instance), _i, _i]),
+    "rif_presplit_b_bytes": (ctypes.c_ulonglong, [_i, _i, _i]),
+    "rif_presplit_b": (_i, [_vp, _i, _i, _vp, _i, _vp]),
     "rif_batch_create": (_i, [_vp, _i, ctypes.POINTER(Instance), _i, _i, ctypes.POINTER(_vp)]),
     "rif_batch_run": (_i, [_vp, _i]),
     "rif_batch_destroy": (None, [_vp]),
@@ -257,25 +259,42 @@ class Context:
         return energy, lam, grad
 
     # ---- one build: every hot-path step once -----------------------------
-    def build(self, b, C, H, occ, pair_of, n_pairs, n_cwo, prec=FP64, functional=PNOF7, out=None):
+    def presplit_b(self, b, prec, out=None):
+        """rif_presplit_b: b stored once for a reduced-precision mode (a byte
+        tensor of rif_presplit_b_bytes), to pass as b_split to build calls in
+        that mode."""
+        import torch
+        n_aux, n_bf, _ = b.shape
+        nbytes = int(self.lib.rif_presplit_b_bytes(n_bf, n_aux, prec))
+        if nbytes == 0:
+            raise RifError(-4, "rif_presplit_b: FP32, BF16x3 or BF16x6 only")
+        if out is None:
+            out = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
+        self._chk(self.lib.rif_presplit_b(self.h, n_bf, n_aux, _ptr(b, "b", torch.float64, n_aux * n_bf * n_bf),
+                                          prec, _ptr(out, "out", torch.uint8, nbytes)))
+        return out
+
+    def build(self, b, C, H, occ, pair_of, n_pairs, n_cwo, prec=FP64, functional=PNOF7, out=None, b_split=None):
         """Transform, J/K (MO), J^q/K^q (AO), energy, Lagrangian and gradient in
         one rif_build call.  `out` (a dict from a previous call with the same
-        shapes) is reused to avoid allocations."""
+        shapes) is reused to avoid allocations; `b_split` is presplit_b's
+        result for this `prec` (or None)."""
         n_aux, n_bf, _ = b.shape
         if out is None:
             out = self.outputs(n_bf, n_aux, n_pairs, n_cwo, C.shape[1], prec, b.device)
-        inp = {"b": b, "C": C, "H": H, "occ": occ, "pair_of": pair_of}
+        inp = {"b": b, "C": C, "H": H, "occ": occ, "pair_of": pair_of, "b_split": b_split}
         inst = self.instance(inp, n_pairs, n_cwo, out, prec)
         self._chk(self.lib.rif_build(self.h, ctypes.byref(inst), prec, functional))
         return out
 
-    def build_direct(self, b, C, H, occ, pair_of, n_pairs, n_cwo, prec=FP64, functional=PNOF7, out=None):
+    def build_direct(self, b, C, H, occ, pair_of, n_pairs, n_cwo, prec=FP64, functional=PNOF7, out=None,
+                     b_split=None):
         """rif_build_direct: energy, lambda and G without the per-MO AO
         matrices (out has no Jn/Kn)."""
         n_aux, n_bf, _ = b.shape
         if out is None:
             out = self.outputs(n_bf, n_aux, n_pairs, n_cwo, C.shape[1], prec, b.device, per_mo_ao=False)
-        inp = {"b": b, "C": C, "H": H, "occ": occ, "pair_of": pair_of}
+        inp = {"b": b, "C": C, "H": H, "occ": occ, "pair_of": pair_of, "b_split": b_split}
         inst = self.instance(inp, n_pairs, n_cwo, out, prec)
         self._chk(self.lib.rif_build_direct(self.h, ctypes.byref(inst), prec, functional))
         return out
@@ -331,7 +350,7 @@ class Context:
             _ptr(out["d"], "d", f64, n_aux * w), _ptr(out["J"], "J", f64, w * w), _ptr(out["K"], "K", f64, w * w),
             _ptr(out.get("Jn"), "Jn", dt, w * n_bf * n_bf), _ptr(out.get("Kn"), "Kn", dt, w * n_bf * n_bf),
             _ptr(out["energy"], "energy", f64, 1), _ptr(out["lam"], "lambda", f64, n_mo * w),
-            _ptr(out["grad"], "grad", f64, n_mo * n_mo))
+            _ptr(out["grad"], "grad", f64, n_mo * n_mo), _ptr(inp.get("b_split"), "b_split", torch.uint8))
 
     def build_instance(self, inp, n_pairs, n_cwo, out=None, prec=FP64, functional=PNOF7):
         """One build through rif_build."""

@@ -72,7 +72,13 @@ constexpr int round32(int k) { return (k + 31) / 32 * 32; }
 // per call by the psplit step (PSplitArgs): row q of C_Omega^T or d^T, k
 // contiguous, row length `ld`, planes `ps` elements apart.
 struct Planes { const unsigned short* p; long ps; int ld; };
-struct HalfArgs { int nb, nw, nmo; long nr; const double* b; const double* C; void* bh; Planes Cs; };
+// Bs / bf: b given pre-split (bf16 piece planes with rows r = l*n_bf + nu, or
+// an FP32 copy in b's layout); unset (null) means b is split on load.
+struct HalfArgs { int nb, nw, nmo; long nr; const double* b; const double* C; void* bh; Planes Cs; Planes Bs; const float* bf; };
+// b pre-split once per call: element (r, mu) = b[r*n_bf + mu] (row r = l*n_bf + nu;
+// b symmetric) into the mode's pieces, rows zero-filled from n_bf up to ld;
+// FP32 mode: a float copy.
+struct BSplitArgs { const double* b; long nr; int nb, ld; void* out; long ps; };
 struct MoArgs { int nb, na, nw, nmo; const void* bh; const double* C; void* bmo; double* d; Planes Cs; };
 struct JaoArgs { int nb, na, nw; const double* b; const double* d; void* Jn; Planes Ds; };
 // Pre-split of X (element (x, k) at X[k*sk + x]) into NPC bf16 planes
@@ -127,8 +133,8 @@ template <int P, class Cfg>
 __host__ __device__ inline long half_tiles(const HalfArgs& a) {
   return (long)cdiv(a.nw, Cfg::BM) * cdiv(a.nr, Cfg::BN);
 }
-template <int P, class Cfg>
-__device__ void half_tile(const HalfArgs& a, long t, char* smem) {
+template <int P, class Cfg, bool kBPre>
+__device__ void half_tile_with(const HalfArgs& a, long t, char* smem) {
   using E = typename EngineOf<P>::type;
   const int nqt = cdiv(a.nw, Cfg::BM);
   const int q0 = (int)(t % nqt) * Cfg::BM;
@@ -142,13 +148,24 @@ __device__ void half_tile(const HalfArgs& a, long t, char* smem) {
     la.init(a.Cs.p, a.Cs.ps, a.Cs.ld, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
   else
     la.init(a.C, a.nmo, nb, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
-  // column r = l*n_bf + nu of b[l][mu][nu] at k = mu: x-contiguous within a slab
-  XCS<P, double, Cfg::BN, Cfg::NT> lb;
-  lb.init(a.b, nb, nb, [&](int x, long& o) {
+  // B: column r = l*n_bf + nu of b[l][mu][nu] at k = mu: x-contiguous within a
+  // slab; pre-split: piece-plane row r (k = mu contiguous, b symmetric) or the
+  // FP32 copy at b's offsets
+  auto slab_off = [&](int x, long& o) {
     const long r = r0 + x, l = r / nb;
     o = l * B2 + (r - l * nb);
     return r < nr;
-  });
+  };
+  using LB = typename std::conditional<
+      !kBPre, XCS<P, double, Cfg::BN, Cfg::NT>,
+      typename std::conditional<(kPieces<P> > 0), PCS<P, Cfg::BN, Cfg::NT>, XCS<P, float, Cfg::BN, Cfg::NT>>::type>::type;
+  LB lb;
+  if constexpr (!kBPre)
+    lb.init(a.b, nb, nb, slab_off);
+  else if constexpr (kPieces<P> > 0)
+    lb.init(a.Bs.p, a.Bs.ps, a.Bs.ld, [&](int x, long& o) { o = r0 + x; return r0 + x < nr; });
+  else
+    lb.init(a.bf, nb, nb, slab_off);
   typename E::template Acc<Cfg> acc;
   gemm_mainloop<E, Cfg>(la, lb, cdiv(nb, E::BK), acc, smem);
   acc.for_each([&](int m, int n, double v) {
@@ -156,6 +173,18 @@ __device__ void half_tile(const HalfArgs& a, long t, char* smem) {
     const long r = r0 + n;
     if (q < nw && r < nr) bh[(long)q * nr + r] = (IOT<P>)v;
   });
+}
+// Separate kernels for b split on load (half) and pre-split (halfp), so each
+// keeps its own register budget.
+template <int P, class Cfg>
+__device__ void half_tile(const HalfArgs& a, long t, char* smem) { half_tile_with<P, Cfg, false>(a, t, smem); }
+template <int P, class Cfg>
+__device__ void halfp_tile(const HalfArgs& a, long t, char* smem) { half_tile_with<P, Cfg, true>(a, t, smem); }
+template <int P, class Cfg>
+__host__ __device__ inline long halfp_tiles(const HalfArgs& a) { return half_tiles<P, Cfg>(a); }
+template <int P>
+inline bool b_presplit(const HalfArgs& a) {
+  return P != kF64 && (kPieces<P> > 0 ? a.Bs.p != nullptr : a.bf != nullptr);
 }
 
 // MO transform: rows s = l*n_omega + p, bmo[s][q] = sum_nu bh[p][l][nu] C[nu][q];
@@ -589,6 +618,32 @@ __device__ void psplit_tile(const PSplitArgs& a, long t, char*) {
   for (int s = 0; s < NPC; ++s) *(unsigned*)(a.out + s * a.ps + (long)x * a.ld + k) = pc[s];
 }
 
+template <int P, class Cfg>
+__host__ __device__ inline long bsplit_tiles(const BSplitArgs& a) {
+  return cdiv(a.nr * (kPieces<P> > 0 ? a.ld / 2 : a.nb), 256);
+}
+template <int P, class Cfg>
+__device__ void bsplit_tile(const BSplitArgs& a, long t, char*) {
+  const long i = t * 256 + threadIdx.x;
+  if constexpr (kPieces<P> > 0) {
+    constexpr int NPC = kPieces<P>;
+    const int hl = a.ld / 2;
+    if (i >= a.nr * hl) return;
+    const long x = i / hl;
+    const int k = 2 * (int)(i - x * hl);
+    const double* row = a.b + x * a.nb;
+    const double d0 = k < a.nb ? row[k] : 0.0;
+    const double d1 = k + 1 < a.nb ? row[k + 1] : 0.0;
+    unsigned pc[NPC];
+    split_pair<NPC>(d0, d1, pc);
+    unsigned short* out = (unsigned short*)a.out;
+#pragma unroll
+    for (int s = 0; s < NPC; ++s) *(unsigned*)(out + s * a.ps + x * a.ld + k) = pc[s];
+  } else {
+    if (i < a.nr * a.nb) ((float*)a.out)[i] = (float)a.b[i];
+  }
+}
+
 // ---- element-wise and reduction steps (256-thread tiles) -------------------
 
 // MO J/K partial sums over a contiguous range of l (fixed split), then a
@@ -843,6 +898,7 @@ constexpr int gemm_wpe() {
 #define GEMM_SMEM smem_bytes<typename EngineOf<P>::type, Cfg>()
 #define GEMM_WPE (gemm_wpe<P, Cfg>())
 RIF_STEP_KERNELS(half, HalfArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
+RIF_STEP_KERNELS(halfp, HalfArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
 RIF_STEP_KERNELS(mo, MoArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
 RIF_STEP_KERNELS(jao, JaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE)
 RIF_STEP_KERNELS(kao, KaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE)
@@ -857,6 +913,7 @@ RIF_STEP_KERNELS(energy, EnergyArgs, kEnergySmem, kEnergyThreads, false, 1)
 RIF_STEP_KERNELS(fred, FockRedArgs, 16, 256, false, 1)
 RIF_STEP_KERNELS(grad, GradArgs, 16, 256, false, 1)
 RIF_STEP_KERNELS(psplit, PSplitArgs, 16, 256, false, 1)
+RIF_STEP_KERNELS(bsplit, BSplitArgs, 16, 256, false, 1)
 
 // ---------------------------------------------------------------------------
 // Launchers.  Each GEMM-shaped step exists in four tile variants per mode:
@@ -919,6 +976,7 @@ static int best_of(int nvar, F&& cost) {
 
 // Fraction of each tile that lands on real outputs, per step (for the model).
 template <class Cfg> static double useful_half(const HalfArgs& a) { return (double)a.nw / (cdiv(a.nw, Cfg::BM) * Cfg::BM); }
+template <class Cfg> static double useful_halfp(const HalfArgs& a) { return useful_half<Cfg>(a); }
 template <class Cfg> static double useful_mo(const MoArgs& a) { return (double)a.nw / (cdiv(a.nw, Cfg::BN) * Cfg::BN); }
 template <class Cfg> static double useful_jao(const JaoArgs& a) { return (double)a.nw / (cdiv(a.nw, Cfg::BM) * Cfg::BM); }
 template <class Cfg> static double useful_kao(const KaoArgs& a) {
@@ -962,6 +1020,13 @@ template <class Cfg> static double useful_fock(const FockArgs& a) {
   }
 
 RIF_GEMM_STEP(half, HalfArgs, "half_transform", 4, a.nb, a.nr, a.nw, a.nmo)
+RIF_GEMM_STEP(halfp, HalfArgs, "half_transform_presplit", 4, a.nb, a.nr, a.nw, a.nmo)
+template <int P>
+static rif_status step_half_any(rif_ctx* c, const HalfArgs& a) {
+  if constexpr (P != kF64)
+    if (b_presplit<P>(a)) return step_halfp<P>(c, a);
+  return step_half<P>(c, a);
+}
 RIF_GEMM_STEP(mo, MoArgs, "mo_transform", 4, a.nb, a.na, a.nw, a.nmo)
 RIF_GEMM_STEP(jao, JaoArgs, "jao", 4, a.nb, a.na, a.nw)
 RIF_GEMM_STEP(kao, KaoArgs, "kao", 2, a.nb, a.na, a.nw)
@@ -1123,7 +1188,8 @@ struct BuildArgs {
   GemmArgs hc; CoefArgs coef; EnergyArgs energy; FockArgs fock; FockRedArgs fred; GemmArgs lam; GradArgs grad;
   YdzArgs ydz; YdArgs yd; FockRedArgs ydred;
 };
-static BuildArgs make_build_args(const Plan& pl, const rif_instance& in, int functional, char* ws, int* flag) {
+static BuildArgs make_build_args(const Plan& pl, const rif_instance& in, int prec, int functional, char* ws,
+                                 int* flag) {
   BuildArgs A;
   const int nb = pl.nb, na = pl.na, nw = pl.nw, nmo = pl.nmo;
   double* part = (double*)(ws + pl.o_part);
@@ -1141,7 +1207,13 @@ static BuildArgs make_build_args(const Plan& pl, const rif_instance& in, int fun
   A.psc = PSplitArgs{in.C, (long)nmo, nw, nb, lc, Cs, (long)nw * lc};
   A.psd = PSplitArgs{in.d, (long)nw, nw, na, ldd, Ds, (long)nw * ldd};
   const Planes cs{Cs, (long)nw * lc, lc}, ds{Ds, (long)nw * ldd, ldd};
-  A.half = HalfArgs{nb, nw, nmo, (long)na * nb, in.b, in.C, in.b_half, cs};
+  A.half = HalfArgs{nb, nw, nmo, (long)na * nb, in.b, in.C, in.b_half, cs, Planes{nullptr, 0, 0}, nullptr};
+  if (in.b_split && (prec == RIF_BF16X3 || prec == RIF_BF16X6)) {
+    const int lb = round32(nb);
+    A.half.Bs = Planes{(const unsigned short*)in.b_split, (long)na * nb * lb, lb};
+  } else if (in.b_split && prec == RIF_FP32) {
+    A.half.bf = (const float*)in.b_split;
+  }
   A.mo = MoArgs{nb, na, nw, nmo, in.b_half, in.C, in.b_mo, in.d, cs};
   A.jk = JkArgs{na, nw, pl.jk_nsplit, in.b_mo, in.d, part, in.J, in.K};
   A.jao = JaoArgs{nb, na, nw, in.b, in.d, in.Jn, ds};
@@ -1169,7 +1241,7 @@ static BuildArgs make_build_args(const Plan& pl, const rif_instance& in, int fun
 template <int P>
 static rif_status run_transform(rif_ctx* c, const PSplitArgs& ps, const HalfArgs& h, const MoArgs& m) {
   rif_status st = step_psplit<P>(c, ps);
-  if (st || (st = step_half<P>(c, h))) return st;
+  if (st || (st = step_half_any<P>(c, h))) return st;
   return step_mo<P>(c, m);
 }
 template <int P>
@@ -1258,7 +1330,7 @@ rif_status op_energy_grad(rif_ctx* c, int prec, int functional, int nb, int nmo,
   in.n_bf = nb; in.n_aux = 1; in.n_pairs = npairs; in.n_cwo = ncwo; in.n_mo = nmo;
   in.H = H; in.C = C; in.occ = occ; in.pair_of = pair_of; in.J = (double*)J; in.K = (double*)K;
   in.Jn = (void*)Jn; in.Kn = (void*)Kn; in.energy = energy; in.lambda = lambda; in.grad = grad;
-  const BuildArgs A = make_build_args(pl, in, functional, (char*)c->ws, c->dflag);
+  const BuildArgs A = make_build_args(pl, in, prec, functional, (char*)c->ws, c->dflag);
   RIF_PREC_SWITCH(prec, run_energy_grad<P>(c, A))
 }
 
@@ -1287,7 +1359,7 @@ static rif_status run_build(rif_ctx* c, const BuildArgs& A) {
     OnStream on(c, side);
     if ((st = step1_gemm(c, A.hc))) return st;
   }
-  if ((st = step_psplit<P>(c, A.psc)) || (st = step_half<P>(c, A.half)) || (st = step_mo<P>(c, A.mo))) return st;
+  if ((st = step_psplit<P>(c, A.psc)) || (st = step_half_any<P>(c, A.half)) || (st = step_mo<P>(c, A.mo))) return st;
   if ((st = hip(hipEventRecord(e_mo, main)))) return st;
   {
     OnStream on(c, side);
@@ -1328,7 +1400,7 @@ static rif_status run_build_direct(rif_ctx* c, const BuildArgs& A) {
     OnStream on(c, side);
     if ((st = step1_gemm(c, A.hc))) return st;
   }
-  if ((st = step_psplit<P>(c, A.psc)) || (st = step_half<P>(c, A.half)) || (st = step_mo<P>(c, A.mo))) return st;
+  if ((st = step_psplit<P>(c, A.psc)) || (st = step_half_any<P>(c, A.half)) || (st = step_mo<P>(c, A.mo))) return st;
   if ((st = hip(hipEventRecord(e_mo, main)))) return st;
   {
     OnStream on(c, side);
@@ -1367,8 +1439,39 @@ rif_status op_build(rif_ctx* c, int prec, int functional, const rif_instance& in
   if (st) return st;
   const Plan pl(in.n_bf, in.n_aux, in.n_pairs, in.n_cwo, in.n_mo);
   if ((st = ws_reserve(c, pl.bytes))) return st;
-  const BuildArgs A = make_build_args(pl, in, functional, (char*)c->ws, c->dflag);
+  const BuildArgs A = make_build_args(pl, in, prec, functional, (char*)c->ws, c->dflag);
   RIF_PREC_SWITCH(prec, run_build<P>(c, A))
+}
+
+unsigned long long presplit_b_bytes(int nb, int na, int prec) {
+  const unsigned long long nr = (unsigned long long)na * nb;
+  if (prec == RIF_FP32) return nr * nb * 4ull;
+  if (prec == RIF_BF16X3 || prec == RIF_BF16X6)
+    return (prec == RIF_BF16X3 ? 2ull : 3ull) * nr * (unsigned long long)round32(nb) * 2ull;
+  return 0;
+}
+
+rif_status op_presplit_b(rif_ctx* c, int prec, int nb, int na, const double* b, void* out) {
+  const int ld = round32(nb);
+  const BSplitArgs a{b, (long)na * nb, nb, ld, out, (long)na * nb * ld};
+  ProfScope ps(c, "presplit_b");
+  switch (prec) {
+    case RIF_FP32:
+      hipLaunchKernelGGL((k_bsplit<kF32, Cfg256>), dim3((unsigned)bsplit_tiles<kF32, Cfg256>(a)), dim3(256), 0,
+                         c->stream, a);
+      break;
+    case RIF_BF16X3:
+      hipLaunchKernelGGL((k_bsplit<kBF16x3, Cfg256>), dim3((unsigned)bsplit_tiles<kBF16x3, Cfg256>(a)), dim3(256),
+                         0, c->stream, a);
+      break;
+    case RIF_BF16X6:
+      hipLaunchKernelGGL((k_bsplit<kBF16x6, Cfg256>), dim3((unsigned)bsplit_tiles<kBF16x6, Cfg256>(a)), dim3(256),
+                         0, c->stream, a);
+      break;
+    default:
+      return fail(c, RIF_ENOTSUP, "rif_presplit_b: FP32, BF16x3 or BF16x6 only");
+  }
+  return check_launch(c, "presplit_b");
 }
 
 rif_status op_build_direct(rif_ctx* c, int prec, int functional, const rif_instance& in) {
@@ -1377,7 +1480,7 @@ rif_status op_build_direct(rif_ctx* c, int prec, int functional, const rif_insta
   if (st) return st;
   const Plan pl(in.n_bf, in.n_aux, in.n_pairs, in.n_cwo, in.n_mo);
   if ((st = ws_reserve(c, pl.bytes_direct))) return st;
-  const BuildArgs A = make_build_args(pl, in, functional, (char*)c->ws, c->dflag);
+  const BuildArgs A = make_build_args(pl, in, prec, functional, (char*)c->ws, c->dflag);
   RIF_PREC_SWITCH(prec, run_build_direct<P>(c, A))
 }
 
@@ -1404,7 +1507,8 @@ struct BatchImpl {
   std::vector<int> order;    // molecule indices, largest first
   void* ws = nullptr;        // workspace of all molecules
   std::vector<void*> dev;    // device allocations to free
-  GroupStep psc, psd, half, mo, jkp, jkr, jao, kao, hc, coef, energy, fock, fred, lam, grad;
+  GroupStep psc, psd, half, halfp, mo, jkp, jkr, jao, kao, hc, coef, energy, fock, fred, lam, grad;
+  bool bpre = false;         // every molecule's b pre-split (grouped halfp in place of half)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -1496,6 +1600,7 @@ static void group_offsets(const std::vector<Args>& a, TilesFn tiles, std::vector
   }
 
 RIF_GROUP_SETUP(half, HalfArgs, "g_half_transform", 4)
+RIF_GROUP_SETUP(halfp, HalfArgs, "g_half_transform_presplit", 4)
 RIF_GROUP_SETUP(mo, MoArgs, "g_mo_transform", 4)
 RIF_GROUP_SETUP(jao, JaoArgs, "g_jao", 4)
 RIF_GROUP_SETUP(kao, KaoArgs, "g_kao", 2)
@@ -1587,8 +1692,16 @@ static rif_status batch_setup(BatchImpl* B, const std::vector<BuildArgs>& A) {
     fock.push_back(x.fock); fred.push_back(x.fred); grad.push_back(x.grad);
   }
   rif_status st;
+  int npre = 0;
+  for (auto& h : half) npre += b_presplit<P>(h) ? 1 : 0;
+  if (npre != 0 && npre != (int)half.size())
+    return fail(B->c, RIF_EINVAL, "batch: give b_split for every molecule or for none");
+  B->bpre = npre > 0;
+  if constexpr (P != kF64) {
+    if (B->bpre && (st = setup_halfp<P>(B, half))) return st;
+  }
   if ((st = setup_psc<P>(B, psc)) || (st = setup_psd<P>(B, psd)) ||
-      (st = setup_half<P>(B, half)) || (st = setup_mo<P>(B, mo)) || (st = setup_jkp<P>(B, jk)) ||
+      (!B->bpre && (st = setup_half<P>(B, half))) || (st = setup_mo<P>(B, mo)) || (st = setup_jkp<P>(B, jk)) ||
       (st = setup_jkr<P>(B, jk)) || (st = setup_jao<P>(B, jao)) || (st = setup_kao<P>(B, kao)) ||
       (st = setup_hc(B, hc)) || (st = setup_coef(B, coef)) || (st = setup_energy(B, en)) ||
       (st = setup_fock<P>(B, fock)) || (st = setup_fred(B, fred)) || (st = setup_lam(B, lam)) ||
@@ -1612,7 +1725,10 @@ static rif_status batch_setup(BatchImpl* B, const std::vector<BuildArgs>& A) {
     g.variant = pick_variant(B->c, g.name.c_str(), {P, B->n, key}, g.nvar, hv, run);
     return g.variant < 0 ? RIF_EHIP : RIF_OK;
   };
-  if ((st = choose(B->half, [&](int v) { return launch_half<P>(B, v); }))) return st;
+  if constexpr (P != kF64) {
+    if (B->bpre && (st = choose(B->halfp, [&](int v) { return launch_halfp<P>(B, v); }))) return st;
+  }
+  if (!B->bpre && (st = choose(B->half, [&](int v) { return launch_half<P>(B, v); }))) return st;
   if ((st = choose(B->mo, [&](int v) { return launch_mo<P>(B, v); }))) return st;
   if ((st = choose(B->jao, [&](int v) { return launch_jao<P>(B, v); }))) return st;
   if ((st = choose(B->kao, [&](int v) { return launch_kao<P>(B, v); }))) return st;
@@ -1630,7 +1746,10 @@ static rif_status batch_enqueue(BatchImpl* B) {
     if ((st = launch_##STEP __VA_ARGS__(B, B->STEP.variant))) return st; \
   }
   RIF_G(psc, <P>)
-  RIF_G(half, <P>)
+  if constexpr (P != kF64) {
+    if (B->bpre) RIF_G(halfp, <P>)
+  }
+  if (!B->bpre) RIF_G(half, <P>)
   RIF_G(mo, <P>)
   RIF_G(jkp, <P>)
   RIF_G(jkr, <P>)
@@ -1675,7 +1794,7 @@ rif_status op_batch_create(rif_ctx* c, int prec, int functional, int n, const ri
   }
   std::vector<BuildArgs> A;
   for (int k = 0; k < n; ++k)
-    A.push_back(make_build_args(plans[k], inst[B->order[k]], functional, (char*)B->ws + base[k], c->dflag));
+    A.push_back(make_build_args(plans[k], inst[B->order[k]], prec, functional, (char*)B->ws + base[k], c->dflag));
   rif_status st;
   auto setup = [&]() -> rif_status { RIF_PREC_SWITCH(prec, batch_setup<P>(B, A)) };
   if ((st = setup())) {

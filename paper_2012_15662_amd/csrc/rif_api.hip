@@ -301,6 +301,21 @@ rif_status rif_pnof_optimize(rif_ctx* c, const rif_instance* in, rif_prec prec, 
   return op_optimize(c, (int)prec, (int)fn, w, *par, C, occ, gamma, res, hist_e, hist_g, hist_len);
 }
 
+unsigned long long rif_presplit_b_bytes(int nb, int na, rif_prec prec) {
+  if (!dims_ok(nb) || !dims_ok(na)) return 0;
+  return presplit_b_bytes(nb, na, (int)prec);
+}
+
+rif_status rif_presplit_b(rif_ctx* c, int nb, int na, const double* b, rif_prec prec, void* out) {
+  if (!c) return RIF_EINVAL;
+  if (!dims_ok(nb) || !dims_ok(na)) return fail(c, RIF_EINVAL, "rif_presplit_b: need n_bf > 0 and n_aux > 0");
+  if (!b || !out) return fail(c, RIF_EINVAL, "rif_presplit_b: NULL pointer");
+  if (prec != RIF_FP32 && prec != RIF_BF16X3 && prec != RIF_BF16X6)
+    return fail(c, RIF_ENOTSUP, "rif_presplit_b: FP32, BF16x3 or BF16x6 only");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  return op_presplit_b(c, (int)prec, nb, na, b, out);
+}
+
 rif_status rif_build_direct(rif_ctx* c, const rif_instance* in, rif_prec prec, rif_functional fn) {
   if (!c) return RIF_EINVAL;
   rif_status st = check_instance(c, in, "rif_build_direct", false);

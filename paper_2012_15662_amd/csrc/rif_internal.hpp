@@ -110,6 +110,9 @@ rif_status op_adam(rif_ctx* c, int n, float* theta, const float* grad, float* m,
 // a2..a8 of one molecule in one call (inst already validated), with the small
 // independent steps on the context's side stream.
 rif_status op_build(rif_ctx* c, int prec, int functional, const rif_instance& in);
+// b pre-split for a reduced-precision mode (layouts as in rif.h).
+unsigned long long presplit_b_bytes(int nb, int na, int prec);
+rif_status op_presplit_b(rif_ctx* c, int prec, int nb, int na, const double* b, void* out);
 // The same energy, lambda and G without forming J^q/K^q (in.Jn/in.Kn unused).
 rif_status op_build_direct(rif_ctx* c, int prec, int functional, const rif_instance& in);
 

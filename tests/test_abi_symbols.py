@@ -13,7 +13,8 @@ HEADER = os.path.join(ROOT, "include", "rif.h")
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([a-z_0-9]+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:const\s+)?(?:unsigned\s+)?(?:long\s+)*[A-Za-z_][A-Za-z0-9_]*(?:\s+|\s*\*+\s*)([a-z_0-9]+)\s*\(",
+                       src, flags=re.M)
     return sorted(set(names))
 
 
