@@ -311,7 +311,9 @@ typedef struct rif_opt_result {
   double energy, max_grad, ms_on, ms_build, ms_orbital;
 } rif_opt_result;
 /* inst: buffers and inputs as for rif_build; inst->C and inst->occ are
- * ignored and C, occ used instead.  Device pointers: C [n_bf][n_mo] in/out,
+ * ignored and C, occ used instead.  With inst->Jn or inst->Kn NULL the inner
+ * builds are rif_build_direct's (no per-MO AO matrices), else rif_build's.
+ * Device pointers: C [n_bf][n_mo] in/out,
  * occ [n_omega] in/out, gamma [n_pairs*n_cwo] in/out.  Host pointers: res,
  * and optionally hist_energy / hist_grad, which receive the energy and
  * max|G| of each inner iteration (first hist_len of them).  Blocks until the

@@ -405,13 +405,14 @@ class Context:
 
     def optimize(self, b, C, H, occ, gamma, pair_of, n_pairs, n_cwo, prec=FP64, functional=PNOF7,
                  max_outer=50, max_inner=500, on_max_it=2000, tol_grad=1e-8, tol_energy=1e-10, on_tol=1e-10,
-                 init_gamma=0, hist_len=0, out=None):
+                 init_gamma=0, hist_len=0, out=None, direct=True):
         """rif_pnof_optimize: C, occ and gamma are updated in place.  Returns
         (result dict, per-inner-iteration energies, max|G|) with the histories
-        as lists of at most hist_len entries."""
+        as lists of at most hist_len entries.  direct: inner builds without
+        the per-MO AO matrices (no Jn/Kn buffers)."""
         n_aux, n_bf, _ = b.shape
         if out is None:
-            out = self.outputs(n_bf, n_aux, n_pairs, n_cwo, C.shape[1], prec, b.device)
+            out = self.outputs(n_bf, n_aux, n_pairs, n_cwo, C.shape[1], prec, b.device, per_mo_ao=not direct)
         inp = {"b": b, "C": C, "H": H, "occ": occ, "pair_of": pair_of}
         inst = self.instance(inp, n_pairs, n_cwo, out, prec)
         import torch

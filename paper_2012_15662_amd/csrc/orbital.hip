@@ -5,7 +5,8 @@
 //   k_maxabs     max |x| over an array, NaN counted as +inf (two passes)
 //   op_orbital_step   F^lambda -> eigenvectors (rocSOLVER dsyevd) -> C <- C V
 //   op_optimize       ON optimisation at fixed orbitals, then inner iterations
-//                     (build -> max|G| -> orbital step) at fixed ONs, repeated
+//                     (build -> max|G| -> orbital step) at fixed ONs, repeated;
+//                     the builds skip J^q/K^q when no Jn/Kn buffers are given
 //
 // F^lambda is not printed in the paper; the reading (from the iterative
 // diagonalisation work it cites): off the diagonal
@@ -169,8 +170,11 @@ rif_status op_orbital_step(rif_ctx* c, int nb, int nmo, int nw, const double* la
 namespace {
 struct DevBlock {   // loop state: its own allocation, since every op carves the arena from its start
   void* p = nullptr;
-  ~DevBlock() {
-    if (p) (void)hipFree(p);
+  hipStream_t s = nullptr;
+  ~DevBlock() {   // an error return may leave kernels that use it in the queue
+    if (!p) return;
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(p);
   }
 };
 struct HostBlock {
@@ -206,6 +210,7 @@ rif_status op_optimize(rif_ctx* c, int prec, int fn, const rif_instance& in0, co
   const size_t oGmax = cv.take<double>(1), oInfo = cv.take<int>(1), oIt = cv.take<int>(1), oSt = cv.take<int>(1);
   const size_t oPart = cv.take<double>(kMaxBlocks);
   DevBlock dev;
+  dev.s = c->stream;
   if (hipMalloc(&dev.p, cv.off) != hipSuccess) {
     (void)hipGetLastError();
     return fail(c, RIF_ENOMEM, "hipMalloc of the optimisation state failed");
@@ -269,7 +274,7 @@ rif_status op_optimize(rif_ctx* c, int prec, int fn, const rif_instance& in0, co
     bool inner_ok = false, have_step = false;
     for (int inner = 0; inner < par.max_inner; ++inner) {
       hipEventRecord(ev.e[2], c->stream);
-      if ((st = op_build(c, prec, fn, in))) return st;
+      if ((st = (in.Jn && in.Kn) ? op_build(c, prec, fn, in) : op_build_direct(c, prec, fn, in))) return st;
       if ((st = op_maxabs(c, (long)nmo * nmo, in.grad, (double*)D(oPart), gmax))) return st;
       hipEventRecord(ev.e[3], c->stream);
       if ((st = pull(in.energy))) return st;

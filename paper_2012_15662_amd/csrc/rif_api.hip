@@ -288,7 +288,7 @@ rif_status rif_pnof_optimize(rif_ctx* c, const rif_instance* in, rif_prec prec, 
   rif_instance w = *in;
   w.C = C;
   w.occ = occ;
-  rif_status st = check_instance(c, &w, "rif_pnof_optimize");
+  rif_status st = check_instance(c, &w, "rif_pnof_optimize", false);
   if (st) return st;
   if (fn != RIF_PNOF7 && fn != RIF_PNOF5) return fail(c, RIF_EINVAL, "rif_pnof_optimize: unknown functional");
   if (in->n_cwo > 14) return fail(c, RIF_EINVAL, "rif_pnof_optimize: the ON optimiser takes n_cwo <= 14");

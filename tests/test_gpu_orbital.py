@@ -164,10 +164,11 @@ def fci_two_electrons(h, eri):
     return w[0], (S @ U[:, 0]).reshape(n, n)
 
 
-@pytest.mark.parametrize("seed", [103, 104])
-def test_full_loop_holds_two_electron_full_ci(ctx, seed):
+@pytest.mark.parametrize("seed,direct", [(103, True), (104, True), (103, False)])
+def test_full_loop_holds_two_electron_full_ci(ctx, seed, direct):
     """One pair over all 5 orbitals, started at the FCI natural orbitals and
-    ONs: the GPU loop stays at the full-CI energy."""
+    ONs: the GPU loop stays at the full-CI energy (inner builds with and
+    without the per-MO AO matrices)."""
     nb = 5
     inst = synth.make_instance(nb, 3 * nb, 1, nb - 1, seed)
     print("case two-electron FCI seed", seed, flush=True)
@@ -182,7 +183,7 @@ def test_full_loop_holds_two_electron_full_ci(ctx, seed):
     occ0 = c ** 2
     occ0[0] = 1.0 - np.sum(occ0[1:])
     res, he, hg, C, occ = run_loop(ctx, inst, np.ascontiguousarray(inst.C @ U), occ0, max_outer=5,
-                                   max_inner=50, tol_grad=1e-8, tol_energy=1e-11, on_tol=1e-10)
+                                   max_inner=50, tol_grad=1e-8, tol_energy=1e-11, on_tol=1e-10, direct=direct)
     print("gpu loop", res, "fci", e_fci, flush=True)
     assert res["status"] == 0
     assert abs(res["energy"] - e_fci) <= 1e-11 * abs(e_fci)
