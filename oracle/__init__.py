@@ -14,5 +14,7 @@ Modules:
   mlp       -- the warm-start network: features, forward, backward, Adam.
   orbital   -- orbital optimisation by iterative diagonalisation of F^lambda
                and the outer/inner loop of Fig. 1.
+  metric    -- b from the three-centre integrals and the metric: pivoted
+               symmetric factorisation, block eigenvalue correction, solve.
 """
 from . import pnof7_ri, brute  # noqa: F401
