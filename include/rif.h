@@ -264,6 +264,24 @@ rif_status rif_mlp_backward(rif_ctx *ctx, int rows, const float *X, const float 
 rif_status rif_adam(rif_ctx *ctx, int n, float *theta, const float *grad, float *m, float *v, int step,
                     float lr, float beta1, float beta2, float eps);
 
+/* b from the three-centre integrals and the metric (Sec. II, RI), done once
+ * per molecule: the metric G_kl = (k|l) is factorised as G = P L D L^T P^T
+ * (L unit lower triangular, D block diagonal with 1x1 and 2x2 blocks,
+ * Bunch-Kaufman partial pivoting with alpha = (1 + sqrt 17)/8), the
+ * eigenvalues of each D block below delta are raised to delta (D~), and
+ *   P L D~^(1/2) b^T = T,  T[k][mu nu] = (mu nu|k),
+ * is solved: b^T = D~^(-1/2) L^-1 P^T T.  Then sum_k b^k b^k = T^T G~^-1 T with
+ * G~ = P L D~ L^T P^T (= G if nothing was raised).  Device pointers:
+ *   T [n_aux][n_bf][n_bf] (symmetric in mu, nu), G [n_aux][n_aux] symmetric
+ *   b [n_aux][n_bf][n_bf] out
+ *   optional (NULL to skip): perm [n_aux] (P^T x)[i] = x[perm[i]]; L and D
+ *   [n_aux][n_aux] dense; n_raised: number of raised eigenvalues
+ * delta <= 0 takes 2^-26 * max_k sum_l |G_kl|.  Uses 6 n_aux^2 doubles of the
+ * context arena.  Asynchronous.  RIF_EINVAL for sizes (n_aux < 46341) or NULL
+ * T, G, b. */
+rif_status rif_prepare_b(rif_ctx *ctx, int n_bf, int n_aux, const double *T, const double *G, double delta,
+                         double *b, int *perm, double *L, double *D, int *n_raised);
+
 /* ---- Orbital optimisation and the outer/inner loop ----
  * Sec. II, orbital optimisation with RI: at fixed ONs the natural orbitals are
  * found by repeated diagonalisation of a symmetric matrix F^lambda built from

@@ -89,6 +89,7 @@ EXPORTS = {
     "rif_mlp_backward": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "rif_adam": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _i, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                       ctypes.c_float]),
+    "rif_prepare_b": (_i, [_vp, _i, _i, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp]),
     "rif_orbital_step": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]),
     "rif_pnof_optimize": (_i, [_vp, ctypes.POINTER(Instance), _i, _i, ctypes.POINTER(OptParams), _vp, _vp, _vp,
                                ctypes.POINTER(OptResult), _vp, _vp, _i]),
@@ -389,6 +390,27 @@ class Context:
         import torch
         self._chk(self.lib.rif_on_warmstart(self.h, len(onset.arr), onset.arr,
                                             _ptr(P, "P", torch.float32, onset.rows * 7)))
+
+    # ---- b from the three-centre integrals and the metric --------------------
+    def prepare_b(self, T, G, delta=0.0, b=None, factors=False):
+        """rif_prepare_b: b [n_aux][n_bf][n_bf].  With factors=True also
+        returns perm, L, D (dense) and the number of raised eigenvalues."""
+        import torch
+        n_aux, n_bf, _ = T.shape
+        if b is None:
+            b = torch.empty_like(T)
+        perm = L = D = nr = None
+        if factors:
+            perm = torch.empty(n_aux, dtype=torch.int32, device=T.device)
+            L = torch.empty((n_aux, n_aux), dtype=torch.float64, device=T.device)
+            D = torch.empty((n_aux, n_aux), dtype=torch.float64, device=T.device)
+            nr = torch.zeros(1, dtype=torch.int32, device=T.device)
+        self._chk(self.lib.rif_prepare_b(
+            self.h, n_bf, n_aux, _ptr(T, "T", torch.float64, n_aux * n_bf * n_bf),
+            _ptr(G, "G", torch.float64, n_aux * n_aux), float(delta), _ptr(b, "b", torch.float64, b.numel()),
+            _ptr(perm, "perm", torch.int32, n_aux), _ptr(L, "L", torch.float64, n_aux * n_aux),
+            _ptr(D, "D", torch.float64, n_aux * n_aux), _ptr(nr, "n_raised", torch.int32, 1)))
+        return (b, perm, L, D, nr) if factors else b
 
     # ---- orbital optimisation and the outer/inner loop ----------------------
     def orbital_step(self, lam, C, n_omega, eps_in=None, eps_out=None, info=None):

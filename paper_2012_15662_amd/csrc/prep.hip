@@ -1,0 +1,352 @@
+// Preparation of the three-index factors b from the three-centre integrals
+// T[k][mu][nu] = (mu nu|k) and the metric G_kl = (k|l) (Sec. II, RI): the
+// metric is factorised as G = P L D L^T P^T (L unit lower triangular, D block
+// diagonal with 1x1 and 2x2 blocks, Bunch-Kaufman partial pivoting), each D
+// block's eigenvalues below delta are raised to delta (D~), and
+//   b^T = D~^(-1/2) L^-1 P^T T,
+// i.e. the solution of P L D~^(1/2) b^T = T.  Done once per molecule.
+//
+//   k_rowsum     ||G||_inf (max row sum of |G|), for the default delta
+//   k_bk_init    working copy of G, L = I, perm, step state
+//   k_bk_pivot   one workgroup: the pivot decision at the current column, the
+//                symmetric interchange, the D block and the L column(s)
+//   k_bk_update  trailing update A -= L_k D_k L_k^T (all workgroups)
+//   k_bk_correct D~^(-1/2) per block (2x2 blocks in closed form)
+//   k_linv       X = L^-1 one column step at a time (rank-1 updates)
+//   k_compose    M^T[perm[i]][k] = sum_r D~^(-1/2)[k][r] X[r][i]
+//   then b^T = M T on the FP64 MFMA GEMM.
+//
+// Pivot rule (alpha = (1 + sqrt 17)/8) at column k, with colmax/imax the
+// largest |A_ik| below the diagonal (lowest index on ties) and rowmax the
+// largest off-diagonal |A_{imax,j}| of the trailing row imax: 1x1 at k if
+// |A_kk| >= alpha colmax or |A_kk| rowmax >= alpha colmax^2; else 1x1 at imax
+// if |A_{imax,imax}| >= alpha rowmax; else 2x2 on (k, imax).  Interchanges
+// also swap the rows of the L columns already computed (P L form).
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "rif_internal.hpp"
+
+namespace rif {
+
+namespace {
+constexpr double kAlpha = 0.6403882032022076;   // (1 + sqrt(17)) / 8
+constexpr int kPivThreads = 1024;
+struct BkState { int k, kstep, next; };
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_rowsum(int n, const double* __restrict__ G, double* __restrict__ part) {
+  // one row per thread, then a max over the block; part[blockIdx.x]
+  __shared__ double red[256];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  double s = 0.0;
+  if (i < n)
+    for (int j = 0; j < n; ++j) s += fabs(G[(long)i * n + j]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_delta(int nblk, const double* __restrict__ part, double* __restrict__ del) {
+  // delta = sqrt(2^-52) * max row sum = 2^-26 * ||G||_inf
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += 256) m = fmax(m, part[i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) del[0] = red[0] * 0x1p-26;
+}
+
+__global__ __launch_bounds__(256) void k_bk_init(int n, const double* __restrict__ G, double* __restrict__ A,
+                                                 double* __restrict__ L, double* __restrict__ D,
+                                                 int* __restrict__ perm, int* __restrict__ bsz, BkState* st) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  const long nn = (long)n * n;
+  if (i < nn) {
+    const int r = (int)(i / n), c = (int)(i - (long)r * n);
+    A[i] = G[i];
+    L[i] = r == c ? 1.0 : 0.0;
+    D[i] = 0.0;
+  }
+  if (i < n) { perm[i] = (int)i; bsz[i] = 0; }
+  if (i == 0) { st->k = 0; st->kstep = 0; st->next = 0; }
+}
+
+// Max of |v| with its index (lowest index on ties) over a workgroup.
+__device__ void block_argmax(double& v, int& idx, double* sv, int* si) {
+  const int t = threadIdx.x;
+  sv[t] = v;
+  si[t] = idx;
+  __syncthreads();
+  for (int h = kPivThreads / 2; h > 0; h >>= 1) {
+    if (t < h) {
+      const double a = sv[t], b = sv[t + h];
+      const int ia = si[t], ib = si[t + h];
+      if (b > a || (b == a && ib < ia)) { sv[t] = b; si[t] = ib; }
+    }
+    __syncthreads();
+  }
+  v = sv[0];
+  idx = si[0];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kPivThreads) void k_bk_pivot(int n, double* __restrict__ A, double* __restrict__ L,
+                                                          double* __restrict__ D, int* __restrict__ perm,
+                                                          int* __restrict__ bsz, BkState* st) {
+  __shared__ double sv[kPivThreads];
+  __shared__ int si[kPivThreads];
+  const int t = threadIdx.x;
+  const int k = st->next;
+  if (k >= n) {   // factorisation finished: the update launched after this does nothing
+    if (t == 0) st->kstep = 0;
+    return;
+  }
+  auto a = [&](int i, int j) -> double& { return A[(long)i * n + j]; };
+  // column search below the diagonal
+  double cm = 0.0;
+  int im = n;
+  for (int i = k + 1 + t; i < n; i += kPivThreads) {
+    const double v = fabs(a(i, k));
+    if (v > cm || (v == cm && i < im)) { cm = v; im = i; }
+  }
+  block_argmax(cm, im, sv, si);
+  const double absakk = fabs(a(k, k));
+  int kstep = 1, kp = k;
+  if (k + 1 < n && fmax(absakk, cm) != 0.0 && absakk < kAlpha * cm) {
+    // rowmax: row imax left of the diagonal (columns k..imax-1), column imax
+    // below it (the trailing matrix is symmetric only to rounding)
+    double rm = 0.0;
+    int dummy = 0;
+    for (int j = k + t; j < n; j += kPivThreads)
+      if (j != im) rm = fmax(rm, fabs(j < im ? a(im, j) : a(j, im)));
+    block_argmax(rm, dummy, sv, si);
+    if (absakk * rm >= kAlpha * cm * cm) {
+      kstep = 1; kp = k;
+    } else if (fabs(a(im, im)) >= kAlpha * rm) {
+      kstep = 1; kp = im;
+    } else {
+      kstep = 2; kp = im;
+    }
+  }
+  const int kk = k + kstep - 1;
+  if (kp != kk) {
+    // symmetric interchange: rows kk <-> kp (all columns), then columns
+    for (int j = t; j < n; j += kPivThreads) {
+      const double x = a(kk, j);
+      a(kk, j) = a(kp, j);
+      a(kp, j) = x;
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += kPivThreads) {
+      const double x = a(i, kk);
+      a(i, kk) = a(i, kp);
+      a(i, kp) = x;
+    }
+    for (int j = t; j < k; j += kPivThreads) {   // rows of the L columns already final
+      const double x = L[(long)kk * n + j];
+      L[(long)kk * n + j] = L[(long)kp * n + j];
+      L[(long)kp * n + j] = x;
+    }
+    if (t == 0) {
+      const int x = perm[kk];
+      perm[kk] = perm[kp];
+      perm[kp] = x;
+    }
+    __syncthreads();
+  }
+  if (kstep == 1) {
+    const double d = a(k, k);
+    if (t == 0) { D[(long)k * n + k] = d; bsz[k] = 1; }
+    if (d != 0.0)
+      for (int i = k + 1 + t; i < n; i += kPivThreads) L[(long)i * n + k] = a(i, k) / d;
+  } else {
+    const double e00 = a(k, k), e10 = a(k + 1, k), e11 = a(k + 1, k + 1);
+    const double det = e00 * e11 - e10 * e10;
+    const double i00 = e11 / det, i01 = -e10 / det, i11 = e00 / det;
+    if (t == 0) {
+      D[(long)k * n + k] = e00;
+      D[(long)k * n + k + 1] = e10;
+      D[(long)(k + 1) * n + k] = e10;
+      D[(long)(k + 1) * n + k + 1] = e11;
+      bsz[k] = 2;
+      bsz[k + 1] = 0;
+    }
+    for (int i = k + 2 + t; i < n; i += kPivThreads) {
+      const double x0 = a(i, k), x1 = a(i, k + 1);
+      L[(long)i * n + k] = x0 * i00 + x1 * i01;
+      L[(long)i * n + k + 1] = x0 * i01 + x1 * i11;
+    }
+  }
+  if (t == 0) {
+    st->k = k;
+    st->kstep = kstep;
+    st->next = k + kstep;
+  }
+}
+
+// Trailing update of the step just decided: for i, j >= k + kstep,
+//   1x1: A_ij -= L_ik A_jk;  2x2: A_ij -= L_ik A_jk + L_i,k+1 A_j,k+1.
+__global__ __launch_bounds__(256) void k_bk_update(int n, double* __restrict__ A, const double* __restrict__ L,
+                                                   const BkState* st) {
+  const int k = st->k, s = st->kstep;
+  const int k0 = k + s;
+  if (s == 0 || k0 >= n) return;
+  const long m = n - k0, mm = m * m;
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < mm; e += (long)gridDim.x * 256) {
+    const int i = k0 + (int)(e / m), j = k0 + (int)(e - (e / m) * m);
+    double v = A[(long)i * n + j] - L[(long)i * n + k] * A[(long)j * n + k];
+    if (s == 2) v -= L[(long)i * n + k + 1] * A[(long)j * n + k + 1];
+    A[(long)i * n + j] = v;
+  }
+}
+
+// D~^(-1/2) per block into Dih (dense, zero outside the blocks); counts the
+// raised eigenvalues.
+__global__ __launch_bounds__(256) void k_bk_correct(int n, const double* __restrict__ D,
+                                                    const int* __restrict__ bsz, const double* __restrict__ delta_p,
+                                                    double delta_in, double* __restrict__ Dih,
+                                                    int* __restrict__ nraised) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  const double delta = delta_in > 0.0 ? delta_in : delta_p[0];
+  const int s = bsz[k];
+  if (s == 1) {
+    const double w = D[(long)k * n + k];
+    const double wt = w < delta ? delta : w;
+    if (w < delta) atomicAdd(nraised, 1);
+    Dih[(long)k * n + k] = 1.0 / sqrt(wt);
+  } else if (s == 2) {
+    const double a = D[(long)k * n + k], b = D[(long)(k + 1) * n + k], c = D[(long)(k + 1) * n + k + 1];
+    // eigenvalues and the unit eigenvector (cs, sn) of the larger one
+    const double h = 0.5 * (a - c), r = sqrt(h * h + b * b);
+    const double w1 = 0.5 * (a + c) + r, w2 = 0.5 * (a + c) - r;
+    double cs, sn;
+    if (h >= 0.0) {
+      const double x = h + r;
+      const double nrm = sqrt(x * x + b * b);
+      cs = nrm > 0.0 ? x / nrm : 1.0;
+      sn = nrm > 0.0 ? b / nrm : 0.0;
+    } else {
+      const double y = r - h;
+      const double nrm = sqrt(b * b + y * y);
+      cs = nrm > 0.0 ? b / nrm : 1.0;
+      sn = nrm > 0.0 ? y / nrm : 0.0;
+    }
+    const double t1 = w1 < delta ? delta : w1, t2 = w2 < delta ? delta : w2;
+    if (w1 < delta) atomicAdd(nraised, 1);
+    if (w2 < delta) atomicAdd(nraised, 1);
+    const double f1 = 1.0 / sqrt(t1), f2 = 1.0 / sqrt(t2);
+    // Q = [[cs, -sn], [sn, cs]], Dih = Q diag(f1, f2) Q^T
+    Dih[(long)k * n + k] = cs * cs * f1 + sn * sn * f2;
+    Dih[(long)k * n + k + 1] = cs * sn * (f1 - f2);
+    Dih[(long)(k + 1) * n + k] = cs * sn * (f1 - f2);
+    Dih[(long)(k + 1) * n + k + 1] = sn * sn * f1 + cs * cs * f2;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fill_eye(long nn, int n, double* __restrict__ X, double* __restrict__ Dih) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nn) return;
+  const int r = (int)(i / n), c = (int)(i - (long)r * n);
+  X[i] = r == c ? 1.0 : 0.0;
+  Dih[i] = 0.0;
+}
+
+// Column step k of X = L^-1: X[i][j] -= L[i][k] X[k][j] for i > k, j <= k.
+__global__ __launch_bounds__(256) void k_linv(int n, int k, const double* __restrict__ L, double* __restrict__ X) {
+  const long m = n - k - 1, w = k + 1, mm = m * w;
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < mm; e += (long)gridDim.x * 256) {
+    const int i = k + 1 + (int)(e / w), j = (int)(e - (e / w) * w);
+    X[(long)i * n + j] -= L[(long)i * n + k] * X[(long)k * n + j];
+  }
+}
+
+// M^T[perm[i]][k] = sum_r Dih[k][r] X[r][i] (Dih block diagonal: r in k's block).
+__global__ __launch_bounds__(256) void k_compose(int n, const double* __restrict__ Dih, const int* __restrict__ bsz,
+                                                 const double* __restrict__ X, const int* __restrict__ perm,
+                                                 double* __restrict__ Mt) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)n * n) return;
+  const int k = (int)(e / n), i = (int)(e - (long)k * n);
+  double v = Dih[(long)k * n + k] * X[(long)k * n + i];
+  if (k + 1 < n && bsz[k] == 2) v += Dih[(long)k * n + k + 1] * X[(long)(k + 1) * n + i];
+  if (k > 0 && bsz[k] == 0) v += Dih[(long)k * n + k - 1] * X[(long)(k - 1) * n + i];
+  Mt[(long)perm[i] * n + k] = v;
+}
+
+rif_status op_prepare_b(rif_ctx* c, int nb, int na, const double* T, const double* G, double delta,
+                        double* b, int* perm_out, double* L_out, double* D_out, int* nraised_out) {
+  const int n = na;
+  const long nn = (long)n * n;
+  Carve cv;
+  const size_t oA = cv.take<double>(nn), oL = cv.take<double>(nn), oD = cv.take<double>(nn);
+  const size_t oX = cv.take<double>(nn), oM = cv.take<double>(nn), oDih = cv.take<double>(nn);
+  const size_t oP = cv.take<int>(n), oB = cv.take<int>(n), oS = cv.take<BkState>(1);
+  const size_t oPart = cv.take<double>((size_t)(n + 255) / 256 + 1), oDel = cv.take<double>(1);
+  const size_t oR = cv.take<int>(1);
+  rif_status st = ws_reserve(c, cv.off);
+  if (st) return st;
+  char* w = (char*)c->ws;
+  double *A = (double*)(w + oA), *L = (double*)(w + oL), *D = (double*)(w + oD), *X = (double*)(w + oX);
+  double *Mt = (double*)(w + oM), *Dih = (double*)(w + oDih), *part = (double*)(w + oPart);
+  double* del = (double*)(w + oDel);
+  int *perm = (int*)(w + oP), *bsz = (int*)(w + oB), *nr = (int*)(w + oR);
+  BkState* sp = (BkState*)(w + oS);
+  const unsigned gnn = (unsigned)((nn + 255) / 256);
+  {
+    ProfScope ps(c, "prep_factorise");
+    const int nblk = (n + 255) / 256;
+    hipLaunchKernelGGL(k_rowsum, dim3(nblk), dim3(256), 0, c->stream, n, G, part);
+    // max over the row-sum partials, times sqrt(2^-52), into del
+    hipLaunchKernelGGL(k_delta, dim3(1), dim3(256), 0, c->stream, nblk, part, del);
+    hipLaunchKernelGGL(k_bk_init, dim3(gnn), dim3(256), 0, c->stream, n, G, A, L, D, perm, bsz, sp);
+    if ((st = check_launch(c, "prep_init"))) return st;
+    const unsigned gup = (unsigned)std::min(1024L, (nn + 255) / 256);
+    for (int it = 0; it < n; ++it) {
+      hipLaunchKernelGGL(k_bk_pivot, dim3(1), dim3(kPivThreads), 0, c->stream, n, A, L, D, perm, bsz, sp);
+      hipLaunchKernelGGL(k_bk_update, dim3(gup), dim3(256), 0, c->stream, n, A, L, (const BkState*)sp);
+    }
+    if ((st = check_launch(c, "prep_factorise"))) return st;
+  }
+  {
+    ProfScope ps(c, "prep_correct_invert");
+    hipLaunchKernelGGL(k_fill_eye, dim3(gnn), dim3(256), 0, c->stream, nn, n, X, Dih);
+    if (hipMemsetAsync(nr, 0, sizeof(int), c->stream) != hipSuccess) return fail(c, RIF_EHIP, "hipMemsetAsync failed");
+    hipLaunchKernelGGL(k_bk_correct, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, D, bsz, del,
+                       delta, Dih, nr);
+    for (int k = 0; k + 1 < n; ++k) {
+      const long work = (long)(n - k - 1) * (k + 1);
+      const unsigned g = (unsigned)std::max(1L, std::min(1024L, (work + 255) / 256));
+      hipLaunchKernelGGL(k_linv, dim3(g), dim3(256), 0, c->stream, n, k, L, X);
+    }
+    hipLaunchKernelGGL(k_compose, dim3(gnn), dim3(256), 0, c->stream, n, Dih, bsz, X, perm, Mt);
+    if ((st = check_launch(c, "prep_correct_invert"))) return st;
+  }
+  {
+    ProfScope ps(c, "prep_solve_gemm");
+    // b^T[k][mu nu] = sum_j M[k][j] T[j][mu nu]: A operand M^T (j-major), B = T
+    const long nb2 = (long)nb * nb;
+    if ((st = op_gemm_kn(c, n, (int)nb2, n, Mt, n, T, nb2, b, nb2))) return st;
+  }
+  if (perm_out && hipMemcpyAsync(perm_out, perm, sizeof(int) * n, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return fail(c, RIF_EHIP, "copying perm failed");
+  if (L_out && hipMemcpyAsync(L_out, L, sizeof(double) * nn, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return fail(c, RIF_EHIP, "copying L failed");
+  if (D_out && hipMemcpyAsync(D_out, D, sizeof(double) * nn, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return fail(c, RIF_EHIP, "copying D failed");
+  if (nraised_out && hipMemcpyAsync(nraised_out, nr, sizeof(int), hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return fail(c, RIF_EHIP, "copying the correction count failed");
+  return RIF_OK;
+}
+
+}  // namespace rif

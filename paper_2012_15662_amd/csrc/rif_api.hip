@@ -269,6 +269,16 @@ rif_status rif_build(rif_ctx* c, const rif_instance* in, rif_prec prec, rif_func
   return op_build(c, (int)prec, (int)fn, *in);
 }
 
+rif_status rif_prepare_b(rif_ctx* c, int nb, int na, const double* T, const double* G, double delta, double* b,
+                         int* perm, double* L, double* D, int* nraised) {
+  if (!c) return RIF_EINVAL;
+  if (!dims_ok(nb) || !dims_ok(na) || na > 46340 || (long)nb * nb > (1L << 30))
+    return fail(c, RIF_EINVAL, "rif_prepare_b: need 0 < n_aux <= 46340 and 0 < n_bf^2 < 2^30");
+  if (!T || !G || !b) return fail(c, RIF_EINVAL, "rif_prepare_b: NULL T, G or b");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  return op_prepare_b(c, nb, na, T, G, delta, b, perm, L, D, nraised);
+}
+
 rif_status rif_orbital_step(rif_ctx* c, int nb, int nmo, int nw, const double* lam, const double* eps_in,
                             double* C, double* eps_out, int* info) {
   if (!c) return RIF_EINVAL;

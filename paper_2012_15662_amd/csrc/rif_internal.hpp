@@ -120,6 +120,10 @@ rif_status op_build_direct(rif_ctx* c, int prec, int functional, const rif_insta
 rif_status op_gemm_kn(rif_ctx* c, int M, int N, int K, const double* A, long lda, const double* B, long ldb,
                       double* out, long ldo);
 
+// b from the three-centre integrals and the metric (prep.hip)
+rif_status op_prepare_b(rif_ctx* c, int nb, int na, const double* T, const double* G, double delta, double* b,
+                        int* perm, double* L, double* D, int* nraised);
+
 // Orbital optimisation (orbital.hip)
 rif_status op_maxabs(rif_ctx* c, long n, const double* x, double* part, double* out);
 rif_status op_orbital_step(rif_ctx* c, int nb, int nmo, int nw, const double* lam, const double* eps_in,

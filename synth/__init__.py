@@ -31,7 +31,7 @@ import numpy as np
 
 __all__ = [
     "Instance", "WORKLOADS", "default_pair_map", "make_instance", "make_b",
-    "rotation_sequence", "batch_sizes", "make_batch",
+    "rotation_sequence", "batch_sizes", "make_batch", "make_metric", "make_three_centre",
 ]
 
 # name -> (n_bf, n_aux, n_pairs, n_cwo, seed)
@@ -186,3 +186,29 @@ def make_instance_device(n_bf: int, n_aux: int, n_pairs: int, n_cwo: int, seed: 
          "H": torch.from_numpy(np.ascontiguousarray(H)).to(device), "occ": torch.from_numpy(occ).to(device),
          "pair_of": torch.from_numpy(pair_of.astype(np.int32)).to(device)}
     return t, n_pairs, n_cwo
+
+
+def make_metric(n_aux: int, seed: int, cond: float = 1e10, n_negative: int = 0) -> np.ndarray:
+    """Symmetric metric stand-in G = Q diag(w) Q^T, Q from the QR of a seeded
+    Gaussian matrix, w geometric from 1 down to 1/cond; the last n_negative
+    eigenvalues are replaced by -1e-3/cond (a numerically indefinite metric,
+    as real auxiliary-basis metrics can be)."""
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n_aux, n_aux)))
+    w = np.geomspace(1.0, 1.0 / cond, n_aux)
+    if n_negative:
+        w[-n_negative:] = -1e-3 / cond
+    G = (Q * w) @ Q.T
+    return (G + G.T) / 2
+
+
+def make_three_centre(n_bf: int, n_aux: int, seed: int) -> np.ndarray:
+    """T[k][mu][nu] = (mu nu|k) stand-in: symmetric Gaussian slabs
+    (X + X^T)/2, X ~ N(0, 1/n_bf)."""
+    rng = np.random.default_rng(seed)
+    T = np.empty((n_aux, n_bf, n_bf))
+    for k in range(n_aux):
+        X = rng.standard_normal((n_bf, n_bf)) / np.sqrt(n_bf)
+        T[k] = (X + X.T) / 2
+    return T
+
