@@ -133,3 +133,24 @@ def test_full_size_ill_conditioned_metric(ctx):
     lhs = bm[:, xs].T @ bm[:, xs]
     rhs = Tm[:, xs].T @ np.linalg.solve(Gt, Tm[:, xs])
     assert np.max(np.abs(lhs - rhs)) <= 1e-5 * np.max(np.abs(rhs))
+
+
+def test_prepared_b_feeds_the_build(ctx):
+    """End to end: T, G -> b (rif_prepare_b) -> rif_build, against the oracle's
+    b and build (well-conditioned metric, so b is accurate to rounding)."""
+    import torch
+    from oracle import pnof7_ri as ri
+    nb, na, npair, ncwo = 40, 120, 3, 2
+    G = synth.make_metric(na, 30, cond=1e4)
+    T = synth.make_three_centre(nb, na, 31)
+    inst = synth.make_instance(nb, na, npair, ncwo, 32)
+    bd = ctx.prepare_b(torch.from_numpy(T).cuda(), torch.from_numpy(G).cuda())
+    C, H = torch.from_numpy(inst.C).cuda(), torch.from_numpy(inst.H).cuda()
+    occ, pm = torch.from_numpy(inst.occ).cuda(), torch.from_numpy(inst.pair_of.astype(np.int32)).cuda()
+    out = ctx.build(bd, C, H, occ, pm, npair, ncwo)
+    ctx.sync()
+    b0, _ = mt.prepare_b(T, G)
+    ref = ri.build(b0, inst.C, inst.H, inst.occ, inst.pair_of, npair)
+    assert relerr(host(bd), b0) < 1e-12
+    assert abs(float(host(out["energy"])[0]) - ref["energy"]) <= 1e-10 * abs(ref["energy"])
+    assert relerr(host(out["grad"]), ref["grad"]) < 1e-10
