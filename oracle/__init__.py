@@ -1,7 +1,8 @@
 """FP64 CPU oracle for the RI-PNOF7 hot path.
 
-TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check of the graft
-entry point and the CPU-baseline leg of the benchmark import this package.
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check
+(__graft_entry__.smoke) and the CPU-baseline leg of the benchmark import this
+package.
 The product path (the HIP library and its Python binding) never imports,
 links or executes anything here, and nothing here imports the product.
 

@@ -4,7 +4,7 @@ The occupancy optimisation (Sec. II) is cheap once J and K exist, but it is
 iterative.  A small MLP, trained on data the method itself generates
 (converged ONs of many molecules), predicts each pair's ONs from per-pair
 features of H_pp, J and K.  The prediction becomes the starting point of the
-plain ON optimiser, which remains the judge: it still iterates to
+plain ON optimiser, which still decides the result: it iterates to
 max|dE/dgamma| <= tol from wherever it starts.
 
 Every numerical step runs in librif kernels (J/K, H_pp, features, MLP

@@ -177,6 +177,6 @@ def test_trained_warm_start_cuts_iterations(ctx):
     print("iters cold", it_c.mean(), "warm", it_w.mean(), flush=True)
     assert np.all(st_c == 0) and np.all(st_w == 0)
     assert it_w.mean() < 0.8 * it_c.mean()
-    # same minima (the optimiser is the judge; a different local minimum would show here)
+    # same minima (the optimiser decides where it ends; a different local minimum would show here)
     Ec, Ew = host(te_cold.energy), host(te_warm.energy)
     assert np.mean(np.abs(Ec - Ew) < 1e-9 * np.abs(Ec)) >= 0.9
