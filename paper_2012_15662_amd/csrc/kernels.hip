@@ -142,9 +142,11 @@ __device__ void half_tile_with(const HalfArgs& a, long t, char* smem) {
   const int nb = a.nb, nw = a.nw;
   const long nr = a.nr, B2 = (long)nb * nb;
   IOT<P>* bh = (IOT<P>*)a.bh;
-  // A: C_Omega^T (x = q, k = mu), from piece planes in the split modes
-  typename std::conditional<kPlanesHalfJao<P>, PCS<P, Cfg::BM, Cfg::NT>, XCS<P, double, Cfg::BM, Cfg::NT>>::type la;
-  if constexpr (kPlanesHalfJao<P>)
+  // A: C_Omega^T (x = q, k = mu), from piece planes in the split modes (in
+  // BF16x6 only when b is pre-split too: then neither operand is split here)
+  constexpr bool kAPlanes = kPlanesHalfJao<P> || (kBPre && kPieces<P> > 0);
+  typename std::conditional<kAPlanes, PCS<P, Cfg::BM, Cfg::NT>, XCS<P, double, Cfg::BM, Cfg::NT>>::type la;
+  if constexpr (kAPlanes)
     la.init(a.Cs.p, a.Cs.ps, a.Cs.ld, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
   else
     la.init(a.C, a.nmo, nb, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
