@@ -200,3 +200,27 @@ def test_loop_in_split_bf16x6(ctx):
     print("fp64", r64, "bf16x6", r6, flush=True)
     assert r64["status"] == 0 and r6["status"] == 0
     assert abs(r6["energy"] - r64["energy"]) < 1e-6
+
+
+def test_entry_point_argument_errors(ctx):
+    """Bad arguments are refused with RIF_EINVAL before any launch."""
+    import ctypes
+    import torch
+    import paper_2012_15662_amd as rif
+    inst = synth.make_instance(10, 20, 2, 1, 40)
+    t = to_dev(inst)
+    occ = t["occ"].clone()
+    gamma = torch.zeros(2, dtype=torch.float64, device="cuda")
+    for bad in (dict(max_outer=0), dict(max_inner=0), dict(tol_grad=0.0), dict(on_tol=-1.0), dict(init_gamma=2)):
+        with pytest.raises(rif.RifError) as e:
+            ctx.optimize(t["b"], t["C"].clone(), t["H"], occ, gamma, t["pair_of"], inst.n_pairs, inst.n_cwo, **bad)
+        assert e.value.status == -1, bad
+    lam = torch.zeros((inst.n_mo, inst.occ.size), dtype=torch.float64, device="cuda")
+    # n_omega > n_mo
+    assert ctx.lib.rif_orbital_step(ctx.h, 10, 10, 11, ctypes.c_void_p(lam.data_ptr()), None,
+                                    ctypes.c_void_p(t["C"].data_ptr()), ctypes.c_void_p(lam.data_ptr()), None) == -1
+    # NULL b for the b preparation, FP64 pre-split
+    assert ctx.lib.rif_prepare_b(ctx.h, 4, 4, None, None, 0.0, None, None, None, None, None) == -1
+    assert ctx.lib.rif_presplit_b(ctx.h, 4, 4, ctypes.c_void_p(t["b"].data_ptr()), rif.FP64,
+                                  ctypes.c_void_p(t["b"].data_ptr())) == -4
+    ctx.sync()
