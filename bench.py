@@ -37,7 +37,7 @@ HBM_GBS = 8000.0
 # were taken on: a figure is reported only while those sources are unchanged.
 # The runs and their command lines are in profiles/.
 TRAFFIC = {
-    ("half_transform", "c6h12", "fp64"): {"src": "f22cdf9e913d1b11", "fetch": 1174031027, "write": 348779520,
+    ("half_transform", "c6h12", "fp64"): {"src": "21a6f16958c6ce72", "fetch": 1174048034, "write": 348779520,
                                          "profile": "profiles/fp64_c6h12_counters.md"},
 }
 
