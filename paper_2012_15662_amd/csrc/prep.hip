@@ -37,12 +37,13 @@ struct BkState { int k, kstep, next; };
 }  // namespace
 
 __global__ __launch_bounds__(256) void k_rowsum(int n, const double* __restrict__ G, double* __restrict__ part) {
-  // one row per thread, then a max over the block; part[blockIdx.x]
+  // row sum i of |G| per thread, read as column i (G symmetric) so that the
+  // threads of a wave read consecutive addresses; then a max over the block
   __shared__ double red[256];
   const int i = blockIdx.x * 256 + threadIdx.x;
   double s = 0.0;
   if (i < n)
-    for (int j = 0; j < n; ++j) s += fabs(G[(long)i * n + j]);
+    for (int j = 0; j < n; ++j) s += fabs(G[(long)j * n + i]);
   red[threadIdx.x] = s;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
