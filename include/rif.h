@@ -301,12 +301,32 @@ rif_status rif_prepare_b(rif_ctx *ctx, int n_bf, int n_aux, const double *T, con
  *   C       [n_bf][n_mo] in/out: replaced by C V, V the eigenvectors
  *   eps_out [n_mo] eigenvalues, ascending (may be eps_in)
  *   info    device int or NULL: 0, or the eigensolver's failure count
- * The eigen-decomposition is rocSOLVER's dsyevd on the context's stream with
- * its workspace in the context arena; the rotation is an FP64 MFMA GEMM.
- * Asynchronous.  RIF_EINVAL: need 0 < n_omega <= n_mo <= n_bf, non-NULL
- * lambda, C and eps_out. */
+ * The eigen-decomposition runs on the context's stream with its workspace in
+ * the context arena (solver chosen by rif_set_eigensolver); the rotation is an
+ * FP64 MFMA GEMM.  info = -1 reports a timed-out wait inside the tridiagonal
+ * reduction (the result is then invalid).  Asynchronous.  RIF_EINVAL: need
+ * 0 < n_omega <= n_mo <= n_bf, non-NULL lambda, C and eps_out. */
 rif_status rif_orbital_step(rif_ctx *ctx, int n_bf, int n_mo, int n_omega, const double *lambda,
                             const double *eps_in, double *C, double *eps_out, int *info);
+
+/* Eigensolver of the orbital step (and of rif_pnof_optimize), per context:
+ *   RIF_EIG_TRD    Householder reduction to tridiagonal form T = Q^T F Q in ONE
+ *                  cooperative launch (rows of F and of Q held in LDS across
+ *                  `groups` workgroups, which exchange v and p of each column
+ *                  through polled single-write slots), then rocSOLVER dstedc
+ *                  (divide and conquer on T) and C <- (C Q) Z as two FP64 MFMA
+ *                  GEMMs.  Needs the rows of F and Q to fit 150 KB of LDS per
+ *                  workgroup with at most 256 workgroups, one per CU (n_mo up
+ *                  to about 1200); the orbital step returns RIF_ENOTSUP
+ *                  otherwise.
+ *   RIF_EIG_SYEVD  rocSOLVER dsyevd (its own blocked reduction).
+ *   RIF_EIG_AUTO   TRD where it fits, else SYEVD (the default).
+ * groups: workgroups of the reduction, 0 for the default (about six rows
+ * each, at least 16 workgroups, more where the rows do not fit).  Results of the two solvers agree to rounding,
+ * eigenvectors up to sign.  RIF_EINVAL for an unknown kind or groups outside
+ * [0, 4096]. */
+typedef enum { RIF_EIG_AUTO = 0, RIF_EIG_SYEVD = 1, RIF_EIG_TRD = 2 } rif_eigensolver;
+rif_status rif_set_eigensolver(rif_ctx *ctx, int kind, int groups);
 
 /* Fig. 1 loop.  Each outer iteration: J, K (MO) and H_pp at the current
  * orbitals, then the ON optimisation (rif_on_optimize's L-BFGS, from the

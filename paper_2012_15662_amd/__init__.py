@@ -16,7 +16,7 @@ import os
 
 __all__ = [
     "Context", "Batch", "Instance", "OnProblem", "OnSet", "OptParams", "OptResult", "RifError", "load_library", "LIB_PATH", "FP64", "FP32", "BF16X3", "BF16X6",
-    "FP16X3", "PNOF7", "PNOF5", "EXPORTS",
+    "FP16X3", "PNOF7", "PNOF5", "EIG_AUTO", "EIG_SYEVD", "EIG_TRD", "EXPORTS",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(HERE, "librif.so")
 
 FP64, FP32, BF16X3, BF16X6, FP16X3 = 0, 1, 2, 3, 4
 PNOF7, PNOF5 = 0, 1
+EIG_AUTO, EIG_SYEVD, EIG_TRD = 0, 1, 2
 _STATUS = {0: "RIF_OK", -1: "RIF_EINVAL", -2: "RIF_ENOMEM", -3: "RIF_EHIP", -4: "RIF_ENOTSUP"}
 
 _vp, _i, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
@@ -91,6 +92,7 @@ EXPORTS = {
                       ctypes.c_float]),
     "rif_prepare_b": (_i, [_vp, _i, _i, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp]),
     "rif_orbital_step": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]),
+    "rif_set_eigensolver": (_i, [_vp, _i, _i]),
     "rif_pnof_optimize": (_i, [_vp, ctypes.POINTER(Instance), _i, _i, ctypes.POINTER(OptParams), _vp, _vp, _vp,
                                ctypes.POINTER(OptResult), _vp, _vp, _i]),
     "rif_autotune": (_i, [_vp, _i]),
@@ -413,6 +415,11 @@ class Context:
         return (b, perm, L, D, nr) if factors else b
 
     # ---- orbital optimisation and the outer/inner loop ----------------------
+    def set_eigensolver(self, kind=EIG_AUTO, groups=0):
+        """rif_set_eigensolver: EIG_TRD (one-launch tridiagonal reduction, then
+        rocSOLVER dstedc/dormtr), EIG_SYEVD (rocSOLVER dsyevd) or EIG_AUTO."""
+        self._chk(self.lib.rif_set_eigensolver(self.h, int(kind), int(groups)))
+
     def orbital_step(self, lam, C, n_omega, eps_in=None, eps_out=None, info=None):
         """One rif_orbital_step: C (in place) <- C V; returns eps_out."""
         import torch

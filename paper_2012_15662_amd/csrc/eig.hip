@@ -1,0 +1,299 @@
+// Tridiagonal reduction of the orbital step's symmetric eigenproblem in one
+// launch (the diagonalisation of F^lambda, Sec. II and Fig. 1).
+//
+// F = Q T Q^T by Householder reflections, Q = H_0 H_1 ... H_{n-2},
+// H_k = I - tau_k v_k v_k^T, v_k zero above index k+1 and one at k+1; T is
+// tridiagonal with diagonal d and off-diagonal e.  Step k, with A the current
+// matrix (trailing rows and columns k+1..n-1 still to be reduced):
+//   x = A[k+1:, k];  beta = -sign(x_0) |x|;  tau = (beta - x_0) / beta;
+//   v = (1, x_1.. / (x_0 - beta));  e_k = beta  (tau = 0 and e_k = x_0 when
+//   x_1.. vanish: H_k = I)
+//   p = tau A v;  w = p - (tau/2)(p^T v) v;  A <- A - v w^T - w v^T  (= H A H)
+//   Q <- Q H_k, row by row: q <- q - tau (q . v) v^T.
+// The rank-2 form of H A H is the textbook one (Golub and Van Loan, Sec. 8.3).
+// The reduction is latency-bound at the orbital step's sizes (n of a few
+// hundred: ~1 MB of FP64), so it runs as ONE cooperative launch instead of a
+// few kernels per column.  Row i of F and row i of Q live in the LDS of
+// workgroup i mod G for the whole reduction.  Per column:
+//   phase A  the owner of row k forms v_k, d_k, e_k, tau_k and publishes v_k
+//            (tau_k in the slot of v_k's unit entry)
+//   phase B  every workgroup forms p_i = tau_k (A v_k)_i for its rows and
+//            publishes them, then applies H_k to its rows of Q (which needs
+//            nothing from other workgroups and covers the wait for p)
+//   phase C  every workgroup reads all of p, forms p^T v itself (the same
+//            fixed-order sum in every wave of every workgroup, so all hold the
+//            same w), and updates its rows; the owner of row k+1 updates that
+//            row first and runs phase A of the next column before its other rows
+// Q is formed here so that the back-transformation of T's eigenvectors is one
+// GEMM instead of a sequence of reflector applications.
+// Workgroups exchange data without barriers or cache flushes: every published
+// value has its own slot per column (v_k and p_k), filled beforehand with a
+// signalling-NaN pattern that no arithmetic result takes (results of
+// arithmetic on NaNs are quiet NaNs), written once with an agent-scope atomic
+// store and read by polling it with agent-scope atomic loads until it no
+// longer holds that pattern.  Each value carries its own readiness, so no
+// ordering between different values is needed.  Every wait is bounded: past
+// the poll limit, or once another workgroup has flagged a timeout, the
+// workgroup flags it and returns, so every wave exits.  Within a workgroup the
+// waves share out the rows (wave w takes rows t0 + w, t0 + w + 4, ..., t0 the
+// first row still active), every reduction is formed whole in each wave, and v
+// and p are double-buffered by the parity of k, so the only workgroup barriers
+// are the two that end each wait (and one in the owner before phase A).
+#include <algorithm>
+#include <string>
+
+#include "rif_internal.hpp"
+
+namespace rif {
+
+namespace {
+constexpr int kTrdThreads = 256;
+constexpr int kTrdWaves = kTrdThreads / 64;
+constexpr size_t kTrdLds = 150 * 1024;        // dynamic LDS per workgroup, at most
+constexpr size_t kTrdLdsDefault = 64 * 1024;  // beyond this the kernel needs the attribute raised
+constexpr long kTrdSpinLimit = 1L << 22;      // polls of one value before it gives up
+constexpr unsigned long long kEmpty = 0x7FF4C0FFEE5E7F11ull;   // signalling NaN
+
+struct TrdArgs {
+  int n, G;
+  const double* F;        // [n][n] symmetric
+  double* Q;              // [n][n] out, row-major
+  double *d, *e;          // [n], [n-1] out
+  double* Vb;             // [n][n] v_k in row k, tau_k at k+1  (slots, kEmpty at launch)
+  double* Pb;             // [n][n] p_k in row k
+  int* err;               // set when a wait timed out
+};
+
+// Sum over the 64 lanes (all active), the same bits in every lane and every
+// call: within each row of 16 lanes by DPP moves (swap neighbours, swap
+// pairs, rotate by 4, rotate by 8), then the four row sums read from lanes 0,
+// 16, 32, 48 and added in that order.
+template <int kCtrl>
+__device__ __forceinline__ double dpp_move(double x) {
+  const long long u = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)u, kCtrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), kCtrl, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_value(double x, int l) {
+  const long long u = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)u, l), hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum(double x) {
+  x += dpp_move<0xB1>(x);    // quad_perm [1,0,3,2]
+  x += dpp_move<0x4E>(x);    // quad_perm [2,3,0,1]
+  x += dpp_move<0x124>(x);   // row_ror:4
+  x += dpp_move<0x128>(x);   // row_ror:8
+  return (lane_value(x, 0) + lane_value(x, 16)) + (lane_value(x, 32) + lane_value(x, 48));
+}
+
+__device__ __forceinline__ void put(double* p, double v) {
+  __hip_atomic_store((unsigned long long*)p, (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long peek(const double* p) {
+  return __hip_atomic_load((unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// The value of slot p once written; false past the poll limit or once another
+// workgroup has flagged a timeout.
+__device__ bool take(const double* p, unsigned long long u, double& out, const int* err) {
+  for (long s = 0; u == kEmpty; ++s) {
+    if (s >= kTrdSpinLimit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    __builtin_amdgcn_s_sleep(1);
+    u = peek(p);
+  }
+  out = __longlong_as_double((long long)u);
+  return true;
+}
+// dst[j] = slot src[j] for j in [j0, j1), two loads in flight per thread
+__device__ bool take_range(const double* src, double* dst, int j0, int j1, const int* err) {
+  for (int j = j0 + (int)threadIdx.x; j < j1; j += 2 * kTrdThreads) {
+    const int j2 = j + kTrdThreads;
+    const unsigned long long u1 = peek(src + j), u2 = j2 < j1 ? peek(src + j2) : 0ull;
+    double x;
+    if (!take(src + j, u1, x, err)) return false;
+    dst[j] = x;
+    if (j2 < j1) {
+      if (!take(src + j2, u2, x, err)) return false;
+      dst[j2] = x;
+    }
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(kTrdThreads) void k_trd(TrdArgs a) {
+  extern __shared__ double sm[];
+  const int n = a.n, G = a.G, g = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int R = g < n ? (n - g + G - 1) / G : 0;   // rows i = g + G t, t < R
+  double* rows = sm;                                // [R][n] rows of A
+  double* qrows = rows + (long)R * n;               // [R][n] rows of Q
+  double* vbuf = qrows + (long)R * n;               // [2][n] v_k by parity of k
+  double* pbuf = vbuf + 2L * n;                     // [2][n] p_k by parity of k
+  for (long x = tid; x < (long)R * n; x += kTrdThreads) {
+    const int t = (int)(x / n), j = (int)(x - (long)t * n);
+    rows[x] = a.F[(long)(g + G * t) * n + j];
+    qrows[x] = j == g + G * t ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // phase A for column k, by the owner of row k (every wave forms the same
+  // |x_1..|^2 in the same order, so no workgroup barrier is needed)
+  auto reflect = [&](int k) {
+    const double* rk = rows + (long)(k / G) * n;
+    const int m0 = k + 1;
+    double ss = 0.0;
+    for (int j = k + 2 + lane; j < n; j += 64) ss += rk[j] * rk[j];
+    ss = wave_sum(ss);
+    const double alpha = rk[m0];
+    double beta = alpha, tau = 0.0, scale = 0.0;
+    if (ss != 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    double* Vk = a.Vb + (long)k * n;
+    for (int j = m0 + tid; j < n; j += kTrdThreads) put(Vk + j, j == m0 ? tau : rk[j] * scale);
+    if (tid == 0) {
+      a.d[k] = rk[k];
+      a.e[k] = beta;
+    }
+  };
+  if (g == 0) reflect(0);
+  for (int k = 0; k + 1 < n; ++k) {
+    const int m0 = k + 1;
+    const int t0 = m0 > g ? (m0 - g + G - 1) / G : 0;   // first row of A held here at or past m0
+    double* v = vbuf + (long)(k & 1) * n;
+    double* p = pbuf + (long)(k & 1) * n;
+    {
+      const bool ok = take_range(a.Vb + (long)k * n, v, m0, n, a.err);
+      if (!ok) atomicExch(a.err, 1);
+      if (__syncthreads_or(!ok)) return;
+    }
+    const double tau = v[m0];
+    auto vv = [&](int j) { return j == m0 ? 1.0 : v[j]; };
+    // phase B: p_i = tau sum_j A_ij v_j for the rows held here
+    double* Pk = a.Pb + (long)k * n;
+    for (int t = t0 + wv; t < R; t += kTrdWaves) {
+      const double* r = rows + (long)t * n;
+      double s = 0.0;
+      for (int j = m0 + lane; j < n; j += 64) s += r[j] * vv(j);
+      s = wave_sum(s);
+      if (lane == 0) put(Pk + g + G * t, tau * s);
+    }
+    // Q <- Q H_k on the rows of Q held here
+    for (int t = wv; t < R; t += kTrdWaves) {
+      double* q = qrows + (long)t * n;
+      double s = 0.0;
+      for (int j = m0 + lane; j < n; j += 64) s += q[j] * vv(j);
+      s = tau * wave_sum(s);
+      for (int j = m0 + lane; j < n; j += 64) q[j] -= s * vv(j);
+    }
+    if (t0 >= R) continue;   // no rows of A left here: p is not needed
+    // phase C: p^T v, w = p - (tau/2)(p^T v) v, A <- A - v w^T - w v^T on the rows held here
+    {
+      const bool ok = take_range(Pk, p, m0, n, a.err);
+      if (!ok) atomicExch(a.err, 1);
+      if (__syncthreads_or(!ok)) return;
+    }
+    double pv = 0.0;
+    for (int j = m0 + lane; j < n; j += 64) pv += p[j] * vv(j);
+    const double K = 0.5 * tau * wave_sum(pv);
+    auto update = [&](int t) {
+      double* r = rows + (long)t * n;
+      const int i = g + G * t;
+      const double vi = vv(i), wi = p[i] - K * vi;
+      for (int j = m0 + lane; j < n; j += 64) {
+        const double vj = vv(j);
+        r[j] -= vi * (p[j] - K * vj) + wi * vj;
+      }
+    };
+    const int kn = k + 1;
+    const bool next = kn + 1 < n && kn % G == g;   // this workgroup reflects column k+1
+    const int tn = next ? kn / G : -1;
+    if (next) {
+      if (wv == tn % kTrdWaves) update(tn);
+      __syncthreads();
+      reflect(kn);
+    }
+    for (int t = t0 + wv; t < R; t += kTrdWaves)
+      if (t != tn) update(t);
+  }
+  __syncthreads();
+  for (long x = tid; x < (long)R * n; x += kTrdThreads) {
+    const int t = (int)(x / n), j = (int)(x - (long)t * n);
+    a.Q[(long)(g + G * t) * n + j] = qrows[x];
+  }
+  if ((n - 1) % G == g && tid == 0) a.d[n - 1] = rows[(long)((n - 1) / G) * n + (n - 1)];
+}
+
+// slots to kEmpty, the timeout flag to zero
+__global__ __launch_bounds__(256) void k_trd_reset(unsigned long long* slots, long count, int* err) {
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < count; i += (long)gridDim.x * 256) slots[i] = kEmpty;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *err = 0;
+}
+
+size_t trd_lds(int n, int G) {
+  const long R = (n + G - 1) / G;
+  return (size_t)(2 * R * n + 4L * n) * sizeof(double);
+}
+long trd_slots(int n) { return 2L * n * n; }
+}  // namespace
+
+int trd_groups(rif_ctx* c, int n, int want) {
+  if (n < 2) return 0;
+  int ncu = 0, coop = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
+      hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device) != hipSuccess || !coop) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  // `want` workgroups if given, else about six rows each (at least 16
+  // workgroups); more if the rows do not fit the LDS budget; at most one per
+  // CU and one per row
+  const int gmax = std::min(ncu, n);
+  int G = want > 0 ? want : std::max(std::min(16, n), (n + 5) / 6);
+  G = std::min(G, gmax);
+  while (G <= gmax && trd_lds(n, G) > kTrdLds) ++G;
+  return G <= gmax ? G : 0;
+}
+
+size_t trd_scratch_bytes(int n) { return (size_t)trd_slots(n) * sizeof(double); }
+
+rif_status op_trd(rif_ctx* c, int n, int G, const double* F, double* Q, double* d, double* e, void* scratch,
+                  int* err) {
+  TrdArgs a{};
+  a.n = n;
+  a.G = G;
+  a.F = F;
+  a.Q = Q;
+  a.d = d;
+  a.e = e;
+  double* s = (double*)scratch;
+  a.Vb = s;
+  a.Pb = s + (long)n * n;
+  a.err = err;
+  const size_t lds = trd_lds(n, G);
+  if (lds > kTrdLdsDefault) {
+    const hipError_t he = hipFuncSetAttribute((const void*)k_trd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (he != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, RIF_EHIP, std::string("tridiagonal reduction: LDS attribute failed: ") + hipGetErrorString(he));
+    }
+  }
+  const long count = trd_slots(n);
+  const unsigned nblk = (unsigned)std::min(1024L, (count + 255) / 256);
+  hipLaunchKernelGGL(k_trd_reset, dim3(nblk), dim3(256), 0, c->stream, (unsigned long long*)s, count, err);
+  if (rif_status st = check_launch(c, "trd_reset")) return st;
+  void* args[] = {&a};
+  const hipError_t he =
+      hipLaunchCooperativeKernel((const void*)k_trd, dim3(G), dim3(kTrdThreads), args, (unsigned)lds, c->stream);
+  if (he != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, RIF_EHIP, std::string("cooperative launch of the tridiagonal reduction failed: ") +
+                                 hipGetErrorString(he));
+  }
+  return RIF_OK;
+}
+
+}  // namespace rif

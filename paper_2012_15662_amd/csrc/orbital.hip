@@ -3,7 +3,11 @@
 //   k_flam       F^lambda from the Lagrange multipliers (reading below)
 //   k_transpose  64x64 LDS-tiled transpose (FP64)
 //   k_maxabs     max |x| over an array, NaN counted as +inf (two passes)
-//   op_orbital_step   F^lambda -> eigenvectors (rocSOLVER dsyevd) -> C <- C V
+//   op_orbital_step   F^lambda -> eigenvectors -> C <- C V.  Eigensolver: the
+//                     one-launch tridiagonal reduction forming Q (eig.hip),
+//                     rocSOLVER dstedc (divide and conquer on T), and
+//                     C <- (C Q) Z as two GEMMs; or rocSOLVER dsyevd throughout
+//                     (rif_set_eigensolver)
 //   op_optimize       ON optimisation at fixed orbitals, then inner iterations
 //                     (build -> max|G| -> orbital step) at fixed ONs, repeated;
 //                     the builds skip J^q/K^q when no Jn/Kn buffers are given
@@ -116,24 +120,46 @@ rif_status op_maxabs(rif_ctx* c, long n, const double* x, double* part, double* 
   return check_launch(c, "maxabs");
 }
 
+__global__ void k_trd_info(const int* err, int* info) {
+  if (threadIdx.x == 0 && *err != 0) *info = -1;
+}
+
 rif_status op_orbital_step(rif_ctx* c, int nb, int nmo, int nw, const double* lam, const double* eps_in,
                            double* C, double* eps_out, int* info) {
   rocblas_handle h;
   rif_status st = blas_handle(c, &h);
   if (st) return st;
   const int n = nmo;
+  // eigensolver: own tridiagonal reduction (forming Q) + rocSOLVER dstedc, or dsyevd
+  const int G = c->eig_kind == RIF_EIG_SYEVD ? 0 : trd_groups(c, n, c->eig_groups);
+  if (c->eig_kind == RIF_EIG_TRD && G == 0)
+    return fail(c, RIF_ENOTSUP, "tridiagonal reduction: n_mo does not fit the cooperative launch");
+  const bool trd = G > 0;
   Carve cv;
   const size_t oF = cv.take<double>((size_t)n * n), oV = cv.take<double>((size_t)n * n);
   const size_t oCt = cv.take<double>((size_t)nb * n), oE = cv.take<double>((size_t)n), oI = cv.take<int>(1);
+  size_t oQ = 0, oWt = 0, oS = 0, oErr = 0;
+  if (trd) {
+    oQ = cv.take<double>((size_t)n * n);
+    oWt = cv.take<double>((size_t)n * nb);
+    oS = cv.take<char>(trd_scratch_bytes(n));
+    oErr = cv.take<int>(1);
+  }
   if ((st = ws_reserve(c, cv.off))) return st;
   auto at = [&](size_t o) { return (char*)c->ws + o; };
   int* dinfo = info ? info : (int*)at(oI);
-  // eigensolver workspace: size query (host only), then carve it after the buffers above
+  // F is symmetric, so its row-major array is also its column-major one.  On
+  // return, column j of the column-major F is eigenvector j of F (dsyevd) or
+  // of T (dstedc, eigenvalues into eps_out, which holds T's diagonal).
+  auto solve = [&](double* F, double* E) -> rocblas_status {
+    if (trd) return rocsolver_dstedc(h, rocblas_evect_tridiagonal, n, eps_out, E, F, n, dinfo);
+    return rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, n, F, n, eps_out, E, dinfo);
+  };
+  // solver workspace: size query (host only), then carve it after the buffers above
   size_t wsz = 0;
   if (rocblas_start_device_memory_size_query(h) != rocblas_status_success)
     return fail(c, RIF_EHIP, "rocBLAS workspace size query failed");
-  rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, n, (double*)at(oF), n, eps_out,
-                   (double*)at(oE), dinfo);
+  solve((double*)at(oF), (double*)at(oE));
   if (rocblas_stop_device_memory_size_query(h, &wsz) != rocblas_status_success)
     return fail(c, RIF_EHIP, "rocBLAS workspace size query failed");
   const size_t oW = cv.take<char>(wsz + 256);
@@ -146,23 +172,35 @@ rif_status op_orbital_step(rif_ctx* c, int nb, int nmo, int nw, const double* la
                        eps_in, F);
     if ((st = check_launch(c, "flam"))) return st;
   }
+  if (trd) {
+    ProfScope ps(c, "tridiagonal");
+    // T's diagonal goes straight to eps_out (k_flam has read eps_in, which may be the same array)
+    if ((st = op_trd(c, n, G, F, (double*)at(oQ), eps_out, E, at(oS), (int*)at(oErr)))) return st;
+  }
   {
     ProfScope ps(c, "eigensolver");
     if (rocblas_set_workspace(h, at(oW), wsz + 256) != rocblas_status_success)
       return fail(c, RIF_EHIP, "rocblas_set_workspace failed");
-    // F is symmetric, so its row-major array is also its column-major one.
-    // Out: column j of the column-major result is eigenvector j.
-    const rocblas_status rs =
-        rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, n, F, n, eps_out, E, dinfo);
+    const rocblas_status rs = solve(F, E);
     if (rs != rocblas_status_success)
-      return fail(c, RIF_EHIP, "rocsolver_dsyevd failed (status " + std::to_string((int)rs) + ")");
+      return fail(c, RIF_EHIP, std::string(trd ? "rocsolver_dstedc" : "rocsolver_dsyevd") + " failed (status " +
+                                   std::to_string((int)rs) + ")");
+    if (trd) {   // a timed-out wait inside the reduction reports as info = -1
+      hipLaunchKernelGGL(k_trd_info, dim3(1), dim3(64), 0, c->stream, (const int*)at(oErr), dinfo);
+      if ((st = check_launch(c, "trd_info"))) return st;
+    }
   }
   ProfScope ps(c, "rotate");
   // V[i][j] = component i of eigenvector j (row-major), Ct = C^T
   if ((st = transpose(c, n, n, F, n, V, n))) return st;
   if ((st = transpose(c, nb, n, C, n, Ct, nb))) return st;
-  // C[mu][j] = sum_i Ct[i][mu] V[i][j]
-  return op_gemm_kn(c, nb, n, n, Ct, nb, V, n, C, n);
+  if (!trd)   // C[mu][j] = sum_i Ct[i][mu] V[i][j]
+    return op_gemm_kn(c, nb, n, n, Ct, nb, V, n, C, n);
+  // eigenvectors of F are Q V: first Wt = (C Q)^T, Wt[c][mu] = sum_i Q[i][c] Ct[i][mu],
+  // then C[mu][j] = sum_c Wt[c][mu] V[c][j]
+  double* Wt = (double*)at(oWt);
+  if ((st = op_gemm_kn(c, n, nb, n, (const double*)at(oQ), n, Ct, nb, Wt, nb))) return st;
+  return op_gemm_kn(c, nb, n, n, Wt, nb, V, n, C, n);
 }
 
 // ---- the outer/inner loop ------------------------------------------------------

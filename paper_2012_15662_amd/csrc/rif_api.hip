@@ -289,6 +289,15 @@ rif_status rif_orbital_step(rif_ctx* c, int nb, int nmo, int nw, const double* l
   return op_orbital_step(c, nb, nmo, nw, lam, eps_in, C, eps_out, info);
 }
 
+rif_status rif_set_eigensolver(rif_ctx* c, int kind, int groups) {
+  if (!c) return RIF_EINVAL;
+  if (kind < RIF_EIG_AUTO || kind > RIF_EIG_TRD || groups < 0 || groups > 4096)
+    return fail(c, RIF_EINVAL, "rif_set_eigensolver: need kind in {0, 1, 2} and 0 <= groups <= 4096");
+  c->eig_kind = kind;
+  c->eig_groups = groups;
+  return RIF_OK;
+}
+
 rif_status rif_pnof_optimize(rif_ctx* c, const rif_instance* in, rif_prec prec, rif_functional fn,
                              const rif_opt_params* par, double* C, double* occ, double* gamma, rif_opt_result* res,
                              double* hist_e, double* hist_g, int hist_len) {

@@ -37,6 +37,9 @@ struct rif_ctx {
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   // rocBLAS handle of the orbital step's eigensolver (created on first use)
   void* blas = nullptr;
+  // orbital-step eigensolver (rif_set_eigensolver): kind and workgroup count
+  int eig_kind = 0;
+  int eig_groups = 0;
 };
 
 namespace rif {
@@ -123,6 +126,15 @@ rif_status op_gemm_kn(rif_ctx* c, int M, int N, int K, const double* A, long lda
 // b from the three-centre integrals and the metric (prep.hip)
 rif_status op_prepare_b(rif_ctx* c, int nb, int na, const double* T, const double* G, double delta, double* b,
                         int* perm, double* L, double* D, int* nraised);
+
+// Tridiagonal reduction in one cooperative launch (eig.hip): F = Q T Q^T with
+// T's diagonal in d and off-diagonal in e, Q row-major.  trd_groups: the
+// workgroups for an n x n problem (`want`, or the default when 0), 0 when it
+// does not fit.
+int trd_groups(rif_ctx* c, int n, int want);
+size_t trd_scratch_bytes(int n);
+rif_status op_trd(rif_ctx* c, int n, int G, const double* F, double* Q, double* d, double* e, void* scratch,
+                  int* err);
 
 // Orbital optimisation (orbital.hip)
 rif_status op_maxabs(rif_ctx* c, long n, const double* x, double* part, double* out);
