@@ -321,7 +321,7 @@ rif_status rif_orbital_step(rif_ctx *ctx, int n_bf, int n_mo, int n_omega, const
  *                  otherwise.
  *   RIF_EIG_SYEVD  rocSOLVER dsyevd (its own blocked reduction).
  *   RIF_EIG_AUTO   TRD where it fits, else SYEVD (the default).
- * groups: workgroups of the reduction, 0 for the default (about six rows
+ * groups: workgroups of the reduction, 0 for the default (about three rows
  * each, at least 16 workgroups, more where the rows do not fit).  Results of the two solvers agree to rounding,
  * eigenvectors up to sign.  RIF_EINVAL for an unknown kind or groups outside
  * [0, 4096]. */

@@ -14,21 +14,23 @@
 // The reduction is latency-bound at the orbital step's sizes (n of a few
 // hundred: ~1 MB of FP64), so it runs as ONE cooperative launch instead of a
 // few kernels per column.  Row i of F and row i of Q live in the LDS of
-// workgroup i mod G for the whole reduction.  Per column:
-//   phase A  the owner of row k forms v_k, d_k, e_k, tau_k and publishes v_k
-//            (tau_k in the slot of v_k's unit entry)
+// workgroup i mod G for the whole reduction.  Per column k, with v_k and
+// tau_k already known to every workgroup:
 //   phase B  every workgroup forms p_i = tau_k (A v_k)_i for its rows and
 //            publishes them, then applies H_k to its rows of Q (which needs
 //            nothing from other workgroups and covers the wait for p)
-//   phase C  every workgroup reads all of p, forms p^T v itself (the same
-//            fixed-order sum in every wave of every workgroup, so all hold the
-//            same w), and updates its rows; the owner of row k+1 updates that
-//            row first and runs phase A of the next column before its other rows
+//   phase C  every workgroup reads all of p, forms p^T v and w itself and
+//            updates its rows of A.  The owner of row k+2 updates that row
+//            first and publishes it (it is needed one column later).  Every
+//            workgroup then applies H_k to row k+1, published by its owner one
+//            column earlier, and forms v_{k+1} and tau_{k+1} from it itself.
+// So each column waits for one exchange (p), and every workgroup forms the
+// same v, w and tau: the same arithmetic in the same order on the same data.
 // Q is formed here so that the back-transformation of T's eigenvectors is one
 // GEMM instead of a sequence of reflector applications.
 // Workgroups exchange data without barriers or cache flushes: every published
-// value has its own slot per column (v_k and p_k), filled beforehand with a
-// signalling-NaN pattern that no arithmetic result takes (results of
+// value has its own slot per column (p_k and row k+2), filled beforehand with
+// a signalling-NaN pattern that no arithmetic result takes (results of
 // arithmetic on NaNs are quiet NaNs), written once with an agent-scope atomic
 // store and read by polling it with agent-scope atomic loads until it no
 // longer holds that pattern.  Each value carries its own readiness, so no
@@ -36,9 +38,7 @@
 // the poll limit, or once another workgroup has flagged a timeout, the
 // workgroup flags it and returns, so every wave exits.  Within a workgroup the
 // waves share out the rows (wave w takes rows t0 + w, t0 + w + 4, ..., t0 the
-// first row still active), every reduction is formed whole in each wave, and v
-// and p are double-buffered by the parity of k, so the only workgroup barriers
-// are the two that end each wait (and one in the owner before phase A).
+// first row still active) and every reduction is formed whole in each wave.
 #include <algorithm>
 #include <string>
 
@@ -59,7 +59,7 @@ struct TrdArgs {
   const double* F;        // [n][n] symmetric
   double* Q;              // [n][n] out, row-major
   double *d, *e;          // [n], [n-1] out
-  double* Vb;             // [n][n] v_k in row k, tau_k at k+1  (slots, kEmpty at launch)
+  double* Rb;             // [n][n] row i of A after H_{i-2}, in row i  (slots, kEmpty at launch)
   double* Pb;             // [n][n] p_k in row k
   int* err;               // set when a wait timed out
 };
@@ -130,54 +130,49 @@ __global__ __launch_bounds__(kTrdThreads) void k_trd(TrdArgs a) {
   double* rows = sm;                                // [R][n] rows of A
   double* qrows = rows + (long)R * n;               // [R][n] rows of Q
   double* vbuf = qrows + (long)R * n;               // [2][n] v_k by parity of k
-  double* pbuf = vbuf + 2L * n;                     // [2][n] p_k by parity of k
-  for (long x = tid; x < (long)R * n; x += kTrdThreads) {
-    const int t = (int)(x / n), j = (int)(x - (long)t * n);
-    rows[x] = a.F[(long)(g + G * t) * n + j];
-    qrows[x] = j == g + G * t ? 1.0 : 0.0;
+  double* p = vbuf + 2L * n;                        // [n] p_k
+  double* x = p + n;                                // [n] row k+1 of A
+  for (long y = tid; y < (long)R * n; y += kTrdThreads) {
+    const int t = (int)(y / n), j = (int)(y - (long)t * n);
+    rows[y] = a.F[(long)(g + G * t) * n + j];
+    qrows[y] = j == g + G * t ? 1.0 : 0.0;
   }
+  for (int j = tid; j < n; j += kTrdThreads) x[j] = a.F[j];   // row 0
   __syncthreads();
-  // phase A for column k, by the owner of row k (every wave forms the same
-  // |x_1..|^2 in the same order, so no workgroup barrier is needed)
-  auto reflect = [&](int k) {
-    const double* rk = rows + (long)(k / G) * n;
+  // v_k and tau_k from row k of A (x, entries k..n-1), in every workgroup
+  // alike; d_k and e_k from workgroup 0.  Ends with a workgroup barrier.
+  auto reflect = [&](int k) -> double {
     const int m0 = k + 1;
     double ss = 0.0;
-    for (int j = k + 2 + lane; j < n; j += 64) ss += rk[j] * rk[j];
+    for (int j = k + 2 + lane; j < n; j += 64) ss += x[j] * x[j];
     ss = wave_sum(ss);
-    const double alpha = rk[m0];
+    const double alpha = x[m0];
     double beta = alpha, tau = 0.0, scale = 0.0;
     if (ss != 0.0) {
       beta = -copysign(sqrt(alpha * alpha + ss), alpha);
       tau = (beta - alpha) / beta;
       scale = 1.0 / (alpha - beta);
     }
-    double* Vk = a.Vb + (long)k * n;
-    for (int j = m0 + tid; j < n; j += kTrdThreads) put(Vk + j, j == m0 ? tau : rk[j] * scale);
-    if (tid == 0) {
-      a.d[k] = rk[k];
+    double* v = vbuf + (long)(k & 1) * n;
+    for (int j = m0 + tid; j < n; j += kTrdThreads) v[j] = j == m0 ? 1.0 : x[j] * scale;
+    if (g == 0 && tid == 0) {
+      a.d[k] = x[k];
       a.e[k] = beta;
     }
+    __syncthreads();
+    return tau;
   };
-  if (g == 0) reflect(0);
+  double tau = n > 1 ? reflect(0) : 0.0;
   for (int k = 0; k + 1 < n; ++k) {
     const int m0 = k + 1;
     const int t0 = m0 > g ? (m0 - g + G - 1) / G : 0;   // first row of A held here at or past m0
-    double* v = vbuf + (long)(k & 1) * n;
-    double* p = pbuf + (long)(k & 1) * n;
-    {
-      const bool ok = take_range(a.Vb + (long)k * n, v, m0, n, a.err);
-      if (!ok) atomicExch(a.err, 1);
-      if (__syncthreads_or(!ok)) return;
-    }
-    const double tau = v[m0];
-    auto vv = [&](int j) { return j == m0 ? 1.0 : v[j]; };
+    const double* v = vbuf + (long)(k & 1) * n;
     // phase B: p_i = tau sum_j A_ij v_j for the rows held here
     double* Pk = a.Pb + (long)k * n;
     for (int t = t0 + wv; t < R; t += kTrdWaves) {
       const double* r = rows + (long)t * n;
       double s = 0.0;
-      for (int j = m0 + lane; j < n; j += 64) s += r[j] * vv(j);
+      for (int j = m0 + lane; j < n; j += 64) s += r[j] * v[j];
       s = wave_sum(s);
       if (lane == 0) put(Pk + g + G * t, tau * s);
     }
@@ -185,44 +180,59 @@ __global__ __launch_bounds__(kTrdThreads) void k_trd(TrdArgs a) {
     for (int t = wv; t < R; t += kTrdWaves) {
       double* q = qrows + (long)t * n;
       double s = 0.0;
-      for (int j = m0 + lane; j < n; j += 64) s += q[j] * vv(j);
+      for (int j = m0 + lane; j < n; j += 64) s += q[j] * v[j];
       s = tau * wave_sum(s);
-      for (int j = m0 + lane; j < n; j += 64) q[j] -= s * vv(j);
+      for (int j = m0 + lane; j < n; j += 64) q[j] -= s * v[j];
     }
-    if (t0 >= R) continue;   // no rows of A left here: p is not needed
-    // phase C: p^T v, w = p - (tau/2)(p^T v) v, A <- A - v w^T - w v^T on the rows held here
+    // phase C: row k+1 before H_k (from F for k = 0), all of p
+    const bool more = k + 2 < n;   // a reflector for column k+1 follows
     {
-      const bool ok = take_range(Pk, p, m0, n, a.err);
+      bool ok = true;
+      if (more) {
+        if (k == 0) {
+          for (int j = m0 + tid; j < n; j += kTrdThreads) x[j] = a.F[(long)n + j];
+        } else {
+          ok = take_range(a.Rb + (long)m0 * n, x, m0, n, a.err);
+        }
+      }
+      ok = ok && take_range(Pk, p, m0, n, a.err);
       if (!ok) atomicExch(a.err, 1);
       if (__syncthreads_or(!ok)) return;
     }
     double pv = 0.0;
-    for (int j = m0 + lane; j < n; j += 64) pv += p[j] * vv(j);
+    for (int j = m0 + lane; j < n; j += 64) pv += p[j] * v[j];
     const double K = 0.5 * tau * wave_sum(pv);
-    auto update = [&](int t) {
-      double* r = rows + (long)t * n;
-      const int i = g + G * t;
-      const double vi = vv(i), wi = p[i] - K * vi;
+    // A <- A - v w^T - w v^T with w = p - K v, on row r (its index i)
+    auto update = [&](double* r, int i) {
+      const double vi = v[i], wi = p[i] - K * vi;
       for (int j = m0 + lane; j < n; j += 64) {
-        const double vj = vv(j);
+        const double vj = v[j];
         r[j] -= vi * (p[j] - K * vj) + wi * vj;
       }
     };
-    const int kn = k + 1;
-    const bool next = kn + 1 < n && kn % G == g;   // this workgroup reflects column k+1
-    const int tn = next ? kn / G : -1;
-    if (next) {
-      if (wv == tn % kTrdWaves) update(tn);
-      __syncthreads();
-      reflect(kn);
+    const int kp = k + 2;   // row published now, for column k+1's successor
+    const int tp = kp + 1 < n && kp % G == g ? kp / G : -1;
+    if (tp >= 0 && wv == tp % kTrdWaves) {
+      double* r = rows + (long)tp * n;
+      update(r, kp);
+      for (int j = kp + lane; j < n; j += 64) put(a.Rb + (long)kp * n + j, r[j]);
     }
     for (int t = t0 + wv; t < R; t += kTrdWaves)
-      if (t != tn) update(t);
+      if (t != tp) update(rows + (long)t * n, g + G * t);
+    if (more) {
+      // row k+1 after H_k, then column k+1's reflector
+      for (int j = m0 + tid; j < n; j += kTrdThreads) {
+        const double vj = v[j];
+        x[j] -= (p[m0] - K) * vj + (p[j] - K * vj);   // v_{m0} = 1
+      }
+      __syncthreads();
+      tau = reflect(k + 1);
+    }
   }
   __syncthreads();
-  for (long x = tid; x < (long)R * n; x += kTrdThreads) {
-    const int t = (int)(x / n), j = (int)(x - (long)t * n);
-    a.Q[(long)(g + G * t) * n + j] = qrows[x];
+  for (long y = tid; y < (long)R * n; y += kTrdThreads) {
+    const int t = (int)(y / n), j = (int)(y - (long)t * n);
+    a.Q[(long)(g + G * t) * n + j] = qrows[y];
   }
   if ((n - 1) % G == g && tid == 0) a.d[n - 1] = rows[(long)((n - 1) / G) * n + (n - 1)];
 }
@@ -235,7 +245,7 @@ __global__ __launch_bounds__(256) void k_trd_reset(unsigned long long* slots, lo
 
 size_t trd_lds(int n, int G) {
   const long R = (n + G - 1) / G;
-  return (size_t)(2 * R * n + 4L * n) * sizeof(double);
+  return (size_t)(2 * R * n + 4L * n) * sizeof(double);   // rows of A and Q, v (two), p, x
 }
 long trd_slots(int n) { return 2L * n * n; }
 }  // namespace
@@ -248,11 +258,12 @@ int trd_groups(rif_ctx* c, int n, int want) {
     (void)hipGetLastError();
     return 0;
   }
-  // `want` workgroups if given, else about six rows each (at least 16
-  // workgroups); more if the rows do not fit the LDS budget; at most one per
-  // CU and one per row
+  // `want` workgroups if given, else about three rows each (at least 16
+  // workgroups: more shorten each one's share of a column, fewer shorten the
+  // waits); more if the rows do not fit the LDS budget; at most one per CU and
+  // one per row
   const int gmax = std::min(ncu, n);
-  int G = want > 0 ? want : std::max(std::min(16, n), (n + 5) / 6);
+  int G = want > 0 ? want : std::max(std::min(16, n), (n + 2) / 3);
   G = std::min(G, gmax);
   while (G <= gmax && trd_lds(n, G) > kTrdLds) ++G;
   return G <= gmax ? G : 0;
@@ -270,7 +281,7 @@ rif_status op_trd(rif_ctx* c, int n, int G, const double* F, double* Q, double* 
   a.d = d;
   a.e = e;
   double* s = (double*)scratch;
-  a.Vb = s;
+  a.Rb = s;
   a.Pb = s + (long)n * n;
   a.err = err;
   const size_t lds = trd_lds(n, G);
