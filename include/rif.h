@@ -272,12 +272,14 @@ rif_status rif_adam(rif_ctx *ctx, int n, float *theta, const float *grad, float 
  *   P L D~^(1/2) b^T = T,  T[k][mu nu] = (mu nu|k),
  * is solved: b^T = D~^(-1/2) L^-1 P^T T.  Then sum_k b^k b^k = T^T G~^-1 T with
  * G~ = P L D~ L^T P^T (= G if nothing was raised).  Device pointers:
- *   T [n_aux][n_bf][n_bf] (symmetric in mu, nu), G [n_aux][n_aux] symmetric
- *   b [n_aux][n_bf][n_bf] out
+ *   T [n_aux][n_bf][n_bf] (symmetric in mu, nu: only nu >= mu is read),
+ *   G [n_aux][n_aux] symmetric
+ *   b [n_aux][n_bf][n_bf] out, exactly symmetric in mu, nu (the solve runs on
+ *   the packed upper triangles; b's buffer also stages them)
  *   optional (NULL to skip): perm [n_aux] (P^T x)[i] = x[perm[i]]; L and D
  *   [n_aux][n_aux] dense; n_raised: number of raised eigenvalues
- * delta <= 0 takes 2^-26 * max_k sum_l |G_kl|.  Uses 6 n_aux^2 doubles of the
- * context arena.  Asynchronous.  RIF_EINVAL for sizes (n_aux < 46341) or NULL
+ * delta <= 0 takes 2^-26 * max_k sum_l |G_kl|.  Uses 6 n_aux^2 +
+ * n_aux n_bf (n_bf + 1) / 2 doubles of the context arena.  Asynchronous.  RIF_EINVAL for sizes (n_aux < 46341) or NULL
  * T, G, b. */
 rif_status rif_prepare_b(rif_ctx *ctx, int n_bf, int n_aux, const double *T, const double *G, double delta,
                          double *b, int *perm, double *L, double *D, int *n_raised);

@@ -14,7 +14,8 @@
 //   k_bk_correct D~^(-1/2) per block (2x2 blocks in closed form)
 //   k_linv       X = L^-1 one column step at a time (rank-1 updates)
 //   k_compose    M^T[perm[i]][k] = sum_r D~^(-1/2)[k][r] X[r][i]
-//   then b^T = M T on the FP64 MFMA GEMM.
+//   then b^T = M T on the FP64 MFMA GEMM, over the packed upper triangles of
+//   the slabs (k_pack_upper before, k_unpack_sym after).
 //
 // Pivot rule (alpha = (1 + sqrt 17)/8) at column k, with colmax/imax the
 // largest |A_ik| below the diagonal (lowest index on ties) and rowmax the
@@ -36,21 +37,15 @@ constexpr int kPivThreads = 1024;
 struct BkState { int k, kstep, next; };
 }  // namespace
 
-__global__ __launch_bounds__(256) void k_rowsum(int n, const double* __restrict__ G, double* __restrict__ part) {
-  // row sum i of |G| per thread, read as column i (G symmetric) so that the
-  // threads of a wave read consecutive addresses; then a max over the block
-  __shared__ double red[256];
-  const int i = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void k_rowsum(int n, const double* __restrict__ G, double* __restrict__ rs) {
+  // row sum i of |G| per wave, the lanes reading along the row
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const double* g = G + (long)i * n;
   double s = 0.0;
-  if (i < n)
-    for (int j = 0; j < n; ++j) s += fabs(G[(long)j * n + i]);
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+  for (int j = lane; j < n; j += 64) s += fabs(g[j]);
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) rs[i] = s;
 }
 
 __global__ __launch_bounds__(256) void k_delta(int nblk, const double* __restrict__ part, double* __restrict__ del) {
@@ -285,6 +280,57 @@ __global__ __launch_bounds__(256) void k_compose(int n, const double* __restrict
   Mt[(long)perm[i] * n + k] = v;
 }
 
+// The solve works on the upper triangle of each slab only (T and b are
+// symmetric in mu, nu): packed by rows, Tp[k][o(mu) + nu - mu] = T[k][mu][nu]
+// for nu >= mu, o(mu) = mu nb - mu (mu - 1) / 2.  One workgroup per (k, mu)
+// row, grid-strided; reads and writes both run along nu.
+__global__ __launch_bounds__(256) void k_pack_upper(int nb, long rows, const double* __restrict__ T,
+                                                    double* __restrict__ Tp) {
+  const long npk = (long)nb * (nb + 1) / 2;
+  for (long rr = blockIdx.x; rr < rows; rr += gridDim.x) {
+    const long k = rr / nb;
+    const int mu = (int)(rr - k * nb);
+    const double* src = T + (k * nb + mu) * nb;
+    double* dst = Tp + k * npk + (long)mu * nb - (long)mu * (mu - 1) / 2 - mu;
+    for (int nu = mu + threadIdx.x; nu < nb; nu += 256) dst[nu] = src[nu];
+  }
+}
+// b[k] from the packed solution, by 64x64 tiles (rb <= cb) of each slab: the
+// tile's upper-triangle elements are read once along c into LDS and written
+// to (r, c) and, through the LDS transpose, to (c, r), both along rows.
+constexpr int kUT = 64;
+__global__ __launch_bounds__(256) void k_unpack_sym(int nb, long ntiles, const double* __restrict__ bp,
+                                                    double* __restrict__ b) {
+  __shared__ double t[kUT][kUT + 1];
+  const long npk = (long)nb * (nb + 1) / 2;
+  const int nbt = (nb + kUT - 1) / kUT, per = nbt * (nbt + 1) / 2;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (long tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
+    const long k = tt / per;
+    int rem = (int)(tt - k * per), rb = 0;
+    while (rem >= nbt - rb) { rem -= nbt - rb; ++rb; }
+    const int cb = rb + rem, r0 = rb * kUT, c0 = cb * kUT;
+    const double* src = bp + k * npk;
+    double* dst = b + k * (long)nb * nb;
+    __syncthreads();
+    for (int y = ty; y < kUT; y += 4) {
+      const int r = r0 + y, cc = c0 + tx;
+      if (r < nb && cc < nb && cc >= r) t[y][tx] = src[(long)r * nb - (long)r * (r - 1) / 2 + (cc - r)];
+    }
+    __syncthreads();
+    for (int y = ty; y < kUT; y += 4) {
+      const int r = r0 + y, cc = c0 + tx;   // (r, cc) from the upper triangle: itself or its mirror
+      if (r < nb && cc < nb) dst[(long)r * nb + cc] = cc >= r ? t[y][tx] : t[tx][y];
+    }
+    if (rb != cb) {
+      for (int y = ty; y < kUT; y += 4) {
+        const int r = c0 + y, cc = r0 + tx;   // lower tile (cb, rb): element (r, cc) = upper (cc, r)
+        if (r < nb && cc < nb) dst[(long)r * nb + cc] = t[tx][y];
+      }
+    }
+  }
+}
+
 rif_status op_prepare_b(rif_ctx* c, int nb, int na, const double* T, const double* G, double delta,
                         double* b, int* perm_out, double* L_out, double* D_out, int* nraised_out) {
   const int n = na;
@@ -293,8 +339,10 @@ rif_status op_prepare_b(rif_ctx* c, int nb, int na, const double* T, const doubl
   const size_t oA = cv.take<double>(nn), oL = cv.take<double>(nn), oD = cv.take<double>(nn);
   const size_t oX = cv.take<double>(nn), oM = cv.take<double>(nn), oDih = cv.take<double>(nn);
   const size_t oP = cv.take<int>(n), oB = cv.take<int>(n), oS = cv.take<BkState>(1);
-  const size_t oPart = cv.take<double>((size_t)(n + 255) / 256 + 1), oDel = cv.take<double>(1);
+  const size_t oPart = cv.take<double>((size_t)n), oDel = cv.take<double>(1);
   const size_t oR = cv.take<int>(1);
+  const long npk = (long)nb * (nb + 1) / 2;
+  const size_t oBp = cv.take<double>((size_t)n * npk);   // packed solution
   rif_status st = ws_reserve(c, cv.off);
   if (st) return st;
   char* w = (char*)c->ws;
@@ -306,10 +354,9 @@ rif_status op_prepare_b(rif_ctx* c, int nb, int na, const double* T, const doubl
   const unsigned gnn = (unsigned)((nn + 255) / 256);
   {
     ProfScope ps(c, "prep_factorise");
-    const int nblk = (n + 255) / 256;
-    hipLaunchKernelGGL(k_rowsum, dim3(nblk), dim3(256), 0, c->stream, n, G, part);
-    // max over the row-sum partials, times sqrt(2^-52), into del
-    hipLaunchKernelGGL(k_delta, dim3(1), dim3(256), 0, c->stream, nblk, part, del);
+    hipLaunchKernelGGL(k_rowsum, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, c->stream, n, G, part);
+    // max over the row sums, times sqrt(2^-52), into del
+    hipLaunchKernelGGL(k_delta, dim3(1), dim3(256), 0, c->stream, n, part, del);
     hipLaunchKernelGGL(k_bk_init, dim3(gnn), dim3(256), 0, c->stream, n, G, A, L, D, perm, bsz, sp);
     if ((st = check_launch(c, "prep_init"))) return st;
     const unsigned gup = (unsigned)std::min(1024L, (nn + 255) / 256);
@@ -335,9 +382,21 @@ rif_status op_prepare_b(rif_ctx* c, int nb, int na, const double* T, const doubl
   }
   {
     ProfScope ps(c, "prep_solve_gemm");
-    // b^T[k][mu nu] = sum_j M[k][j] T[j][mu nu]: A operand M^T (j-major), B = T
-    const long nb2 = (long)nb * nb;
-    if ((st = op_gemm_kn(c, n, (int)nb2, n, Mt, n, T, nb2, b, nb2))) return st;
+    // b^T[k][mu nu] = sum_j M[k][j] T[j][mu nu] on the packed upper triangles
+    // (A operand M^T, j-major; B the packed T, staged in b's own buffer, which
+    // is free until the unpacking writes it), then mirrored into b
+    double* Tp = b;
+    double* bp = (double*)(w + oBp);
+    const long rows = (long)n * nb;
+    const unsigned g = (unsigned)std::min(rows, 65536L);
+    hipLaunchKernelGGL(k_pack_upper, dim3(g), dim3(256), 0, c->stream, nb, rows, T, Tp);
+    if ((st = check_launch(c, "prep_pack"))) return st;
+    if ((st = op_gemm_kn(c, n, (int)npk, n, Mt, n, Tp, npk, bp, npk))) return st;
+    const int nbt = (nb + kUT - 1) / kUT;
+    const long ntiles = (long)n * (nbt * (nbt + 1) / 2);
+    hipLaunchKernelGGL(k_unpack_sym, dim3((unsigned)std::min(ntiles, 65536L)), dim3(256), 0, c->stream, nb, ntiles,
+                       (const double*)bp, b);
+    if ((st = check_launch(c, "prep_unpack"))) return st;
   }
   if (perm_out && hipMemcpyAsync(perm_out, perm, sizeof(int) * n, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
     return fail(c, RIF_EHIP, "copying perm failed");
