@@ -12,7 +12,9 @@
 //                symmetric interchange, the D block and the L column(s)
 //   k_bk_update  trailing update A -= L_k D_k L_k^T (all workgroups)
 //   k_bk_correct D~^(-1/2) per block (2x2 blocks in closed form)
-//   k_linv       X = L^-1 one column step at a time (rank-1 updates)
+//   k_linv_rows  X = L^-1, one wave per column (forward substitution), one
+//                launch; k_linv (one column step at a time, rank-1 updates)
+//                above 2048 auxiliary functions
 //   k_compose    M^T[perm[i]][k] = sum_r D~^(-1/2)[k][r] X[r][i]
 //   then b^T = M T on the FP64 MFMA GEMM, over the packed upper triangles of
 //   the slabs (k_pack_upper before, k_unpack_sym after).
@@ -28,6 +30,7 @@
 #include <string>
 
 #include "rif_internal.hpp"
+#include "wave.hpp"
 
 namespace rif {
 
@@ -280,6 +283,55 @@ __global__ __launch_bounds__(256) void k_compose(int n, const double* __restrict
   Mt[(long)perm[i] * n + k] = v;
 }
 
+// X = L^-1 by columns, one wave per column j: x_j = 1 and, for i > j in order,
+// x_i = -sum_{j <= k < i} L[i][k] x_k (forward substitution on L x = e_j).
+// The four waves of a workgroup take four adjacent columns and share each row
+// of L through a double-buffered LDS row: the next row's loads are issued
+// before the current row's dot products and stored after them.  Needs
+// n <= kLinvMaxN (eight row elements per thread).
+constexpr int kLinvMaxN = 2048;
+__global__ __launch_bounds__(256) void k_linv_rows(int n, const double* __restrict__ L, double* __restrict__ X) {
+  extern __shared__ double sh[];
+  double* rowbuf = sh;         // [2][n]
+  double* xs = sh + 2L * n;    // [4][n]
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j0 = blockIdx.x * 4, j = j0 + w;
+  double* x = xs + (long)w * n;
+  for (int k = lane; k < n; k += 64) x[k] = k == j ? 1.0 : 0.0;
+  const int i0 = j0 + 1;
+  if (i0 < n)
+    for (int k = threadIdx.x; k < i0; k += 256) rowbuf[k] = L[(long)i0 * n + k];
+  __syncthreads();
+  for (int i = i0; i < n; ++i) {
+    const double* cur = rowbuf + (long)((i - i0) & 1) * n;
+    double* nxt = rowbuf + (long)((i - i0 + 1) & 1) * n;
+    const int in = i + 1;
+    double pre[kLinvMaxN / 256];
+#pragma unroll
+    for (int u = 0; u < kLinvMaxN / 256; ++u) {
+      const int k = threadIdx.x + 256 * u;
+      pre[u] = in < n && k < in ? L[(long)in * n + k] : 0.0;
+    }
+    if (j < n && i > j) {   // whole wave
+      double s = 0.0;
+      for (int k = j + lane; k < i; k += 64) s += cur[k] * x[k];
+      s = wave_sum_dpp(s);
+      if (lane == 0) x[i] = -s;
+    }
+#pragma unroll
+    for (int u = 0; u < kLinvMaxN / 256; ++u) {
+      const int k = threadIdx.x + 256 * u;
+      if (in < n && k < in) nxt[k] = pre[u];
+    }
+    __syncthreads();
+  }
+  // columns j0..j0+3 of X, four adjacent doubles per row
+  for (int y = threadIdx.x; y < 4 * n; y += 256) {
+    const int i = y >> 2, c = y & 3;
+    if (j0 + c < n) X[(long)i * n + j0 + c] = xs[(long)c * n + i];
+  }
+}
+
 // The solve works on the upper triangle of each slab only (T and b are
 // symmetric in mu, nu): packed by rows, Tp[k][o(mu) + nu - mu] = T[k][mu][nu]
 // for nu >= mu, o(mu) = mu nb - mu (mu - 1) / 2.  One workgroup per (k, mu)
@@ -372,10 +424,21 @@ rif_status op_prepare_b(rif_ctx* c, int nb, int na, const double* T, const doubl
     if (hipMemsetAsync(nr, 0, sizeof(int), c->stream) != hipSuccess) return fail(c, RIF_EHIP, "hipMemsetAsync failed");
     hipLaunchKernelGGL(k_bk_correct, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, D, bsz, del,
                        delta, Dih, nr);
-    for (int k = 0; k + 1 < n; ++k) {
-      const long work = (long)(n - k - 1) * (k + 1);
-      const unsigned g = (unsigned)std::max(1L, std::min(1024L, (work + 255) / 256));
-      hipLaunchKernelGGL(k_linv, dim3(g), dim3(256), 0, c->stream, n, k, L, X);
+    if (n <= kLinvMaxN) {
+      const size_t lds = (size_t)6 * n * sizeof(double);
+      if (lds > 64 * 1024 &&
+          hipFuncSetAttribute((const void*)k_linv_rows, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+              hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, RIF_EHIP, "L^-1: LDS attribute failed");
+      }
+      hipLaunchKernelGGL(k_linv_rows, dim3((unsigned)((n + 3) / 4)), dim3(256), lds, c->stream, n, L, X);
+    } else {
+      for (int k = 0; k + 1 < n; ++k) {
+        const long work = (long)(n - k - 1) * (k + 1);
+        const unsigned g = (unsigned)std::max(1L, std::min(1024L, (work + 255) / 256));
+        hipLaunchKernelGGL(k_linv, dim3(g), dim3(256), 0, c->stream, n, k, L, X);
+      }
     }
     hipLaunchKernelGGL(k_compose, dim3(gnn), dim3(256), 0, c->stream, n, Dih, bsz, X, perm, Mt);
     if ((st = check_launch(c, "prep_correct_invert"))) return st;
