@@ -283,6 +283,253 @@ __global__ __launch_bounds__(256) void k_compose(int n, const double* __restrict
   Mt[(long)perm[i] * n + k] = v;
 }
 
+// ---- the factorisation in one cooperative launch -----------------------------
+// Row i of A lives in the LDS of workgroup i mod G for the whole factorisation;
+// its entries left of the current column, no longer needed as A, hold row i of
+// L.  Workgroups exchange data through single-write slots: each slot is filled
+// beforehand with a signalling-NaN pattern that no arithmetic result takes
+// (arithmetic on NaNs yields quiet NaNs), written once with an agent-scope
+// atomic store, and read by polling it with agent-scope atomic loads until it
+// no longer holds that pattern.  Every wait is bounded; past the limit, or once
+// another workgroup has flagged a timeout, a workgroup flags it and returns.
+// Per step at column k:
+//   1. every workgroup reads column k (C1; each workgroup published its rows'
+//      entries of it at the end of the previous step, before the rest of its
+//      update) and forms colmax, imax and |A_kk| itself (the same data and
+//      order-free reductions, so the same decision everywhere);
+//   2. where the first pivot test fails: its rows' entries of column imax
+//      (CI) and, from the owners of rows imax, k and k+1, those whole rows (RI,
+//      RK, RK1: the only rows an interchange can move); every workgroup forms
+//      rowmax and takes the decision;
+//   3. every workgroup forms the pivot column(s) after the interchange from
+//      column k and column imax, swaps the interchanged columns in its rows,
+//      takes over a moved row (from RK, RK1 or RI), writes its L entries and
+//      updates its rows with the arithmetic of k_bk_pivot and k_bk_update.
+// Workgroup 0 keeps perm, the block sizes and D.
+constexpr long kBkSpinLimit = 1L << 22;
+constexpr unsigned long long kBkEmpty = 0x7FF4C0FFEE5E7F11ull;   // signalling NaN
+constexpr size_t kBkLds = 150 * 1024;
+
+struct BkcArgs {
+  int n, G;
+  const double* Gm;              // [n][n] the metric
+  double *L, *D;                 // [n][n] out
+  int *perm, *bsz;               // [n] out (bsz zero-filled beforehand)
+  double *C1, *CI;               // [n][n] slots: C1[k][i] = A_ik, CI[k][i] = A_i,imax
+  double *RK, *RK1, *RI;         // [n][n] slots: whole rows k, k+1, imax at step k
+  int* err;
+};
+
+__device__ __forceinline__ void bk_put(double* p, double v) {
+  __hip_atomic_store((unsigned long long*)p, (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long bk_peek(const double* p) {
+  return __hip_atomic_load((unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// dst[j] = slot src[j] for j in [j0, j1), strided over the workgroup
+__device__ bool bk_take_range(const double* src, double* dst, int j0, int j1, const int* err) {
+  for (int j = j0 + (int)threadIdx.x; j < j1; j += 256) {
+    unsigned long long u = bk_peek(src + j);
+    for (long s = 0; u == kBkEmpty; ++s) {
+      if (s >= kBkSpinLimit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+      __builtin_amdgcn_s_sleep(1);
+      u = bk_peek(src + j);
+    }
+    dst[j] = __longlong_as_double((long long)u);
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(256) void k_bk_coop(BkcArgs a) {
+  extern __shared__ double sm[];
+  const int n = a.n, G = a.G, g = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int R = g < n ? (n - g + G - 1) / G : 0;   // rows i = g + G t, t < R
+  double* rows = sm;                                // [R][n]
+  double* c1 = rows + (long)R * n;                  // column k
+  double* ci = c1 + n;                              // column imax
+  double* ri = ci + n;                              // row imax
+  double* ck = ri + n;                              // column k after the interchange
+  double* cq = ck + n;                              // column k+1 after the interchange (2x2)
+  for (long x = tid; x < (long)R * n; x += 256) {
+    const int t = (int)(x / n), j = (int)(x - (long)t * n);
+    rows[x] = a.Gm[(long)(g + G * t) * n + j];
+  }
+  if (g == 0)
+    for (int i = tid; i < n; i += 256) a.perm[i] = i;
+  __syncthreads();
+  auto fail = [&]() { atomicExch(a.err, 1); };
+  int k = 0;
+  while (k < n) {
+    const int t0 = k > g ? (k - g + G - 1) / G : 0;   // first row held here at or past k
+    // 1. column k
+    {
+      double* C1k = a.C1 + (long)k * n;
+      if (k == 0)
+        for (int t = wv; t < R; t += 4)
+          if (lane == 0) bk_put(C1k + g + G * t, rows[(long)t * n]);
+      const bool ok = bk_take_range(C1k, c1, k, n, a.err);
+      if (!ok) fail();
+      if (__syncthreads_or(!ok)) return;
+    }
+    // colmax / imax below the diagonal (lowest index on ties; NaNs never
+    // chosen; 0 and k+1 when the column is zero), the same in every wave
+    double cm = 0.0;
+    int im = n;
+    for (int i = k + 1 + lane; i < n; i += 64) {
+      const double v = fabs(c1[i]);
+      if (v > cm || (v == cm && i < im)) { cm = v; im = i; }
+    }
+    {
+      const double top = wave_max_dpp(cm);
+      im = wave_min_int_dpp(cm == top ? im : n);
+      cm = top;
+    }
+    const double absakk = fabs(c1[k]);
+    int kstep = 1, kp = k;
+    if (k + 1 < n && fmax(absakk, cm) != 0.0 && absakk < kAlpha * cm) {
+      // 2. column imax and row imax; rowmax over row imax left of the diagonal
+      //    (columns k..imax-1) and column imax below it
+      double* CIk = a.CI + (long)k * n;
+      double* RIk = a.RI + (long)k * n;
+      for (int t = t0 + wv; t < R; t += 4)
+        if (lane == 0) bk_put(CIk + g + G * t, rows[(long)t * n + im]);
+      if (im % G == g)
+        for (int j = tid; j < n; j += 256) bk_put(RIk + j, rows[(long)(im / G) * n + j]);
+      if (k % G == g)
+        for (int j = tid; j < n; j += 256) bk_put(a.RK + (long)k * n + j, rows[(long)(k / G) * n + j]);
+      if ((k + 1) % G == g)
+        for (int j = tid; j < n; j += 256) bk_put(a.RK1 + (long)k * n + j, rows[(long)((k + 1) / G) * n + j]);
+      bool ok = bk_take_range(CIk, ci, k, n, a.err);
+      ok = ok && bk_take_range(RIk, ri, k, n, a.err);
+      if (!ok) fail();
+      if (__syncthreads_or(!ok)) return;
+      double rm = 0.0;
+      for (int j = k + lane; j < n; j += 64)
+        if (j != im) rm = fmax(rm, fabs(j < im ? ri[j] : ci[j]));
+      rm = wave_max_dpp(rm);
+      if (absakk * rm >= kAlpha * cm * cm) {
+        kstep = 1; kp = k;
+      } else if (fabs(ri[im]) >= kAlpha * rm) {
+        kstep = 1; kp = im;
+      } else {
+        kstep = 2; kp = im;
+      }
+    }
+    const int kk = k + kstep - 1;
+    auto pi = [&](int j) { return j == kk ? kp : (j == kp ? kk : j); };
+    // 3. pivot column(s) after the interchange (kk kp)
+    for (int j = k + tid; j < n; j += 256) {
+      if (kstep == 1) {
+        ck[j] = kp == k ? c1[j] : ci[pi(j)];
+      } else {
+        ck[j] = c1[pi(j)];
+        cq[j] = ci[pi(j)];
+      }
+    }
+    if (kp != kk) {
+      // the row moving into a position held here (its whole row, L part included)
+      const double* from = nullptr;
+      int tdst = -1;
+      if (kk % G == g) { from = a.RI + (long)k * n; tdst = kk / G; }                          // old row kp
+      else if (kp % G == g) { from = (kstep == 1 ? a.RK : a.RK1) + (long)k * n; tdst = kp / G; }   // old row kk
+      if (kk % G == g && kp % G == g) {   // both positions held here: swap in place
+        from = nullptr;
+        for (int j = tid; j < n; j += 256) {
+          const double x = rows[(long)(kk / G) * n + j];
+          rows[(long)(kk / G) * n + j] = rows[(long)(kp / G) * n + j];
+          rows[(long)(kp / G) * n + j] = x;
+        }
+      }
+      if (from) {
+        const bool ok = bk_take_range(from, rows + (long)tdst * n, 0, n, a.err);
+        if (!ok) fail();
+        if (__syncthreads_or(!ok)) return;
+      }
+      __syncthreads();
+      // columns kk <-> kp in the rows still active
+      for (int t = t0 + wv; t < R; t += 4)
+        if (lane == 0) {
+          double* r = rows + (long)t * n;
+          const double x = r[kk];
+          r[kk] = r[kp];
+          r[kp] = x;
+        }
+      if (g == 0 && tid == 0) {
+        const int x = a.perm[kk];
+        a.perm[kk] = a.perm[kp];
+        a.perm[kp] = x;
+      }
+    }
+    __syncthreads();
+    // D block, L entries and the trailing update on the rows held here; each
+    // row's entry of the next pivot column k0 is published before the rest
+    const int k0 = k + kstep;
+    double* C1n = a.C1 + (long)(k0 < n ? k0 : 0) * n;
+    if (kstep == 1) {
+      const double d = ck[k];
+      if (g == 0 && tid == 0) { a.D[(long)k * n + k] = d; a.bsz[k] = 1; }
+      for (int t = (k0 > g ? (k0 - g + G - 1) / G : 0) + wv; t < R; t += 4) {
+        double* r = rows + (long)t * n;
+        const int i = g + G * t;
+        const double l = d != 0.0 ? ck[i] / d : 0.0;
+        if (lane == 0) bk_put(C1n + i, r[k0] - l * ck[k0]);   // next pivot column first
+        for (int j = k0 + lane; j < n; j += 64) r[j] = r[j] - l * ck[j];
+        if (lane == 0) r[k] = l;
+      }
+    } else {
+      const double e00 = ck[k], e10 = ck[k + 1], e11 = cq[k + 1];
+      const double det = e00 * e11 - e10 * e10;
+      const double i00 = e11 / det, i01 = -e10 / det, i11 = e00 / det;
+      if (g == 0 && tid == 0) {
+        a.D[(long)k * n + k] = e00;
+        a.D[(long)k * n + k + 1] = e10;
+        a.D[(long)(k + 1) * n + k] = e10;
+        a.D[(long)(k + 1) * n + k + 1] = e11;
+        a.bsz[k] = 2;
+        a.bsz[k + 1] = 0;
+      }
+      if ((k + 1) % G == g && tid == 0) rows[(long)((k + 1) / G) * n + k] = 0.0;   // L is I on the block
+      for (int t = (k0 > g ? (k0 - g + G - 1) / G : 0) + wv; t < R; t += 4) {
+        double* r = rows + (long)t * n;
+        const int i = g + G * t;
+        const double x0 = ck[i], x1 = cq[i];
+        const double l0 = x0 * i00 + x1 * i01, l1 = x0 * i01 + x1 * i11;
+        if (lane == 0) {   // next pivot column first
+          double v = r[k0] - l0 * ck[k0];
+          v -= l1 * cq[k0];
+          bk_put(C1n + i, v);
+        }
+        for (int j = k0 + lane; j < n; j += 64) {
+          double v = r[j] - l0 * ck[j];
+          v -= l1 * cq[j];
+          r[j] = v;
+        }
+        if (lane == 0) { r[k] = l0; r[k + 1] = l1; }
+      }
+    }
+    __syncthreads();
+    k = k0;
+  }
+  // L: the left parts of the rows, unit diagonal, zero above
+  for (long x = tid; x < (long)R * n; x += 256) {
+    const int t = (int)(x / n), j = (int)(x - (long)t * n), i = g + G * t;
+    a.L[(long)i * n + j] = j < i ? rows[x] : (j == i ? 1.0 : 0.0);
+  }
+}
+
+__global__ void k_bk_coop_reset(unsigned long long* slots, long count, int* err) {
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < count; i += (long)gridDim.x * 256) slots[i] = kBkEmpty;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *err = 0;
+}
+// a timed-out factorisation leaves NaN in D, so b comes out NaN, never silently wrong
+__global__ void k_bk_coop_check(const int* err, double* D) {
+  if (threadIdx.x == 0 && *err != 0) D[0] = __longlong_as_double(0x7FF8000000000000ll);
+}
+
+size_t bk_coop_lds(int n, int G) { return (size_t)(((n + G - 1) / G) + 5L) * n * sizeof(double); }
+
 // X = L^-1 by columns, one wave per column j: x_j = 1 and, for i > j in order,
 // x_i = -sum_{j <= k < i} L[i][k] x_k (forward substitution on L x = e_j).
 // The four waves of a workgroup take four adjacent columns and share each row
@@ -383,7 +630,7 @@ __global__ __launch_bounds__(256) void k_unpack_sym(int nb, long ntiles, const d
   }
 }
 
-rif_status op_prepare_b(rif_ctx* c, int nb, int na, const double* T, const double* G, double delta,
+rif_status op_prepare_b(rif_ctx* c, int nb, int na, const double* T, const double* Gm, double delta,
                         double* b, int* perm_out, double* L_out, double* D_out, int* nraised_out) {
   const int n = na;
   const long nn = (long)n * n;
@@ -395,6 +642,20 @@ rif_status op_prepare_b(rif_ctx* c, int nb, int na, const double* T, const doubl
   const size_t oR = cv.take<int>(1);
   const long npk = (long)nb * (nb + 1) / 2;
   const size_t oBp = cv.take<double>((size_t)n * npk);   // packed solution
+  // the one-launch factorisation where the rows fit the LDS of at most one
+  // workgroup per CU (n_aux up to about 1600), else a pivot and an update
+  // launch per column
+  int G = 0;
+  {
+    int ncu = 0, coop = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess &&
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device) == hipSuccess && coop) {
+      G = std::min({ncu, n, 256});
+      if (bk_coop_lds(n, G) > kBkLds) G = 0;
+    }
+    (void)hipGetLastError();
+  }
+  const size_t oSlots = G ? cv.take<double>((size_t)5 * nn) : 0, oErr = G ? cv.take<int>(1) : 0;
   rif_status st = ws_reserve(c, cv.off);
   if (st) return st;
   char* w = (char*)c->ws;
@@ -406,15 +667,52 @@ rif_status op_prepare_b(rif_ctx* c, int nb, int na, const double* T, const doubl
   const unsigned gnn = (unsigned)((nn + 255) / 256);
   {
     ProfScope ps(c, "prep_factorise");
-    hipLaunchKernelGGL(k_rowsum, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, c->stream, n, G, part);
+    hipLaunchKernelGGL(k_rowsum, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, c->stream, n, Gm, part);
     // max over the row sums, times sqrt(2^-52), into del
     hipLaunchKernelGGL(k_delta, dim3(1), dim3(256), 0, c->stream, n, part, del);
-    hipLaunchKernelGGL(k_bk_init, dim3(gnn), dim3(256), 0, c->stream, n, G, A, L, D, perm, bsz, sp);
+    hipLaunchKernelGGL(k_bk_init, dim3(gnn), dim3(256), 0, c->stream, n, Gm, A, L, D, perm, bsz, sp);
     if ((st = check_launch(c, "prep_init"))) return st;
-    const unsigned gup = (unsigned)std::min(1024L, (nn + 255) / 256);
-    for (int it = 0; it < n; ++it) {
-      hipLaunchKernelGGL(k_bk_pivot, dim3(1), dim3(kPivThreads), 0, c->stream, n, A, L, D, perm, bsz, sp);
-      hipLaunchKernelGGL(k_bk_update, dim3(gup), dim3(256), 0, c->stream, n, A, L, (const BkState*)sp);
+    if (G) {
+      BkcArgs ba{};
+      ba.n = n;
+      ba.G = G;
+      ba.Gm = Gm;
+      ba.L = L;
+      ba.D = D;
+      ba.perm = perm;
+      ba.bsz = bsz;
+      double* sl = (double*)(w + oSlots);
+      ba.C1 = sl;
+      ba.CI = sl + nn;
+      ba.RK = sl + 2 * nn;
+      ba.RK1 = sl + 3 * nn;
+      ba.RI = sl + 4 * nn;
+      ba.err = (int*)(w + oErr);
+      const size_t lds = bk_coop_lds(n, G);
+      if (lds > 64 * 1024 &&
+          hipFuncSetAttribute((const void*)k_bk_coop, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+              hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, RIF_EHIP, "factorisation: LDS attribute failed");
+      }
+      hipLaunchKernelGGL(k_bk_coop_reset, dim3((unsigned)std::min(4096L, (5 * nn + 255) / 256)), dim3(256), 0,
+                         c->stream, (unsigned long long*)sl, 5 * nn, ba.err);
+      if ((st = check_launch(c, "prep_factorise_reset"))) return st;
+      void* args[] = {&ba};
+      const hipError_t he =
+          hipLaunchCooperativeKernel((const void*)k_bk_coop, dim3(G), dim3(256), args, (unsigned)lds, c->stream);
+      if (he != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, RIF_EHIP, std::string("cooperative launch of the factorisation failed: ") +
+                                     hipGetErrorString(he));
+      }
+      hipLaunchKernelGGL(k_bk_coop_check, dim3(1), dim3(64), 0, c->stream, (const int*)ba.err, D);
+    } else {
+      const unsigned gup = (unsigned)std::min(1024L, (nn + 255) / 256);
+      for (int it = 0; it < n; ++it) {
+        hipLaunchKernelGGL(k_bk_pivot, dim3(1), dim3(kPivThreads), 0, c->stream, n, A, L, D, perm, bsz, sp);
+        hipLaunchKernelGGL(k_bk_update, dim3(gup), dim3(256), 0, c->stream, n, A, L, (const BkState*)sp);
+      }
     }
     if ((st = check_launch(c, "prep_factorise"))) return st;
   }

@@ -28,4 +28,23 @@ __device__ __forceinline__ double wave_sum_dpp(double x) {
   return (lane_value(x, 0) + lane_value(x, 16)) + (lane_value(x, 32) + lane_value(x, 48));
 }
 
+// Max over the 64 lanes (all active) of doubles (NaN lanes ignored, as fmax
+// does) and min of ints, every lane getting the result; both are
+// order-free, so every wave gets the same value.
+__device__ __forceinline__ double wave_max_dpp(double x) {
+  x = fmax(x, dpp_move<0xB1>(x));
+  x = fmax(x, dpp_move<0x4E>(x));
+  x = fmax(x, dpp_move<0x124>(x));
+  x = fmax(x, dpp_move<0x128>(x));
+  return fmax(fmax(lane_value(x, 0), lane_value(x, 16)), fmax(lane_value(x, 32), lane_value(x, 48)));
+}
+__device__ __forceinline__ int wave_min_int_dpp(int x) {
+  x = min(x, __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));
+  x = min(x, __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));
+  x = min(x, __builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false));
+  x = min(x, __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false));
+  return min(min(__builtin_amdgcn_readlane(x, 0), __builtin_amdgcn_readlane(x, 16)),
+             min(__builtin_amdgcn_readlane(x, 32), __builtin_amdgcn_readlane(x, 48)));
+}
+
 }  // namespace rif

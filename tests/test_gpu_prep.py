@@ -3,7 +3,9 @@ the oracle (oracle/metric.py), through the C ABI.
 
 The factorisation is compared where it is unique given the pivot rule: the
 permutation exactly, L and D to 1e-10 (normwise), on SPD, indefinite,
-2x2-forcing and singular metrics.  b is compared with the oracle's to a bound
+2x2-forcing and singular metrics.  Up to about 1600 auxiliary functions it is
+the one-launch factorisation; a 1640-function metric takes the per-column
+launches and is checked the same way.  b is compared with the oracle's to a bound
 scaled by kappa(G~) (the solve amplifies rounding by it), and the number of
 raised eigenvalues exactly.  At full cyclohexane size (n_bf=348, n_aux=1044)
 with an ill-conditioned, slightly indefinite metric: the same, plus the RI
@@ -103,6 +105,20 @@ def test_singular_column(ctx):
     b, perm, L, D, nr = run(ctx, synth.make_three_centre(4, 12, 11), G)
     p0, L0, D0, _ = mt.bunch_kaufman(G)
     assert np.array_equal(perm, p0) and relerr(L, L0) < 1e-10 and relerr(D, D0) < 1e-10
+
+
+def test_large_metric_takes_the_per_column_path(ctx):
+    """1640 auxiliary functions: past what the one-launch factorisation holds in
+    LDS, so the pivot and update launches per column run (indefinite metric,
+    1x1 and 2x2 pivots)."""
+    n = 1640
+    print("case factorisation per-column path", n, flush=True)
+    G = sym(n, 7)
+    b, perm, L, D, nr = run(ctx, synth.make_three_centre(3, n, 12), G)
+    p0, L0, D0, steps = mt.bunch_kaufman(G)
+    assert 2 in steps and 1 in steps
+    assert np.array_equal(perm, p0)
+    assert relerr(L, L0) < 1e-10 and relerr(D, D0) < 1e-10
 
 
 def test_full_size_ill_conditioned_metric(ctx):
