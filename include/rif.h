@@ -330,6 +330,17 @@ rif_status rif_orbital_step(rif_ctx *ctx, int n_bf, int n_mo, int n_omega, const
 typedef enum { RIF_EIG_AUTO = 0, RIF_EIG_SYEVD = 1, RIF_EIG_TRD = 2 } rif_eigensolver;
 rif_status rif_set_eigensolver(rif_ctx *ctx, int kind, int groups);
 
+/* Bound on the waits inside the one-launch kernels (the tridiagonal reduction
+ * of rif_orbital_step, the factorisation of rif_prepare_b): the number of
+ * polls of one exchanged value before the kernel gives up (default 2^22,
+ * seconds).  Workgroups exchange values through slots that each consumer
+ * polls; a wait past the bound makes every workgroup return, and the call
+ * reports it: rif_orbital_step sets info = -1 (rif_pnof_optimize then fails
+ * with RIF_EHIP, status 2); rif_prepare_b leaves every element of b NaN.
+ * Negative: every such wait gives up at once (to exercise those paths).
+ * Per context; takes effect on the next call. */
+rif_status rif_set_wait_limit(rif_ctx *ctx, long long polls);
+
 /* Fig. 1 loop.  Each outer iteration: J, K (MO) and H_pp at the current
  * orbitals, then the ON optimisation (rif_on_optimize's L-BFGS, from the
  * current gamma); then inner iterations at the new ONs, each one build

@@ -93,6 +93,7 @@ EXPORTS = {
     "rif_prepare_b": (_i, [_vp, _i, _i, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp]),
     "rif_orbital_step": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]),
     "rif_set_eigensolver": (_i, [_vp, _i, _i]),
+    "rif_set_wait_limit": (_i, [_vp, ctypes.c_longlong]),
     "rif_pnof_optimize": (_i, [_vp, ctypes.POINTER(Instance), _i, _i, ctypes.POINTER(OptParams), _vp, _vp, _vp,
                                ctypes.POINTER(OptResult), _vp, _vp, _i]),
     "rif_autotune": (_i, [_vp, _i]),
@@ -415,6 +416,11 @@ class Context:
         return (b, perm, L, D, nr) if factors else b
 
     # ---- orbital optimisation and the outer/inner loop ----------------------
+    def set_wait_limit(self, polls=1 << 22):
+        """rif_set_wait_limit: polls of one exchanged value before the one-launch
+        kernels give up (negative: at once)."""
+        self._chk(self.lib.rif_set_wait_limit(self.h, int(polls)))
+
     def set_eigensolver(self, kind=EIG_AUTO, groups=0):
         """rif_set_eigensolver: EIG_TRD (one-launch tridiagonal reduction, then
         rocSOLVER dstedc/dormtr), EIG_SYEVD (rocSOLVER dsyevd) or EIG_AUTO."""

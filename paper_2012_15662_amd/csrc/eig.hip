@@ -52,7 +52,6 @@ constexpr int kTrdThreads = 256;
 constexpr int kTrdWaves = kTrdThreads / 64;
 constexpr size_t kTrdLds = 150 * 1024;        // dynamic LDS per workgroup, at most
 constexpr size_t kTrdLdsDefault = 64 * 1024;  // beyond this the kernel needs the attribute raised
-constexpr long kTrdSpinLimit = 1L << 22;      // polls of one value before it gives up
 constexpr unsigned long long kEmpty = 0x7FF4C0FFEE5E7F11ull;   // signalling NaN
 
 struct TrdArgs {
@@ -63,6 +62,7 @@ struct TrdArgs {
   double* Rb;             // [n][n] row i of A after H_{i-2}, in row i  (slots, kEmpty at launch)
   double* Pb;             // [n][n] p_k in row k
   int* err;               // set when a wait timed out
+  long long spin;         // polls of one value before giving up; < 0: give up at once
 };
 
 __device__ __forceinline__ double wave_sum(double x) { return wave_sum_dpp(x); }
@@ -74,11 +74,12 @@ __device__ __forceinline__ void put(double* p, double v) {
 __device__ __forceinline__ unsigned long long peek(const double* p) {
   return __hip_atomic_load((unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// The value of slot p once written; false past the poll limit or once another
-// workgroup has flagged a timeout.
-__device__ bool take(const double* p, unsigned long long u, double& out, const int* err) {
-  for (long s = 0; u == kEmpty; ++s) {
-    if (s >= kTrdSpinLimit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+// The value of slot p once written; false past the poll limit (at once for a
+// negative limit) or once another workgroup has flagged a timeout.
+__device__ bool take(const double* p, unsigned long long u, double& out, const int* err, long long spin) {
+  if (spin < 0) return false;
+  for (long long s = 0; u == kEmpty; ++s) {
+    if (s >= spin || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
     __builtin_amdgcn_s_sleep(1);
     u = peek(p);
   }
@@ -86,15 +87,15 @@ __device__ bool take(const double* p, unsigned long long u, double& out, const i
   return true;
 }
 // dst[j] = slot src[j] for j in [j0, j1), two loads in flight per thread
-__device__ bool take_range(const double* src, double* dst, int j0, int j1, const int* err) {
+__device__ bool take_range(const double* src, double* dst, int j0, int j1, const int* err, long long spin) {
   for (int j = j0 + (int)threadIdx.x; j < j1; j += 2 * kTrdThreads) {
     const int j2 = j + kTrdThreads;
     const unsigned long long u1 = peek(src + j), u2 = j2 < j1 ? peek(src + j2) : 0ull;
     double x;
-    if (!take(src + j, u1, x, err)) return false;
+    if (!take(src + j, u1, x, err, spin)) return false;
     dst[j] = x;
     if (j2 < j1) {
-      if (!take(src + j2, u2, x, err)) return false;
+      if (!take(src + j2, u2, x, err, spin)) return false;
       dst[j2] = x;
     }
   }
@@ -171,10 +172,10 @@ __global__ __launch_bounds__(kTrdThreads) void k_trd(TrdArgs a) {
         if (k == 0) {
           for (int j = m0 + tid; j < n; j += kTrdThreads) x[j] = a.F[(long)n + j];
         } else {
-          ok = take_range(a.Rb + (long)m0 * n, x, m0, n, a.err);
+          ok = take_range(a.Rb + (long)m0 * n, x, m0, n, a.err, a.spin);
         }
       }
-      ok = ok && take_range(Pk, p, m0, n, a.err);
+      ok = ok && take_range(Pk, p, m0, n, a.err, a.spin);
       if (!ok) atomicExch(a.err, 1);
       if (__syncthreads_or(!ok)) return;
     }
@@ -214,6 +215,16 @@ __global__ __launch_bounds__(kTrdThreads) void k_trd(TrdArgs a) {
     a.Q[(long)(g + G * t) * n + j] = qrows[y];
   }
   if ((n - 1) % G == g && tid == 0) a.d[n - 1] = rows[(long)((n - 1) / G) * n + (n - 1)];
+}
+
+// after a timed-out wait: T to zero, so the tridiagonal eigensolver that
+// follows runs on a valid matrix (the step then reports the timeout)
+__global__ __launch_bounds__(256) void k_trd_sanitize(int n, const int* err, double* d, double* e) {
+  if (*err == 0) return;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    d[i] = 0.0;
+    if (i + 1 < n) e[i] = 0.0;
+  }
 }
 
 // slots to kEmpty, the timeout flag to zero
@@ -263,6 +274,7 @@ rif_status op_trd(rif_ctx* c, int n, int G, const double* F, double* Q, double* 
   a.Rb = s;
   a.Pb = s + (long)n * n;
   a.err = err;
+  a.spin = c->wait_limit;
   const size_t lds = trd_lds(n, G);
   if (lds > kTrdLdsDefault) {
     const hipError_t he = hipFuncSetAttribute((const void*)k_trd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -283,7 +295,9 @@ rif_status op_trd(rif_ctx* c, int n, int G, const double* F, double* Q, double* 
     return fail(c, RIF_EHIP, std::string("cooperative launch of the tridiagonal reduction failed: ") +
                                  hipGetErrorString(he));
   }
-  return RIF_OK;
+  hipLaunchKernelGGL(k_trd_sanitize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, (const int*)err,
+                     d, e);
+  return check_launch(c, "trd_sanitize");
 }
 
 }  // namespace rif

@@ -306,7 +306,6 @@ __global__ __launch_bounds__(256) void k_compose(int n, const double* __restrict
 //      takes over a moved row (from RK, RK1 or RI), writes its L entries and
 //      updates its rows with the arithmetic of k_bk_pivot and k_bk_update.
 // Workgroup 0 keeps perm, the block sizes and D.
-constexpr long kBkSpinLimit = 1L << 22;
 constexpr unsigned long long kBkEmpty = 0x7FF4C0FFEE5E7F11ull;   // signalling NaN
 constexpr size_t kBkLds = 150 * 1024;
 
@@ -318,6 +317,7 @@ struct BkcArgs {
   double *C1, *CI;               // [n][n] slots: C1[k][i] = A_ik, CI[k][i] = A_i,imax
   double *RK, *RK1, *RI;         // [n][n] slots: whole rows k, k+1, imax at step k
   int* err;
+  long long spin;                // polls of one value before giving up; < 0: give up at once
 };
 
 __device__ __forceinline__ void bk_put(double* p, double v) {
@@ -328,11 +328,12 @@ __device__ __forceinline__ unsigned long long bk_peek(const double* p) {
   return __hip_atomic_load((unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // dst[j] = slot src[j] for j in [j0, j1), strided over the workgroup
-__device__ bool bk_take_range(const double* src, double* dst, int j0, int j1, const int* err) {
+__device__ bool bk_take_range(const double* src, double* dst, int j0, int j1, const int* err, long long spin) {
+  if (spin < 0) return false;
   for (int j = j0 + (int)threadIdx.x; j < j1; j += 256) {
     unsigned long long u = bk_peek(src + j);
-    for (long s = 0; u == kBkEmpty; ++s) {
-      if (s >= kBkSpinLimit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    for (long long s = 0; u == kBkEmpty; ++s) {
+      if (s >= spin || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
       __builtin_amdgcn_s_sleep(1);
       u = bk_peek(src + j);
     }
@@ -369,7 +370,7 @@ __global__ __launch_bounds__(256) void k_bk_coop(BkcArgs a) {
       if (k == 0)
         for (int t = wv; t < R; t += 4)
           if (lane == 0) bk_put(C1k + g + G * t, rows[(long)t * n]);
-      const bool ok = bk_take_range(C1k, c1, k, n, a.err);
+      const bool ok = bk_take_range(C1k, c1, k, n, a.err, a.spin);
       if (!ok) fail();
       if (__syncthreads_or(!ok)) return;
     }
@@ -401,8 +402,8 @@ __global__ __launch_bounds__(256) void k_bk_coop(BkcArgs a) {
         for (int j = tid; j < n; j += 256) bk_put(a.RK + (long)k * n + j, rows[(long)(k / G) * n + j]);
       if ((k + 1) % G == g)
         for (int j = tid; j < n; j += 256) bk_put(a.RK1 + (long)k * n + j, rows[(long)((k + 1) / G) * n + j]);
-      bool ok = bk_take_range(CIk, ci, k, n, a.err);
-      ok = ok && bk_take_range(RIk, ri, k, n, a.err);
+      bool ok = bk_take_range(CIk, ci, k, n, a.err, a.spin);
+      ok = ok && bk_take_range(RIk, ri, k, n, a.err, a.spin);
       if (!ok) fail();
       if (__syncthreads_or(!ok)) return;
       double rm = 0.0;
@@ -443,7 +444,7 @@ __global__ __launch_bounds__(256) void k_bk_coop(BkcArgs a) {
         }
       }
       if (from) {
-        const bool ok = bk_take_range(from, rows + (long)tdst * n, 0, n, a.err);
+        const bool ok = bk_take_range(from, rows + (long)tdst * n, 0, n, a.err, a.spin);
         if (!ok) fail();
         if (__syncthreads_or(!ok)) return;
       }
@@ -523,9 +524,14 @@ __global__ void k_bk_coop_reset(unsigned long long* slots, long count, int* err)
   for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < count; i += (long)gridDim.x * 256) slots[i] = kBkEmpty;
   if (blockIdx.x == 0 && threadIdx.x == 0) *err = 0;
 }
-// a timed-out factorisation leaves NaN in D, so b comes out NaN, never silently wrong
-__global__ void k_bk_coop_check(const int* err, double* D) {
-  if (threadIdx.x == 0 && *err != 0) D[0] = __longlong_as_double(0x7FF8000000000000ll);
+// a timed-out factorisation leaves 1x1 blocks of NaN on the diagonal of D, so
+// every slab of b comes out NaN, never silently wrong
+__global__ void k_bk_coop_check(int n, const int* err, double* D, int* bsz) {
+  if (*err == 0) return;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    D[(long)i * n + i] = __longlong_as_double(0x7FF8000000000000ll);
+    bsz[i] = 1;
+  }
 }
 
 size_t bk_coop_lds(int n, int G) { return (size_t)(((n + G - 1) / G) + 5L) * n * sizeof(double); }
@@ -688,6 +694,7 @@ rif_status op_prepare_b(rif_ctx* c, int nb, int na, const double* T, const doubl
       ba.RK1 = sl + 3 * nn;
       ba.RI = sl + 4 * nn;
       ba.err = (int*)(w + oErr);
+      ba.spin = c->wait_limit;
       const size_t lds = bk_coop_lds(n, G);
       if (lds > 64 * 1024 &&
           hipFuncSetAttribute((const void*)k_bk_coop, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
@@ -706,7 +713,8 @@ rif_status op_prepare_b(rif_ctx* c, int nb, int na, const double* T, const doubl
         return fail(c, RIF_EHIP, std::string("cooperative launch of the factorisation failed: ") +
                                      hipGetErrorString(he));
       }
-      hipLaunchKernelGGL(k_bk_coop_check, dim3(1), dim3(64), 0, c->stream, (const int*)ba.err, D);
+      hipLaunchKernelGGL(k_bk_coop_check, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n,
+                         (const int*)ba.err, D, bsz);
     } else {
       const unsigned gup = (unsigned)std::min(1024L, (nn + 255) / 256);
       for (int it = 0; it < n; ++it) {

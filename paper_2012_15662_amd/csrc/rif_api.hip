@@ -298,6 +298,12 @@ rif_status rif_set_eigensolver(rif_ctx* c, int kind, int groups) {
   return RIF_OK;
 }
 
+rif_status rif_set_wait_limit(rif_ctx* c, long long polls) {
+  if (!c) return RIF_EINVAL;
+  c->wait_limit = polls;
+  return RIF_OK;
+}
+
 rif_status rif_pnof_optimize(rif_ctx* c, const rif_instance* in, rif_prec prec, rif_functional fn,
                              const rif_opt_params* par, double* C, double* occ, double* gamma, rif_opt_result* res,
                              double* hist_e, double* hist_g, int hist_len) {

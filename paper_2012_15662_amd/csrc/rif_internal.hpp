@@ -40,6 +40,9 @@ struct rif_ctx {
   // orbital-step eigensolver (rif_set_eigensolver): kind and workgroup count
   int eig_kind = 0;
   int eig_groups = 0;
+  // polls of one exchanged value before a cooperative kernel gives up
+  // (rif_set_wait_limit; negative: every wait gives up at once)
+  long long wait_limit = 1LL << 22;
 };
 
 namespace rif {
@@ -134,7 +137,7 @@ rif_status op_prepare_b(rif_ctx* c, int nb, int na, const double* T, const doubl
 int trd_groups(rif_ctx* c, int n, int want);
 size_t trd_scratch_bytes(int n);
 rif_status op_trd(rif_ctx* c, int n, int G, const double* F, double* Q, double* d, double* e, void* scratch,
-                  int* err);
+                  int* err);   // waits bounded by c->wait_limit
 
 // Orbital optimisation (orbital.hip)
 rif_status op_maxabs(rif_ctx* c, long n, const double* x, double* part, double* out);
