@@ -385,6 +385,7 @@ def bench_prep(args):
     G = synth.make_metric(na, 20, cond=1e10, n_negative=3)
     T = synth.make_three_centre(nb, na, 21)
     ctx = rif.Context(0)
+    ctx.autotune(True)   # the solve GEMM's tile, measured in the warm-up
     Td, Gd = torch.from_numpy(T).cuda(), torch.from_numpy(G).cuda()
     b = torch.empty_like(Td)
     for _ in range(max(1, args.warmup)):

@@ -16,7 +16,7 @@
 //                launch; k_linv (one column step at a time, rank-1 updates)
 //                above 2048 auxiliary functions
 //   k_compose    M^T[perm[i]][k] = sum_r D~^(-1/2)[k][r] X[r][i]
-//   then b^T = M T on the FP64 MFMA GEMM, over the packed upper triangles of
+//   then b^T = M T on the FP64 MFMA GEMM (tile chosen per shape), over the packed upper triangles of
 //   the slabs (k_pack_upper before, k_unpack_sym after).
 //
 // Pivot rule (alpha = (1 + sqrt 17)/8) at column k, with colmax/imax the
@@ -760,7 +760,7 @@ rif_status op_prepare_b(rif_ctx* c, int nb, int na, const double* T, const doubl
     const unsigned g = (unsigned)std::min(rows, 65536L);
     hipLaunchKernelGGL(k_pack_upper, dim3(g), dim3(256), 0, c->stream, nb, rows, T, Tp);
     if ((st = check_launch(c, "prep_pack"))) return st;
-    if ((st = op_gemm_kn(c, n, (int)npk, n, Mt, n, Tp, npk, bp, npk))) return st;
+    if ((st = op_gemm_big(c, n, (int)npk, n, Mt, n, Tp, npk, bp, npk))) return st;
     const int nbt = (nb + kUT - 1) / kUT;
     const long ntiles = (long)n * (nbt * (nbt + 1) / 2);
     hipLaunchKernelGGL(k_unpack_sym, dim3((unsigned)std::min(ntiles, 65536L)), dim3(256), 0, c->stream, nb, ntiles,

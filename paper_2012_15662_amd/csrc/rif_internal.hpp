@@ -126,6 +126,11 @@ rif_status op_build_direct(rif_ctx* c, int prec, int functional, const rif_insta
 rif_status op_gemm_kn(rif_ctx* c, int M, int N, int K, const double* A, long lda, const double* B, long ldb,
                       double* out, long ldo);
 
+// The same product with the tile shape chosen per problem (gemm.hip), for the
+// large one-off product of the b preparation.
+rif_status op_gemm_big(rif_ctx* c, int M, int N, int K, const double* A, long lda, const double* B, long ldb,
+                       double* out, long ldo);
+
 // b from the three-centre integrals and the metric (prep.hip)
 rif_status op_prepare_b(rif_ctx* c, int nb, int na, const double* T, const double* G, double delta, double* b,
                         int* perm, double* L, double* D, int* nraised);
