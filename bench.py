@@ -180,6 +180,28 @@ def bench_batch(args):
     el_seq = time.perf_counter() - t1
     ctx.sync()
     per = el / args.steps
+    presplit = None
+    if prec != MODES["fp64"]:
+        # the same batch with every b stored once in this mode's pieces
+        # (rif_presplit_b; bitwise the same results)
+        items2 = []
+        for inp, npair, ncwo, _ in items:
+            inp2 = dict(inp)
+            inp2["b_split"] = ctx.presplit_b(inp["b"], prec)
+            items2.append((inp2, npair, ncwo, None))
+        batch2 = ctx.batch(items2, prec=prec)
+        for _ in range(max(args.warmup, 1)):
+            batch2.run(use_graph=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(args.steps):
+            batch2.run(use_graph=True)
+        torch.cuda.synchronize()
+        per2 = (time.perf_counter() - t2) / args.steps
+        batch2.close()
+        del items2
+        presplit = {"builds_s": round(64 / per2, 2), "ms_per_step": round(per2 * 1e3, 3),
+                    "vs_split_on_load": round(per / per2, 3)}
     line = {
         "metric": METRIC, "value": round(64 / per, 2), "unit": "builds/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(per * 1e3, 3),
@@ -191,6 +213,7 @@ def bench_batch(args):
                    "precision": args.prec},
         "tflops": round(flops / per / 1e12, 2), "flops_per_step": flops,
         "sequential_builds_s": round(64 / el_seq, 2), "batch_speedup": round(el_seq / per, 3),
+        "presplit_b": presplit,
         "tiles": [t for t in ctx.tune_report().strip().splitlines() if t.startswith("g_")],
     }
     batch.close()
