@@ -3,9 +3,11 @@ the oracle (oracle/metric.py), through the C ABI.
 
 The factorisation is compared where it is unique given the pivot rule: the
 permutation exactly, L and D to 1e-10 (normwise), on SPD, indefinite,
-2x2-forcing and singular metrics.  Up to about 1600 auxiliary functions it is
-the one-launch factorisation; a 1640-function metric takes the per-column
-launches and is checked the same way.  b is compared with the oracle's to a bound
+2x2-forcing and singular metrics, up to 600 functions (several rows per
+workgroup of the one-launch factorisation, with interchanges across and within
+workgroups).  Up to about 1600 auxiliary functions it is the one-launch
+factorisation; a 1640-function metric takes the per-column launches and is
+checked the same way.  b is compared with the oracle's to a bound
 scaled by kappa(G~) (the solve amplifies rounding by it), and the number of
 raised eigenvalues exactly.  At full cyclohexane size (n_bf=348, n_aux=1044)
 with an ill-conditioned, slightly indefinite metric: the same, plus the RI
@@ -79,6 +81,8 @@ def raised_count(D, steps, delta):
     ("indefinite_150", sym(150, 4)),
     ("forced_2x2_101", sym(101, 5, zero_diag=True)),
     ("one_aux", np.array([[2.5]])),
+    ("indefinite_600", sym(600, 9)),
+    ("forced_2x2_520", sym(520, 10, zero_diag=True)),
 ])
 def test_factorisation_matches_oracle(ctx, name, G):
     print("case factorisation", name, G.shape, flush=True)
@@ -105,6 +109,36 @@ def test_singular_column(ctx):
     b, perm, L, D, nr = run(ctx, synth.make_three_centre(4, 12, 11), G)
     p0, L0, D0, _ = mt.bunch_kaufman(G)
     assert np.array_equal(perm, p0) and relerr(L, L0) < 1e-10 and relerr(D, D0) < 1e-10
+
+
+def crafted_interchange(kind, n=300, seed=8):
+    """A diagonally dominant metric whose first pivot step interchanges two rows
+    held by one workgroup of the one-launch factorisation (256 workgroups, row
+    i in workgroup i mod 256): a 1x1 pivot at row 256 (0 <-> 256), or a 2x2
+    pivot on (0, 257) (1 <-> 257)."""
+    rng = np.random.default_rng(seed)
+    X = 0.01 * rng.standard_normal((n, n))
+    G = (X + X.T) / 2 + np.diag(rng.uniform(1.0, 2.0, n))
+    G[0, 0] = 1e-3
+    if kind == "1x1":
+        G[0, 256] = G[256, 0] = 1.0
+        G[256, 256] = 5.0
+    else:
+        G[0, 257] = G[257, 0] = 1.0
+        G[257, 257] = 1e-3
+    return G
+
+
+@pytest.mark.parametrize("kind", ["1x1", "2x2"])
+def test_interchange_within_one_workgroup(ctx, kind):
+    print("case factorisation interchange within a workgroup", kind, flush=True)
+    G = crafted_interchange(kind)
+    b, perm, L, D, nr = run(ctx, synth.make_three_centre(4, G.shape[0], 13), G)
+    p0, L0, D0, steps = mt.bunch_kaufman(G)
+    assert steps[0] == (1 if kind == "1x1" else 2)
+    assert p0[0 if kind == "1x1" else 1] == (256 if kind == "1x1" else 257)
+    assert np.array_equal(perm, p0)
+    assert relerr(L, L0) < 1e-10 and relerr(D, D0) < 1e-10
 
 
 def test_large_metric_takes_the_per_column_path(ctx):
