@@ -425,9 +425,10 @@ def bench_prep(args):
     prof = ctx.profile_report()
     ctx.profile(False)
     phases = {k: round(ms / n, 3) for k, (n, ms) in prof.items() if k.startswith("prep_")}
-    # the solve runs on the packed upper triangles of the slabs (phase time
-    # includes the packing and the mirrored unpacking)
-    gemm_flops = 2.0 * na * na * nb * (nb + 1) / 2
+    # the solve runs on the packed upper triangles of the slabs with the
+    # triangular factor's zeros skipped: n_aux^2 n_bf (n_bf + 1) / 2 flops
+    # (phase time includes the packing and the mirrored unpacking)
+    gemm_flops = 1.0 * na * na * nb * (nb + 1) / 2
     gemm_ms = phases.get("prep_solve_gemm")
     cpu = None
     if not args.no_cpu:

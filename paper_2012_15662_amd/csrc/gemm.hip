@@ -2,7 +2,9 @@
 // strides lda, ldb, ldo) with the tile shape chosen per problem.  It serves the
 // large one-off product outside the build, the solve of the b preparation
 // (n_aux x n_bf(n_bf+1)/2 x n_aux), where the build's fixed 64x64 small-GEMM
-// tile leaves MFMA time unused.  Same engine,
+// tile leaves MFMA time unused.  With lower_a, A is zero past its first
+// superdiagonal (A[k][m] = 0 for k > m + 1) and each row tile stops its k range
+// there, so only exact zeros are skipped.  Same engine,
 // loader and main loop as the build's GEMM steps (mfma_engine.hpp); tiles run
 // m-fastest, so consecutive workgroups share the panel of B.
 #include <algorithm>
@@ -21,6 +23,7 @@ struct BigGemm {
   long ldb;
   double* out;
   long ldo;
+  int lower;   // A[k][m] = 0 for k > m + 1: a row tile m0 stops at k = m0 + BM + 1
 };
 
 using E64 = EngineOf<kF64>::type;
@@ -45,12 +48,13 @@ k_gemm_big(BigGemm a) {
   const int nmt = (a.M + Cfg::BM - 1) / Cfg::BM;
   const int m0 = (int)(t % nmt) * Cfg::BM, n0 = (int)(t / nmt) * Cfg::BN;
   const int M = a.M, N = a.N;
+  const int K = a.lower ? min(a.K, m0 + Cfg::BM + 1) : a.K;   // only exact zeros are skipped
   XCSrc<double, Cfg::BM, E64::BK, Cfg::NT, E64::KV> la;
-  la.init(a.A, a.lda, a.K, [&](int x, long& o) { o = m0 + x; return m0 + x < M; });
+  la.init(a.A, a.lda, K, [&](int x, long& o) { o = m0 + x; return m0 + x < M; });
   XCSrc<double, Cfg::BN, E64::BK, Cfg::NT, E64::KV> lb;
-  lb.init(a.B, a.ldb, a.K, [&](int x, long& o) { o = n0 + x; return n0 + x < N; });
+  lb.init(a.B, a.ldb, K, [&](int x, long& o) { o = n0 + x; return n0 + x < N; });
   typename E64::template Acc<Cfg> acc;
-  gemm_mainloop<E64, Cfg>(la, lb, (a.K + E64::BK - 1) / E64::BK, acc, smem);
+  gemm_mainloop<E64, Cfg>(la, lb, (K + E64::BK - 1) / E64::BK, acc, smem);
   acc.for_each([&](int m, int n, double v) {
     if (m0 + m < M && n0 + n < N) a.out[(long)(m0 + m) * a.ldo + n0 + n] = v;
   });
@@ -80,8 +84,8 @@ double big_cost(const BigGemm& a) {
 }  // namespace
 
 rif_status op_gemm_big(rif_ctx* c, int M, int N, int K, const double* A, long lda, const double* B, long ldb,
-                       double* out, long ldo) {
-  const BigGemm a{M, N, K, A, lda, B, ldb, out, ldo};
+                       double* out, long ldo, bool lower_a) {
+  const BigGemm a{M, N, K, A, lda, B, ldb, out, ldo, lower_a ? 1 : 0};
   auto run = [&](int v) -> rif_status {
     return with_big(v, [&](auto cfg) {
       using Cfg = decltype(cfg);
@@ -95,7 +99,7 @@ rif_status op_gemm_big(rif_ctx* c, int M, int N, int K, const double* A, long ld
     const double e = with_big(v, [&](auto cfg) { return big_cost<decltype(cfg)>(a); });
     if (e < best) { best = e; hv = v; }
   }
-  const int v = pick_variant(c, "gemm", {M, N, K}, kBigVariants, hv, run);
+  const int v = pick_variant(c, "gemm", {M, N, K, lower_a ? 1 : 0}, kBigVariants, hv, run);
   if (v < 0) return RIF_EHIP;
   ProfScope ps(c, "gemm");
   return run(v);

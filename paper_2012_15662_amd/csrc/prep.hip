@@ -15,7 +15,8 @@
 //   k_linv_rows  X = L^-1, one wave per column (forward substitution), one
 //                launch; k_linv (one column step at a time, rank-1 updates)
 //                above 2048 auxiliary functions
-//   k_compose    M^T[perm[i]][k] = sum_r D~^(-1/2)[k][r] X[r][i]
+//   k_compose    M'^T[i][k] = sum_r D~^(-1/2)[k][r] X[r][i]  (M' = D~^(-1/2) L^-1,
+//                zero right of its first superdiagonal)
 //   then b^T = M T on the FP64 MFMA GEMM (tile chosen per shape), over the packed upper triangles of
 //   the slabs (k_pack_upper before, k_unpack_sym after).
 //
@@ -272,15 +273,14 @@ __global__ __launch_bounds__(256) void k_linv(int n, int k, const double* __rest
 
 // M^T[perm[i]][k] = sum_r Dih[k][r] X[r][i] (Dih block diagonal: r in k's block).
 __global__ __launch_bounds__(256) void k_compose(int n, const double* __restrict__ Dih, const int* __restrict__ bsz,
-                                                 const double* __restrict__ X, const int* __restrict__ perm,
-                                                 double* __restrict__ Mt) {
+                                                 const double* __restrict__ X, double* __restrict__ Mt) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e >= (long)n * n) return;
   const int k = (int)(e / n), i = (int)(e - (long)k * n);
   double v = Dih[(long)k * n + k] * X[(long)k * n + i];
   if (k + 1 < n && bsz[k] == 2) v += Dih[(long)k * n + k + 1] * X[(long)(k + 1) * n + i];
   if (k > 0 && bsz[k] == 0) v += Dih[(long)k * n + k - 1] * X[(long)(k - 1) * n + i];
-  Mt[(long)perm[i] * n + k] = v;
+  Mt[(long)i * n + k] = v;
 }
 
 // ---- the factorisation in one cooperative launch -----------------------------
@@ -586,16 +586,18 @@ __global__ __launch_bounds__(256) void k_linv_rows(int n, const double* __restri
 }
 
 // The solve works on the upper triangle of each slab only (T and b are
-// symmetric in mu, nu): packed by rows, Tp[k][o(mu) + nu - mu] = T[k][mu][nu]
-// for nu >= mu, o(mu) = mu nb - mu (mu - 1) / 2.  One workgroup per (k, mu)
-// row, grid-strided; reads and writes both run along nu.
+// symmetric in mu, nu), with the slabs in pivot order: packed by rows,
+// Tp[i][o(mu) + nu - mu] = T[perm[i]][mu][nu] for nu >= mu,
+// o(mu) = mu nb - mu (mu - 1) / 2, so that b^T = M' Tp with M' = D~^(-1/2) L^-1
+// (the (P^T T)[i] = T[perm[i]] of the solve).  One workgroup per (i, mu) row,
+// grid-strided; reads and writes both run along nu.
 __global__ __launch_bounds__(256) void k_pack_upper(int nb, long rows, const double* __restrict__ T,
-                                                    double* __restrict__ Tp) {
+                                                    const int* __restrict__ perm, double* __restrict__ Tp) {
   const long npk = (long)nb * (nb + 1) / 2;
   for (long rr = blockIdx.x; rr < rows; rr += gridDim.x) {
     const long k = rr / nb;
     const int mu = (int)(rr - k * nb);
-    const double* src = T + (k * nb + mu) * nb;
+    const double* src = T + ((long)perm[k] * nb + mu) * nb;
     double* dst = Tp + k * npk + (long)mu * nb - (long)mu * (mu - 1) / 2 - mu;
     for (int nu = mu + threadIdx.x; nu < nb; nu += 256) dst[nu] = src[nu];
   }
@@ -746,21 +748,23 @@ rif_status op_prepare_b(rif_ctx* c, int nb, int na, const double* T, const doubl
         hipLaunchKernelGGL(k_linv, dim3(g), dim3(256), 0, c->stream, n, k, L, X);
       }
     }
-    hipLaunchKernelGGL(k_compose, dim3(gnn), dim3(256), 0, c->stream, n, Dih, bsz, X, perm, Mt);
+    hipLaunchKernelGGL(k_compose, dim3(gnn), dim3(256), 0, c->stream, n, Dih, bsz, X, Mt);
     if ((st = check_launch(c, "prep_correct_invert"))) return st;
   }
   {
     ProfScope ps(c, "prep_solve_gemm");
-    // b^T[k][mu nu] = sum_j M[k][j] T[j][mu nu] on the packed upper triangles
-    // (A operand M^T, j-major; B the packed T, staged in b's own buffer, which
-    // is free until the unpacking writes it), then mirrored into b
+    // b^T[k][mu nu] = sum_i M'[k][i] T[perm[i]][mu nu] on the packed upper
+    // triangles (A operand M'^T, i-major; B the packed T in pivot order,
+    // staged in b's own buffer, which is free until the unpacking writes it),
+    // then mirrored into b
     double* Tp = b;
     double* bp = (double*)(w + oBp);
     const long rows = (long)n * nb;
     const unsigned g = (unsigned)std::min(rows, 65536L);
-    hipLaunchKernelGGL(k_pack_upper, dim3(g), dim3(256), 0, c->stream, nb, rows, T, Tp);
+    hipLaunchKernelGGL(k_pack_upper, dim3(g), dim3(256), 0, c->stream, nb, rows, T, (const int*)perm, Tp);
     if ((st = check_launch(c, "prep_pack"))) return st;
-    if ((st = op_gemm_big(c, n, (int)npk, n, Mt, n, Tp, npk, bp, npk))) return st;
+    // M' is zero right of its first superdiagonal: row tile m0 needs k < m0 + BM + 1 only
+    if ((st = op_gemm_big(c, n, (int)npk, n, Mt, n, Tp, npk, bp, npk, true))) return st;
     const int nbt = (nb + kUT - 1) / kUT;
     const long ntiles = (long)n * (nbt * (nbt + 1) / 2);
     hipLaunchKernelGGL(k_unpack_sym, dim3((unsigned)std::min(ntiles, 65536L)), dim3(256), 0, c->stream, nb, ntiles,

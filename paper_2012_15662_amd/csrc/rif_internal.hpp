@@ -128,8 +128,9 @@ rif_status op_gemm_kn(rif_ctx* c, int M, int N, int K, const double* A, long lda
 
 // The same product with the tile shape chosen per problem (gemm.hip), for the
 // large one-off product of the b preparation.
+// lower_a: A[k][m] = 0 for k > m + 1 (those products are skipped).
 rif_status op_gemm_big(rif_ctx* c, int M, int N, int K, const double* A, long lda, const double* B, long ldb,
-                       double* out, long ldo);
+                       double* out, long ldo, bool lower_a = false);
 
 // b from the three-centre integrals and the metric (prep.hip)
 rif_status op_prepare_b(rif_ctx* c, int nb, int na, const double* T, const double* G, double delta, double* b,
