@@ -278,9 +278,14 @@ rif_status rif_adam(rif_ctx *ctx, int n, float *theta, const float *grad, float 
  *   the packed upper triangles; b's buffer also stages them)
  *   optional (NULL to skip): perm [n_aux] (P^T x)[i] = x[perm[i]]; L and D
  *   [n_aux][n_aux] dense; n_raised: number of raised eigenvalues
- * delta <= 0 takes 2^-26 * max_k sum_l |G_kl|.  Uses 6 n_aux^2 +
- * n_aux n_bf (n_bf + 1) / 2 doubles of the context arena.  Asynchronous.  RIF_EINVAL for sizes (n_aux < 46341) or NULL
- * T, G, b. */
+ * delta <= 0 takes 2^-26 * max_k sum_l |G_kl|.  The factorisation runs as
+ * one cooperative launch where the metric's rows fit the LDS of at most 256
+ * workgroups (n_aux up to about 1600; its waits are bounded by
+ * rif_set_wait_limit, and a timed-out one leaves b all NaN), else as a pivot
+ * and an update launch per column.  Uses 6 n_aux^2 + n_aux n_bf (n_bf + 1) / 2
+ * doubles of the context arena, plus 5 n_aux^2 for the one-launch
+ * factorisation's exchange slots.  Asynchronous.  RIF_EINVAL for sizes
+ * (n_aux < 46341) or NULL T, G, b. */
 rif_status rif_prepare_b(rif_ctx *ctx, int n_bf, int n_aux, const double *T, const double *G, double delta,
                          double *b, int *perm, double *L, double *D, int *n_raised);
 
@@ -302,7 +307,8 @@ rif_status rif_prepare_b(rif_ctx *ctx, int n_bf, int n_aux, const double *T, con
  *   eps_in  [n_mo] diagonal of F^lambda, or NULL for lambda_pp
  *   C       [n_bf][n_mo] in/out: replaced by C V, V the eigenvectors
  *   eps_out [n_mo] eigenvalues, ascending (may be eps_in)
- *   info    device int or NULL: 0, or the eigensolver's failure count
+ *   info    device int or NULL: 0; > 0 rocSOLVER's failure count; -1 a
+ *           timed-out wait of the one-launch reduction (rif_set_wait_limit)
  * The eigen-decomposition runs on the context's stream with its workspace in
  * the context arena (solver chosen by rif_set_eigensolver); the rotation is an
  * FP64 MFMA GEMM.  info = -1 reports a timed-out wait inside the tridiagonal
