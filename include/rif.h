@@ -399,6 +399,12 @@ rif_status rif_tune_report(rif_ctx *ctx, char *buf, int len);
  * (truncated to len bytes, NUL-terminated).  Enabling again clears totals. */
 rif_status rif_profile_enable(rif_ctx *ctx, int on);
 rif_status rif_profile_report(rif_ctx *ctx, char *buf, int len);
+/* Restrict recording to launches whose report name equals name (a copy is
+ * kept); NULL or "" records every launch again.  With one kernel selected the
+ * recording adds two event records per launch of that kernel and nothing
+ * elsewhere, so a timed loop can carry it.  Takes effect for launches issued
+ * after the call; unknown names simply record nothing. */
+rif_status rif_profile_only(rif_ctx *ctx, const char *name);
 
 #ifdef __cplusplus
 }

@@ -101,6 +101,7 @@ EXPORTS = {
     "rif_tune_report": (_i, [_vp, ctypes.c_char_p, _i]),
     "rif_profile_enable": (_i, [_vp, _i]),
     "rif_profile_report": (_i, [_vp, ctypes.c_char_p, _i]),
+    "rif_profile_only": (_i, [_vp, ctypes.c_char_p]),
 }
 
 _lib = None
@@ -502,7 +503,10 @@ class Context:
         return buf.value.decode()
 
     # ---- per-kernel timing ------------------------------------------------
-    def profile(self, on: bool = True):
+    def profile(self, on: bool = True, only: str | None = None):
+        """Start (or stop) per-launch event timing; `only` restricts it to
+        launches of that report name."""
+        self._chk(self.lib.rif_profile_only(self.h, only.encode() if only else None))
         self._chk(self.lib.rif_profile_enable(self.h, 1 if on else 0))
 
     def profile_report(self) -> dict:

@@ -88,6 +88,7 @@ int pick_variant(rif_ctx* c, const char* kernel, std::initializer_list<long> sha
 
 ProfScope::ProfScope(rif_ctx* c_, const char* name) : c(c_) {
   if (!c->prof) return;
+  if (!c->prof_only.empty() && c->prof_only != name) return;
   auto get = [&]() {
     hipEvent_t e;
     if (!c->pool.empty()) {
@@ -523,6 +524,12 @@ rif_status rif_profile_enable(rif_ctx* c, int on) {
   c->evs.clear();
   c->totals.clear();
   c->prof = on != 0;
+  return RIF_OK;
+}
+
+rif_status rif_profile_only(rif_ctx* c, const char* name) {
+  if (!c) return RIF_EINVAL;
+  c->prof_only = name ? name : "";
   return RIF_OK;
 }
 

@@ -21,6 +21,7 @@ struct rif_ctx {
   int* dflag = nullptr;       // device status word for device-side validation
   // profiling
   bool prof = false;
+  std::string prof_only;      // non-empty: record only launches of this name
   struct Ev { std::string name; hipEvent_t a, b; };
   std::vector<Ev> evs;        // recorded pairs, not yet folded
   std::vector<hipEvent_t> pool;

@@ -202,3 +202,32 @@ def test_autotune_picks_and_matches(ctx):
     assert relerr(host(o["grad"]), ref["grad"]) < TOL
     assert abs(float(host(o["energy"])[0]) - ref["energy"]) < TOL * abs(ref["energy"])
     c2.close()
+
+
+def test_profile_all_and_one_kernel(ctx):
+    """Per-launch event timing: every kernel by default, one named kernel with
+    rif_profile_only, and the results of the profiled builds unchanged."""
+    inst = synth.make_instance(64, 150, 5, 2, 41)
+    t = to_dev(inst)
+    args = (t["b"], t["C"], t["H"], t["occ"], t["pair_of"], inst.n_pairs, inst.n_cwo)
+    o0 = ctx.build(*args)
+    ref = host(o0["grad"]).copy()
+    try:
+        ctx.profile(True)
+        ctx.build(*args)
+        ctx.build(*args)
+        allk = ctx.profile_report()
+        assert {"half_transform", "mo_transform", "jao", "kao", "fock"} <= set(allk), allk
+        assert allk["half_transform"][0] == 2 and allk["kao"][0] == 2, allk
+        ctx.profile(True, only="half_transform")
+        for _ in range(3):
+            o = ctx.build(*args)
+        one = ctx.profile_report()
+        assert set(one) == {"half_transform"}, one
+        assert one["half_transform"][0] == 3 and one["half_transform"][1] > 0.0
+        assert np.array_equal(host(o["grad"]), ref)
+        ctx.profile(True, only="no_such_kernel")
+        ctx.build(*args)
+        assert ctx.profile_report() == {}
+    finally:
+        ctx.profile(False)
