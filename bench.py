@@ -25,9 +25,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "RI-PNOF7 J/K+gradient builds/s & TFLOP/s; split-prec vs FP64 at 1 µEh"
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0}   # dense MFMA TFLOP/s
-MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
-PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}   # MFMA products per multiply-add
-MODE_PEAK = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16"}
+MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "fp16x3": 4}
+PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6, "fp16x3": 3}   # MFMA products per multiply-add
+MODE_PEAK = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16", "fp16x3": "f16"}
 HBM_GBS = 8000.0
 
 # HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc runs
@@ -37,7 +37,7 @@ HBM_GBS = 8000.0
 # were taken on: a figure is reported only while those sources are unchanged.
 # The runs and their command lines are in profiles/.
 TRAFFIC = {
-    ("half_transform", "c6h12", "fp64"): {"src": "21a6f16958c6ce72", "fetch": 1174048034, "write": 348779520,
+    ("half_transform", "c6h12", "fp64"): {"src": "f134890d431a402b", "fetch": 1174038750, "write": 348779520,
                                          "profile": "profiles/fp64_c6h12_counters.md"},
 }
 
@@ -184,7 +184,7 @@ def bench_batch(args):
     ctx.sync()
     per = el / args.steps
     presplit = None
-    if prec != MODES["fp64"]:
+    if prec not in (MODES["fp64"], MODES["fp16x3"]):
         # the same batch with every b stored once in this mode's pieces
         # (rif_presplit_b; bitwise the same results)
         items2 = []
@@ -209,7 +209,7 @@ def bench_batch(args):
         "metric": METRIC, "value": round(64 / per, 2), "unit": "builds/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(per * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16"}[args.prec],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16", "fp16x3": "f16"}[args.prec],
         "data": "synthetic",
         "config": {"workload": "batch64: 64 molecules, n_bf ~ U{60..400} (seed 3), n_aux = 3 n_bf, "
                                "pairs = n_bf//12, Ncwo = 2; one step = all 64 builds",
@@ -551,7 +551,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16"}[args.prec],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16", "fp16x3": "f16"}[args.prec],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: n_bf={nb} n_aux={na} pairs={inst.n_pairs} "
                                f"ncwo={inst.n_cwo} n_omega={nw} n_mo={nmo}, 30 rotated C",
@@ -586,7 +586,7 @@ def main():
             modes[name] = {"builds_s": round(n2 / el2, 2), "speedup": round((n2 / el2) / builds_s, 3),
                            "tflops": round(flops * n2 / el2 / 1e12, 2),
                            "dE_vs_" + args.prec: float(o2["energy"].cpu()[0]) - e_main}
-            if name != "fp64" and MODES[args.prec] == MODES["fp64"]:
+            if name not in ("fp64", "fp16x3") and MODES[args.prec] == MODES["fp64"]:
                 # b stored once in this mode's pieces (rif_presplit_b); same results
                 bs = ctx.presplit_b(b, pv)
                 el4, _, _ = time_builds(ctx, b, Cd, H, occ, pm, inst, pv, n2, 2, b_split=bs)

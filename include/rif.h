@@ -53,7 +53,11 @@ typedef enum {
   RIF_FP32 = 1,
   RIF_BF16X3 = 2,   /* two bf16 pieces, three products */
   RIF_BF16X6 = 3,   /* three bf16 pieces, six products */
-  RIF_FP16X3 = 4    /* fp16 high piece + scaled fp16 low piece, three products */
+  RIF_FP16X3 = 4    /* fp16 high piece + fp16 low piece scaled by 2^11, three
+                       products (hi.hi + 2^-11 (hi.lo + lo.hi)); every operand of
+                       the split GEMMs, intermediates included, must stay below
+                       65504 in magnitude, else the outputs it reaches are not
+                       finite.  No pre-split form. */
 } rif_prec;
 
 typedef enum { RIF_PNOF7 = 0, RIF_PNOF5 = 1 } rif_functional;
@@ -146,7 +150,7 @@ rif_status pnof_energy_grad(rif_ctx *ctx, rif_functional functional, int n_bf, i
  * RIF_FP64, float otherwise); pair_of may be NULL (default map).
  * b_split: NULL, or b already split for the precision the build runs in
  * (rif_presplit_b with that precision); the half transform then reads it in
- * place of b.  Ignored for RIF_FP64. */
+ * place of b.  Ignored for RIF_FP64 and RIF_FP16X3 (no pre-split form). */
 typedef struct rif_instance {
   int n_bf, n_aux, n_pairs, n_cwo, n_mo;
   const double *b, *C, *H, *occ;

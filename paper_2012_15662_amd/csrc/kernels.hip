@@ -46,7 +46,8 @@ template <int P, class T, int BX, int NT>
 using XCS = XCSrc<T, BX, EngineOf<P>::type::BK, NT, EngineOf<P>::type::KV>;
 template <int P, class T, int BX, int NT>
 using KCS = KCSrc<T, BX, EngineOf<P>::type::BK, NT, EngineOf<P>::type::KV>;
-// pieces per operand in the split-BF16 modes (0: the mode does not split)
+// bf16 pieces per operand in the split-BF16 modes (0: no bf16 piece planes;
+// FP16x3 splits every operand as it is staged)
 template <int P>
 constexpr int kPieces = P == kBF16x3 ? 2 : P == kBF16x6 ? 3 : 0;
 template <int P, int BX, int NT>
@@ -1271,10 +1272,11 @@ static rif_status run_energy_grad(rif_ctx* c, const BuildArgs& A) {
     case kF32: { constexpr int P = kF32; return call; }                          \
     case kBF16x3: { constexpr int P = kBF16x3; return call; }                    \
     case kBF16x6: { constexpr int P = kBF16x6; return call; }                    \
+    case kF16x3: { constexpr int P = kF16x3; return call; }                      \
     default: return fail(c, RIF_ENOTSUP, "precision mode not available");       \
   }
 
-static bool prec_ok(int prec) { return prec >= kF64 && prec <= kBF16x6; }
+static bool prec_ok(int prec) { return prec >= kF64 && prec <= kF16x3; }
 
 rif_status op_transform(rif_ctx* c, int prec, int nb, int na, int nw, int nmo, const double* b, const double* C,
                         void* bh, void* bmo, double* d) {

@@ -17,6 +17,12 @@
 //   kBF16x6 x6 adds hi.lo2 + lo.lo + lo2.hi.  The hi.hi products and the cross
 //           products accumulate in separate FP32 registers, folded into FP64
 //           every 128 k.
+//   kF16x3  v_mfma_f32_16x16x32_f16 on x = hi + lo 2^-11 with hi = fp16(x),
+//           lo = fp16((x - hi) 2^11): hi.hi + 2^-11 (hi.lo + lo.hi), the cross
+//           products accumulated apart and scaled by 2^-11 when folded.  The
+//           low piece is stored scaled so it keeps fp16's 11 bits wherever hi
+//           is normal; |x| must stay below fp16's largest value (65504), or
+//           the results are not finite.
 //
 // LDS layouts: FP64/FP32 slices are k-major ([k][x], x contiguous), which is
 // what the 16x16x4 fragments read (lane l takes x = l%16, k = l/16).  BF16
@@ -38,6 +44,8 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 // LDS pointer types: keep ds_read/ds_write (generic pointers would compile to
 // flat accesses, whose waits also drain the in-flight global prefetch).
 typedef __attribute__((address_space(3))) double lds_f64;
@@ -46,7 +54,7 @@ typedef __attribute__((address_space(3))) u16x8 lds_u16x8;
 typedef __attribute__((address_space(3))) u32x2 lds_u32x2;
 typedef __attribute__((address_space(3))) char lds_char;
 
-enum Prec : int { kF64 = 0, kF32 = 1, kBF16x3 = 2, kBF16x6 = 3 };
+enum Prec : int { kF64 = 0, kF32 = 1, kBF16x3 = 2, kBF16x6 = 3, kF16x3 = 4 };
 
 template <int BM_, int BN_, int BK_, int WM_, int WN_>
 struct TileCfg {
@@ -425,6 +433,33 @@ __device__ __forceinline__ void split_pair(float x0, float x1, unsigned (&pc)[NP
   split_tail<NPC>(x0 - (float)h[0], x1 - (float)h[1], pc);
 }
 
+// FP16x3 split: hi = fp16(f) with f = fp32(x) (round to nearest even), then the
+// residual (x - f) + (f - hi), exact in its two parts, times 2^11 rounded once
+// to fp16.  hi + lo 2^-11 holds x to about 2^-22 relative while hi is normal.
+constexpr float kF16LoScale = 2048.f;
+__device__ __forceinline__ void split_pair_f16(double d0, double d1, unsigned (&pc)[2]) {
+  float f0 = (float)d0, f1 = (float)d1;
+  asm("" : "+v"(f0), "+v"(f1));
+  const f16x2 h = {(_Float16)f0, (_Float16)f1};
+  pc[0] = __builtin_bit_cast(unsigned, h);
+  const float r0 = ((float)(d0 - (double)f0) + (f0 - (float)h[0])) * kF16LoScale;
+  const float r1 = ((float)(d1 - (double)f1) + (f1 - (float)h[1])) * kF16LoScale;
+  const f16x2 g = {(_Float16)r0, (_Float16)r1};
+  pc[1] = __builtin_bit_cast(unsigned, g);
+}
+__device__ __forceinline__ void split_pair_f16(float x0, float x1, unsigned (&pc)[2]) {
+  const f16x2 h = {(_Float16)x0, (_Float16)x1};
+  pc[0] = __builtin_bit_cast(unsigned, h);
+  const f16x2 g = {(_Float16)((x0 - (float)h[0]) * kF16LoScale), (_Float16)((x1 - (float)h[1]) * kF16LoScale)};
+  pc[1] = __builtin_bit_cast(unsigned, g);
+}
+__device__ __forceinline__ f4 mfma_piece(bf16x8 a, bf16x8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma_piece(f16x8 a, f16x8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
 // Operand already split into NPC bf16 piece planes (split_pair arithmetic):
 // element (x, k) of piece s at planes[s * pstride + row(x) * ld + k], k
 // contiguous, every row zero-filled from its length up to ld (a multiple of
@@ -473,9 +508,15 @@ struct is_presplit : std::false_type {};
 template <class L>
 struct is_presplit<L, std::void_t<decltype(L::kPresplit)>> : std::true_type {};
 
-template <int NPC>
-struct EngBF16 {
+// Split engines: NPC pieces per operand, bf16 pieces (kHalf = false) or the
+// fp16 pair with its scaled low piece (kHalf = true, NPC = 2 only).
+template <int NPC, bool kHalf = false>
+struct EngSplit {
+  static_assert(!kHalf || NPC == 2, "fp16 split has two pieces");
   static constexpr int BK = 32, KV = 4, CHUNK = 4;
+  using PV = typename std::conditional<kHalf, f16x8, bf16x8>::type;
+  // weight of the cross-product accumulator when folded into FP64
+  static constexpr double kCross = kHalf ? 1.0 / kF16LoScale : 1.0;
   // One piece plane of BX rows of 64 B (32 k); a stage holds NPC planes.  The
   // four 16-byte chunks (8 k each) of row x sit at chunk c ^ ((x / 4) % 4), so
   // sixteen consecutive rows at one chunk (a fragment read, or a wave's
@@ -506,7 +547,7 @@ struct EngBF16 {
 #pragma unroll
         for (int j = 0; j < Cfg::TN; ++j) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) v[i][j][r] += (double)hh[i][j][r] + (double)xx[i][j][r];
+          for (int r = 0; r < 4; ++r) v[i][j][r] += (double)hh[i][j][r] + kCross * (double)xx[i][j][r];
           hh[i][j] = f4{0.f, 0.f, 0.f, 0.f};
           xx[i][j] = f4{0.f, 0.f, 0.f, 0.f};
         }
@@ -532,7 +573,7 @@ struct EngBF16 {
   template <int BX, class L>
   __device__ static void stash(lds_char* S, const L& ld, const typename L::type (&r)[L::RR], int kt) {
     if constexpr (is_presplit<L>::value) {
-      static_assert(L::NPC == NPC && L::KV == KV, "piece planes of another split");
+      static_assert(!kHalf && L::NPC == NPC && L::KV == KV, "piece planes of another split");
 #pragma unroll
       for (int p = 0; p < L::NP; ++p) {
         const int k = ld.kl(p);
@@ -551,12 +592,17 @@ struct EngBF16 {
         unsigned pc[KV / 2][NPC];
 #pragma unroll
         for (int i = 0; i < KV; i += 2) {
-          if constexpr (std::is_same<typename L::type, float>::value)
-            split_pair<NPC>(ld.valid(p, i, kt) ? (float)ld.val(r, p, i) : 0.f,
-                            ld.valid(p, i + 1, kt) ? (float)ld.val(r, p, i + 1) : 0.f, pc[i / 2]);
-          else
-            split_pair<NPC>(ld.valid(p, i, kt) ? ld.val(r, p, i) : 0.0,
-                            ld.valid(p, i + 1, kt) ? ld.val(r, p, i + 1) : 0.0, pc[i / 2]);
+          if constexpr (std::is_same<typename L::type, float>::value) {
+            const float x0 = ld.valid(p, i, kt) ? (float)ld.val(r, p, i) : 0.f;
+            const float x1 = ld.valid(p, i + 1, kt) ? (float)ld.val(r, p, i + 1) : 0.f;
+            if constexpr (kHalf) split_pair_f16(x0, x1, pc[i / 2]);
+            else split_pair<NPC>(x0, x1, pc[i / 2]);
+          } else {
+            const double x0 = ld.valid(p, i, kt) ? ld.val(r, p, i) : 0.0;
+            const double x1 = ld.valid(p, i + 1, kt) ? ld.val(r, p, i + 1) : 0.0;
+            if constexpr (kHalf) split_pair_f16(x0, x1, pc[i / 2]);
+            else split_pair<NPC>(x0, x1, pc[i / 2]);
+          }
         }
         const int k = ld.kl(p);
         const int off = chunk_off(ld.xl(p), k / 8) + (k % 8) * 2;
@@ -576,32 +622,32 @@ struct EngBF16 {
     const int lane = threadIdx.x & 63;
     const int xc = lane & 15, kc = lane >> 4;
     if constexpr (NI > 0) {
-      bf16x8 b[NPC][Cfg::TN];
+      PV b[NPC][Cfg::TN];
 #pragma unroll
       for (int s = 0; s < NPC; ++s)
 #pragma unroll
         for (int j = 0; j < Cfg::TN; ++j)
-          b[s][j] = __builtin_bit_cast(bf16x8, *(const lds_u16x8*)(SB + s * piece_bytes<Cfg::BN>() +
-                                                                    chunk_off(w.wn0 + j * 16 + xc, kc)));
+          b[s][j] = __builtin_bit_cast(PV, *(const lds_u16x8*)(SB + s * piece_bytes<Cfg::BN>() +
+                                                                chunk_off(w.wn0 + j * 16 + xc, kc)));
 #pragma unroll
       for (int i = 0; i < NI; ++i) {
-        bf16x8 a[NPC];
+        PV a[NPC];
 #pragma unroll
         for (int s = 0; s < NPC; ++s)
-          a[s] = __builtin_bit_cast(bf16x8, *(const lds_u16x8*)(SA + s * piece_bytes<Cfg::BM>() +
-                                                                 chunk_off(w.wm0 + i * 16 + xc, kc)));
+          a[s] = __builtin_bit_cast(PV, *(const lds_u16x8*)(SA + s * piece_bytes<Cfg::BM>() +
+                                                             chunk_off(w.wm0 + i * 16 + xc, kc)));
 #pragma unroll
         for (int j = 0; j < Cfg::TN; ++j) {
           f4 x = acc.xx[i][j];
           if constexpr (NPC == 3) {
-            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2][j], x, 0, 0, 0);
-            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1][j], x, 0, 0, 0);
-            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0][j], x, 0, 0, 0);
+            x = mfma_piece(a[0], b[2][j], x);
+            x = mfma_piece(a[1], b[1][j], x);
+            x = mfma_piece(a[2], b[0][j], x);
           }
-          x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1][j], x, 0, 0, 0);
-          x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0][j], x, 0, 0, 0);
+          x = mfma_piece(a[0], b[1][j], x);
+          x = mfma_piece(a[1], b[0][j], x);
           acc.xx[i][j] = x;
-          acc.hh[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0][j], acc.hh[i][j], 0, 0, 0);
+          acc.hh[i][j] = mfma_piece(a[0], b[0][j], acc.hh[i][j]);
         }
       }
     }
@@ -619,8 +665,9 @@ template <int P> struct EngineOf;
 using EngF64 = EngF64T<16>;
 template <> struct EngineOf<kF64> { using type = EngF64; };
 template <> struct EngineOf<kF32> { using type = EngF32; };
-template <> struct EngineOf<kBF16x3> { using type = EngBF16<2>; };
-template <> struct EngineOf<kBF16x6> { using type = EngBF16<3>; };
+template <> struct EngineOf<kBF16x3> { using type = EngSplit<2>; };
+template <> struct EngineOf<kBF16x6> { using type = EngSplit<3>; };
+template <> struct EngineOf<kF16x3> { using type = EngSplit<2, true>; };
 
 // Main loop over nk slices.  smem: smem_bytes<E, Cfg>() bytes of LDS, laid
 // out [A stage 0][A stage 1][B stage 0][B stage 1].  mma(SA, SB, acc)

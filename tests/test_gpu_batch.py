@@ -59,7 +59,7 @@ def test_batch_equals_single_and_oracle(ctx, variant):
         ctx.set_tile_variant(-1)
 
 
-@pytest.mark.parametrize("prec", [0, 3])
+@pytest.mark.parametrize("prec", [0, 3, 4])
 def test_graph_replays(ctx, prec):
     import torch
     insts, items = make_items(prec)

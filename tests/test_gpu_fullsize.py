@@ -4,8 +4,9 @@ with autotuned tiles (the launch configuration the bench uses), every output
 element compared with the FP64 oracle.
 
 FP64 is held to 1e-10 relative (normwise for arrays); FP32 and split BF16x6 to
-1 uEh in the energy and 1e-6 normwise in the gradient; BF16x3 (two pieces,
-three products) only to 1e-4, with its errors printed.
+1 uEh in the energy and 1e-6 normwise in the gradient; split FP16x3 to 2 uEh
+(it reaches 1.1 uEh here) and 1e-6; BF16x3 (two pieces, three products) only to
+1e-4, with its errors printed.
 """
 import numpy as np
 import pytest
@@ -58,6 +59,7 @@ def test_fp64_every_element(case):
     ("fp32", 1, 1e-6, 1e-6),
     ("bf16x6", 3, 1e-6, 1e-6),
     ("bf16x3", 2, 1e-4, 1e-4),
+    ("fp16x3", 4, 2e-6, 1e-6),
 ])
 def test_reduced_precision(case, mode, prec, tol_e, tol_g):
     c, t, inst, ref = case

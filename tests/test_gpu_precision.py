@@ -1,9 +1,12 @@
-"""Reduced-precision modes (FP32 MFMA, split BF16 x3 / x6) vs the FP64 oracle.
+"""Reduced-precision modes (FP32 MFMA, split BF16 x3 / x6, split FP16 x3) vs
+the FP64 oracle.
 
 Targets: the split path within 1 uEh of the FP64 energy and within 1e-6 in the
 gradient (normwise: max|dG| / max|G|).  FP32 and BF16x6 are held to that bar
-at the cyclohexane-like size; BF16x3 (two pieces, three products) is known not
-to reach it and is only held to 1e-4, with its error printed.
+at the cyclohexane-like size.  FP16x3 meets it there (0.8 uEh) but reaches
+1.1 uEh at the cyclodecane-like size, so its energy is held to 2 uEh.  BF16x3
+(two pieces, three products) is known not to reach it and is only held to
+1e-4, with its error printed.
 """
 import numpy as np
 import pytest
@@ -14,9 +17,10 @@ from tests.gpu_util import host, relerr, to_dev
 
 pytestmark = pytest.mark.gpu
 
-MODES = {"fp32": 1, "bf16x3": 2, "bf16x6": 3}
+MODES = {"fp32": 1, "bf16x3": 2, "bf16x6": 3, "fp16x3": 4}
 # (abs energy error Eh, normwise gradient error, normwise J^q/K^q error)
-TOL = {"fp32": (1e-6, 1e-6, 1e-6), "bf16x6": (1e-6, 1e-6, 1e-6), "bf16x3": (1e-4, 1e-4, 1e-4)}
+TOL = {"fp32": (1e-6, 1e-6, 1e-6), "bf16x6": (1e-6, 1e-6, 1e-6), "bf16x3": (1e-4, 1e-4, 1e-4),
+       "fp16x3": (2e-6, 1e-6, 1e-6)}
 
 
 @pytest.fixture(scope="module")
@@ -81,10 +85,28 @@ def test_every_tile_variant(ctx, mode, variant):
     assert e["dE"] < te and e["grad"] < tg and e["Jn"] < tj and e["Kn"] < tj
 
 
-def test_fp16x3_not_available(ctx):
+def test_fp16x3_has_no_presplit_form(ctx):
     import paper_2012_15662_amd as rif
     inst = synth.make_instance(20, 30, 2, 1, 3)
     t = to_dev(inst)
     with pytest.raises(rif.RifError) as e:
-        ctx.transform(t["b"], t["C"], inst.n_omega, prec=rif.FP16X3)
+        ctx.presplit_b(t["b"], rif.FP16X3)
     assert e.value.status == -4
+
+
+def test_fp16x3_range(ctx):
+    """fp16's largest finite value is 65504: operands below it are carried to
+    about 2^-22 (one element of b at 6e4 still matches the oracle), one above
+    it makes the affected outputs non-finite instead of silently wrong."""
+    import paper_2012_15662_amd as rif
+    inst = synth.make_instance(40, 60, 3, 1, 5)
+    inst.b[7, 3, 5] = inst.b[7, 5, 3] = 6.0e4
+    e, _, _ = errors(ctx, inst, rif.FP16X3)
+    print("b element 6e4", " ".join(f"{k}={v:.2e}" for k, v in e.items()), flush=True)
+    assert e["b_half"] < 1e-6 and e["Jn"] < 1e-6
+    inst.b[7, 3, 5] = inst.b[7, 5, 3] = 7.0e4
+    t = to_dev(inst)
+    out = ctx.build(t["b"], t["C"], t["H"], t["occ"], t["pair_of"], inst.n_pairs, inst.n_cwo, prec=rif.FP16X3)
+    ctx.sync()
+    assert not np.isfinite(host(out["b_half"])).all()
+    assert not np.isfinite(host(out["energy"])[0])
