@@ -37,7 +37,7 @@ HBM_GBS = 8000.0
 # were taken on: a figure is reported only while those sources are unchanged.
 # The runs and their command lines are in profiles/.
 TRAFFIC = {
-    ("half_transform", "c6h12", "fp64"): {"src": "f134890d431a402b", "fetch": 1174038750, "write": 348779520,
+    ("half_transform", "c6h12", "fp64"): {"src": "59d4457903d1e6cf", "fetch": 1174029874, "write": 348779520,
                                          "profile": "profiles/fp64_c6h12_counters.md"},
 }
 
@@ -184,7 +184,7 @@ def bench_batch(args):
     ctx.sync()
     per = el / args.steps
     presplit = None
-    if prec not in (MODES["fp64"], MODES["fp16x3"]):
+    if prec != MODES["fp64"]:
         # the same batch with every b stored once in this mode's pieces
         # (rif_presplit_b; bitwise the same results)
         items2 = []
@@ -586,7 +586,7 @@ def main():
             modes[name] = {"builds_s": round(n2 / el2, 2), "speedup": round((n2 / el2) / builds_s, 3),
                            "tflops": round(flops * n2 / el2 / 1e12, 2),
                            "dE_vs_" + args.prec: float(o2["energy"].cpu()[0]) - e_main}
-            if name not in ("fp64", "fp16x3") and MODES[args.prec] == MODES["fp64"]:
+            if name != "fp64" and MODES[args.prec] == MODES["fp64"]:
                 # b stored once in this mode's pieces (rif_presplit_b); same results
                 bs = ctx.presplit_b(b, pv)
                 el4, _, _ = time_builds(ctx, b, Cd, H, occ, pm, inst, pv, n2, 2, b_split=bs)

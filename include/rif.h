@@ -57,7 +57,7 @@ typedef enum {
                        products (hi.hi + 2^-11 (hi.lo + lo.hi)); every operand of
                        the split GEMMs, intermediates included, must stay below
                        65504 in magnitude, else the outputs it reaches are not
-                       finite.  No pre-split form. */
+                       finite. */
 } rif_prec;
 
 typedef enum { RIF_PNOF7 = 0, RIF_PNOF5 = 1 } rif_functional;
@@ -150,7 +150,7 @@ rif_status pnof_energy_grad(rif_ctx *ctx, rif_functional functional, int n_bf, i
  * RIF_FP64, float otherwise); pair_of may be NULL (default map).
  * b_split: NULL, or b already split for the precision the build runs in
  * (rif_presplit_b with that precision); the half transform then reads it in
- * place of b.  Ignored for RIF_FP64 and RIF_FP16X3 (no pre-split form). */
+ * place of b.  Ignored for RIF_FP64. */
 typedef struct rif_instance {
   int n_bf, n_aux, n_pairs, n_cwo, n_mo;
   const double *b, *C, *H, *occ;
@@ -164,13 +164,13 @@ typedef struct rif_instance {
 
 /* b stored once for a reduced-precision mode (Sec. III: b is computed once
  * and kept in memory).  RIF_FP32: a float copy in b's layout.  RIF_BF16X3 /
- * RIF_BF16X6: 2 / 3 bf16 piece planes (the same split arithmetic as the
- * kernels' staging), plane s at out + s * n_aux * n_bf * ld with
+ * RIF_BF16X6: 2 / 3 bf16 piece planes; RIF_FP16X3: 2 fp16 planes, hi and
+ * lo * 2^11 (each the same split arithmetic as the kernels' staging), plane s at out + s * n_aux * n_bf * ld with
  * ld = n_bf rounded up to a multiple of 32; element (l*n_bf + nu, mu) of a
  * plane holds piece s of b[l][nu][mu] (b symmetric in mu, nu), zero from mu =
  * n_bf up to ld.  rif_presplit_b_bytes gives the size of out (host function,
  * no GPU call; 0 for RIF_FP64 or bad sizes).  Asynchronous.  RIF_EINVAL for
- * sizes or NULL pointers, RIF_ENOTSUP for RIF_FP64 and RIF_FP16X3. */
+ * sizes or NULL pointers, RIF_ENOTSUP for RIF_FP64. */
 unsigned long long rif_presplit_b_bytes(int n_bf, int n_aux, rif_prec prec);
 rif_status rif_presplit_b(rif_ctx *ctx, int n_bf, int n_aux, const double *b, rif_prec prec, void *out);
 

@@ -272,7 +272,7 @@ class Context:
         n_aux, n_bf, _ = b.shape
         nbytes = int(self.lib.rif_presplit_b_bytes(n_bf, n_aux, prec))
         if nbytes == 0:
-            raise RifError(-4, "rif_presplit_b: FP32, BF16x3 or BF16x6 only")
+            raise RifError(-4, "rif_presplit_b: FP32, BF16x3, BF16x6 or FP16x3 only")
         if out is None:
             out = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
         self._chk(self.lib.rif_presplit_b(self.h, n_bf, n_aux, _ptr(b, "b", torch.float64, n_aux * n_bf * n_bf),

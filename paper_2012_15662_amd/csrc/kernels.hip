@@ -46,10 +46,15 @@ template <int P, class T, int BX, int NT>
 using XCS = XCSrc<T, BX, EngineOf<P>::type::BK, NT, EngineOf<P>::type::KV>;
 template <int P, class T, int BX, int NT>
 using KCS = KCSrc<T, BX, EngineOf<P>::type::BK, NT, EngineOf<P>::type::KV>;
-// bf16 pieces per operand in the split-BF16 modes (0: no bf16 piece planes;
-// FP16x3 splits every operand as it is staged)
+// pieces per operand in the split modes (0: the mode does not split)
 template <int P>
-constexpr int kPieces = P == kBF16x3 ? 2 : P == kBF16x6 ? 3 : 0;
+constexpr int kPieces = P == kBF16x3 ? 2 : P == kBF16x6 ? 3 : P == kF16x3 ? 2 : 0;
+// The mode's split of two values into its pieces (the staging path's arithmetic).
+template <int P, int NPC>
+__device__ __forceinline__ void split_mode(double d0, double d1, unsigned (&pc)[NPC]) {
+  if constexpr (P == kF16x3) split_pair_f16(d0, d1, pc);
+  else split_pair<NPC>(d0, d1, pc);
+}
 template <int P, int BX, int NT>
 using PCS = PieceSrc<kPieces<P> ? kPieces<P> : 1, BX, 32, NT>;
 // Which split-mode operands come from piece planes (measured): C_Omega in the
@@ -601,9 +606,9 @@ __device__ void yd_tile(const YdArgs& a, long t, char* smem) {
   });
 }
 
-// ---- pre-split of the small reused operands (split-BF16 modes) --------------
+// ---- pre-split of the small reused operands (split modes) -------------------
 // One thread per pair of k of one row; same split arithmetic as the staging
-// path (split_pair), so a pre-split operand gives the same pieces.
+// path (split_mode), so a pre-split operand gives the same pieces.
 template <int P, class Cfg>
 __host__ __device__ inline long psplit_tiles(const PSplitArgs& a) { return cdiv((long)a.nx * (a.ld / 2), 256); }
 template <int P, class Cfg>
@@ -616,7 +621,7 @@ __device__ void psplit_tile(const PSplitArgs& a, long t, char*) {
   const double d0 = k < a.K ? a.X[(long)k * a.sk + x] : 0.0;
   const double d1 = k + 1 < a.K ? a.X[(long)(k + 1) * a.sk + x] : 0.0;
   unsigned pc[NPC];
-  split_pair<NPC>(d0, d1, pc);
+  split_mode<P>(d0, d1, pc);
 #pragma unroll
   for (int s = 0; s < NPC; ++s) *(unsigned*)(a.out + s * a.ps + (long)x * a.ld + k) = pc[s];
 }
@@ -638,7 +643,7 @@ __device__ void bsplit_tile(const BSplitArgs& a, long t, char*) {
     const double d0 = k < a.nb ? row[k] : 0.0;
     const double d1 = k + 1 < a.nb ? row[k + 1] : 0.0;
     unsigned pc[NPC];
-    split_pair<NPC>(d0, d1, pc);
+    split_mode<P>(d0, d1, pc);
     unsigned short* out = (unsigned short*)a.out;
 #pragma unroll
     for (int s = 0; s < NPC; ++s) *(unsigned*)(out + s * a.ps + x * a.ld + k) = pc[s];
@@ -1211,7 +1216,7 @@ static BuildArgs make_build_args(const Plan& pl, const rif_instance& in, int pre
   A.psd = PSplitArgs{in.d, (long)nw, nw, na, ldd, Ds, (long)nw * ldd};
   const Planes cs{Cs, (long)nw * lc, lc}, ds{Ds, (long)nw * ldd, ldd};
   A.half = HalfArgs{nb, nw, nmo, (long)na * nb, in.b, in.C, in.b_half, cs, Planes{nullptr, 0, 0}, nullptr};
-  if (in.b_split && (prec == RIF_BF16X3 || prec == RIF_BF16X6)) {
+  if (in.b_split && (prec == RIF_BF16X3 || prec == RIF_BF16X6 || prec == RIF_FP16X3)) {
     const int lb = round32(nb);
     A.half.Bs = Planes{(const unsigned short*)in.b_split, (long)na * nb * lb, lb};
   } else if (in.b_split && prec == RIF_FP32) {
@@ -1450,8 +1455,8 @@ rif_status op_build(rif_ctx* c, int prec, int functional, const rif_instance& in
 unsigned long long presplit_b_bytes(int nb, int na, int prec) {
   const unsigned long long nr = (unsigned long long)na * nb;
   if (prec == RIF_FP32) return nr * nb * 4ull;
-  if (prec == RIF_BF16X3 || prec == RIF_BF16X6)
-    return (prec == RIF_BF16X3 ? 2ull : 3ull) * nr * (unsigned long long)round32(nb) * 2ull;
+  if (prec == RIF_BF16X3 || prec == RIF_BF16X6 || prec == RIF_FP16X3)
+    return (prec == RIF_BF16X6 ? 3ull : 2ull) * nr * (unsigned long long)round32(nb) * 2ull;
   return 0;
 }
 
@@ -1472,8 +1477,12 @@ rif_status op_presplit_b(rif_ctx* c, int prec, int nb, int na, const double* b, 
       hipLaunchKernelGGL((k_bsplit<kBF16x6, Cfg256>), dim3((unsigned)bsplit_tiles<kBF16x6, Cfg256>(a)), dim3(256),
                          0, c->stream, a);
       break;
+    case RIF_FP16X3:
+      hipLaunchKernelGGL((k_bsplit<kF16x3, Cfg256>), dim3((unsigned)bsplit_tiles<kF16x3, Cfg256>(a)), dim3(256),
+                         0, c->stream, a);
+      break;
     default:
-      return fail(c, RIF_ENOTSUP, "rif_presplit_b: FP32, BF16x3 or BF16x6 only");
+      return fail(c, RIF_ENOTSUP, "rif_presplit_b: FP32, BF16x3, BF16x6 or FP16x3 only");
   }
   return check_launch(c, "presplit_b");
 }

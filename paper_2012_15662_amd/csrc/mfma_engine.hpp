@@ -573,7 +573,8 @@ struct EngSplit {
   template <int BX, class L>
   __device__ static void stash(lds_char* S, const L& ld, const typename L::type (&r)[L::RR], int kt) {
     if constexpr (is_presplit<L>::value) {
-      static_assert(!kHalf && L::NPC == NPC && L::KV == KV, "piece planes of another split");
+      // planes made by the same mode's split (the kernels pair them by mode)
+      static_assert(L::NPC == NPC && L::KV == KV, "piece planes of another split");
 #pragma unroll
       for (int p = 0; p < L::NP; ++p) {
         const int k = ld.kl(p);

@@ -336,8 +336,8 @@ rif_status rif_presplit_b(rif_ctx* c, int nb, int na, const double* b, rif_prec 
   if (!c) return RIF_EINVAL;
   if (!dims_ok(nb) || !dims_ok(na)) return fail(c, RIF_EINVAL, "rif_presplit_b: need n_bf > 0 and n_aux > 0");
   if (!b || !out) return fail(c, RIF_EINVAL, "rif_presplit_b: NULL pointer");
-  if (prec != RIF_FP32 && prec != RIF_BF16X3 && prec != RIF_BF16X6)
-    return fail(c, RIF_ENOTSUP, "rif_presplit_b: FP32, BF16x3 or BF16x6 only");
+  if (prec != RIF_FP32 && prec != RIF_BF16X3 && prec != RIF_BF16X6 && prec != RIF_FP16X3)
+    return fail(c, RIF_ENOTSUP, "rif_presplit_b: FP32, BF16x3, BF16x6 or FP16x3 only");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
   return op_presplit_b(c, (int)prec, nb, na, b, out);
 }

@@ -85,15 +85,6 @@ def test_every_tile_variant(ctx, mode, variant):
     assert e["dE"] < te and e["grad"] < tg and e["Jn"] < tj and e["Kn"] < tj
 
 
-def test_fp16x3_has_no_presplit_form(ctx):
-    import paper_2012_15662_amd as rif
-    inst = synth.make_instance(20, 30, 2, 1, 3)
-    t = to_dev(inst)
-    with pytest.raises(rif.RifError) as e:
-        ctx.presplit_b(t["b"], rif.FP16X3)
-    assert e.value.status == -4
-
-
 def test_fp16x3_range(ctx):
     """fp16's largest finite value is 65504: operands below it are carried to
     about 2^-22 (one element of b at 6e4 still matches the oracle), one above

@@ -3,10 +3,11 @@
 The half transform splits b on load with the same arithmetic and the same
 pairing of consecutive mu as the pre-split kernel, and b is exactly symmetric,
 so a build that reads the pre-split b must equal the one that does not,
-bitwise, in every output (FP32, split BF16x3 and x6; rif_build,
+bitwise, in every output (FP32, split BF16x3 and x6, split FP16x3; rif_build,
 rif_build_direct and a batch).  The piece planes themselves are checked
 against their definition: the pieces sum to b within the precision of three
-(or two) bf16 pieces, and the padding is zero.
+(or two) bf16 pieces, or of the fp16 pair hi + lo 2^-11, and the padding is
+zero.
 """
 import numpy as np
 import pytest
@@ -15,7 +16,7 @@ import synth
 from tests.gpu_util import host, to_dev
 
 pytestmark = pytest.mark.gpu
-MODES = [("fp32", 1), ("bf16x3", 2), ("bf16x6", 3)]
+MODES = [("fp32", 1), ("bf16x3", 2), ("bf16x6", 3), ("fp16x3", 4)]
 
 
 @pytest.fixture(scope="module")
@@ -71,6 +72,25 @@ def test_piece_planes_sum_to_b(ctx, mode, prec, npc):
     assert np.max(np.abs(hi - ref) / np.maximum(np.abs(ref), 1e-300)) <= 2.0 ** -8 * 1.0001
 
 
+def test_fp16_planes_sum_to_b(ctx):
+    """FP16x3 planes: hi = fp16(b) (round to nearest even, numpy's float16
+    conversion of the FP32 value) and lo with hi + lo 2^-11 = b to about 2^-22."""
+    import paper_2012_15662_amd as rif
+    inst = synth.make_instance(37, 20, 2, 1, 5)
+    t = to_dev(inst)
+    raw = host(ctx.presplit_b(t["b"], rif.FP16X3)).view(np.uint16)
+    nb, na, ld = inst.n_bf, inst.n_aux, 64
+    planes = raw.reshape(2, na * nb, ld)
+    assert np.all(planes[:, :, nb:] == 0)
+    hi = planes[0, :, :nb].view(np.float16).astype(np.float64)
+    lo = planes[1, :, :nb].view(np.float16).astype(np.float64)
+    ref = inst.b.reshape(na * nb, nb)
+    assert np.array_equal(hi, ref.astype(np.float32).astype(np.float16).astype(np.float64))
+    err = np.max(np.abs(hi + lo / 2048.0 - ref)) / np.max(np.abs(ref))
+    print("fp16x3 piece-sum error", err, flush=True)
+    assert err < 2.0 ** -21
+
+
 def test_fp32_copy_and_errors(ctx):
     import torch
     import paper_2012_15662_amd as rif
@@ -82,9 +102,10 @@ def test_fp32_copy_and_errors(ctx):
         ctx.presplit_b(t["b"], rif.FP64)
     assert ctx.lib.rif_presplit_b_bytes(20, 30, rif.FP64) == 0
     assert ctx.lib.rif_presplit_b_bytes(20, 30, rif.BF16X6) == 3 * 30 * 20 * 32 * 2
+    assert ctx.lib.rif_presplit_b_bytes(20, 30, rif.FP16X3) == 2 * 30 * 20 * 32 * 2
 
 
-@pytest.mark.parametrize("prec", [1, 3])
+@pytest.mark.parametrize("prec", [1, 3, 4])
 def test_batch_with_presplit_b(ctx, prec):
     insts = [synth.make_instance(60 + 17 * i, 2 * (60 + 17 * i), 3 + i, 2, 70 + i) for i in range(3)]
     items_a, items_b, outs = [], [], []
