@@ -595,6 +595,17 @@ def main():
                                              "bytes": int(bs.numel())}
                 del bs
         line["modes"] = modes
+        # the fastest mode whose energy stays within 1 uEh of this run's
+        # (with b pre-split where that is faster)
+        best = None
+        for name, m in modes.items():
+            if abs(m["dE_vs_" + args.prec]) > 1e-6:
+                continue
+            for pre, rate in ((False, m["builds_s"]), (True, (m.get("presplit_b") or {}).get("builds_s"))):
+                if rate and (best is None or rate > best["builds_s"]):
+                    best = {"mode": name, "b_presplit": pre, "builds_s": rate,
+                            "speedup": round(rate / builds_s, 3), "dE": m["dE_vs_" + args.prec]}
+        line["fastest_within_1uEh"] = best
     if not args.no_direct:
         # the same energy, lambda and G without the per-MO AO matrices
         el3, o3, prof3 = time_builds(ctx, b, Cd, H, occ, pm, inst, MODES[args.prec], args.steps, args.warmup,
