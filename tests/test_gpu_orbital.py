@@ -190,14 +190,16 @@ def test_full_loop_holds_two_electron_full_ci(ctx, seed, direct):
     assert min(he) >= e_fci - 1e-11 * abs(e_fci)
 
 
-def test_loop_in_split_bf16x6(ctx):
-    """The Fig. 1 loop with split-BF16x6 builds (n_bf=20, n_aux=40) converges
-    to max|G| <= 1e-5 at an energy within 1 uEh of the FP64 loop's."""
+@pytest.mark.parametrize("mode,prec", [("bf16x6", 3), ("fp16x3", 4)])
+def test_loop_in_split_precision(ctx, mode, prec):
+    """The Fig. 1 loop with split-BF16x6 or split-FP16x3 builds (n_bf=20,
+    n_aux=40) converges to max|G| <= 1e-5 at an energy within 1 uEh of the
+    FP64 loop's."""
     inst = synth.make_instance(20, 40, 2, 1, 31)
     kw = dict(max_outer=40, max_inner=4000, tol_grad=1e-5, tol_energy=1e-9, on_tol=1e-10)
     r64, _, _, _, _ = run_loop(ctx, inst, inst.C, inst.occ, **kw)
-    r6, _, _, _, _ = run_loop(ctx, inst, inst.C, inst.occ, prec=3, **kw)
-    print("fp64", r64, "bf16x6", r6, flush=True)
+    r6, _, _, _, _ = run_loop(ctx, inst, inst.C, inst.occ, prec=prec, **kw)
+    print("fp64", r64, mode, r6, flush=True)
     assert r64["status"] == 0 and r6["status"] == 0
     assert abs(r6["energy"] - r64["energy"]) < 1e-6
 
