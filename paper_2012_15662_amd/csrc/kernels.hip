@@ -101,7 +101,7 @@ struct GemmArgs {
   int ksplit, kc; long ostride;
 };
 struct FockArgs {
-  int nb, nw, nmo, per, nsplit;
+  int nb, nw, nmo, nsplit;
   const void *Jn, *Kn;
   const double *Ac, *Bc, *C;
   double* Yp;
@@ -401,10 +401,12 @@ __device__ void gemm_tile(const GemmArgs& a, long t, char* smem) {
   });
 }
 
-// Fock-apply, split over the slabs t of the stacked operand [J^0..J^{W-1}, K^0..K^{W-1}]:
-//   Ypart[s][mu][q] = sum_{t in split s} sum_nu X_t[nu][mu] coef_t[q] C[nu][q]
+// Fock-apply over the stacked operand [J^0..J^{W-1}, K^0..K^{W-1}]:
+//   Ypart[s][mu][q] = sum_{(t, nu) in split s} X_t[nu][mu] coef_t[q] C[nu][q]
 // with X_t = J^t (coef A[q][t]) or K^{t-W} (coef B[q][t-W]).  M = mu, N = q,
-// K = (t, nu), nu padded per slab to a multiple of the slice depth.
+// K = (t, nu), nu padded per slab to a multiple of the slice depth; the K
+// slices (slab-major) are split into nsplit near-equal ranges, so a split may
+// start or end inside a slab.  The loaders start at global slice g0.
 template <int P, class Cfg>
 struct FockA {  // element (mu, nu) of slab t; X_t symmetric, so read row nu
   using E = typename EngineOf<P>::type;
@@ -414,17 +416,17 @@ struct FockA {  // element (mu, nu) of slab t; X_t symmetric, so read row nu
   using type = T;
   G g;
   const T *Jn, *Kn;
-  int nb, nw, t0, nchunk, mu;
-  __device__ void init(const T* Jn_, const T* Kn_, int nb_, int nw_, int t0_, int mu0) {
-    Jn = Jn_; Kn = Kn_; nb = nb_; nw = nw_; t0 = t0_; nchunk = (nb + BK - 1) / BK;
+  int nb, nw, g0, nchunk, mu;
+  __device__ void init(const T* Jn_, const T* Kn_, int nb_, int nw_, int g0_, int mu0) {
+    Jn = Jn_; Kn = Kn_; nb = nb_; nw = nw_; g0 = g0_; nchunk = (nb + BK - 1) / BK;
     g.x = threadIdx.x % Cfg::BM; g.kg = threadIdx.x / Cfg::BM;
     mu = mu0 + g.x; g.ok = mu < nb;
   }
   __device__ int xl(int p) const { return g.xl(p); }
   __device__ int kl(int p) const { return g.kl(p); }
-  __device__ bool valid(int p, int i, int kt) const { return g.ok && (kt % nchunk) * BK + g.kl(p) + i < nb; }
+  __device__ bool valid(int p, int i, int kt) const { return g.ok && ((g0 + kt) % nchunk) * BK + g.kl(p) + i < nb; }
   __device__ void fetch(int kt, T (&r)[RR]) const {
-    const int t = t0 + kt / nchunk, nu0 = (kt % nchunk) * BK;
+    const int t = (g0 + kt) / nchunk, nu0 = ((g0 + kt) % nchunk) * BK;
     const T* X = (t < nw ? Jn + (long)t * nb * nb : Kn + (long)(t - nw) * nb * nb);
     const int muc = g.ok ? mu : 0;
 #pragma unroll
@@ -446,19 +448,19 @@ struct FockB {  // element (q, nu) of slab t: coef_t[q] * C[nu][q]; r[R] holds c
   using type = double;
   G g;
   const double *Ac, *Bc, *C;
-  int nb, nw, nmo, t0, nchunk, q;
+  int nb, nw, nmo, g0, nchunk, q;
   __device__ void init(const double* Ac_, const double* Bc_, const double* C_, int nb_, int nw_, int nmo_,
-                       int t0_, int q0) {
-    Ac = Ac_; Bc = Bc_; C = C_; nb = nb_; nw = nw_; nmo = nmo_; t0 = t0_;
+                       int g0_, int q0) {
+    Ac = Ac_; Bc = Bc_; C = C_; nb = nb_; nw = nw_; nmo = nmo_; g0 = g0_;
     nchunk = (nb + BK - 1) / BK;
     g.x = threadIdx.x % Cfg::BN; g.kg = threadIdx.x / Cfg::BN;
     q = q0 + g.x; g.ok = q < nw;
   }
   __device__ int xl(int p) const { return g.xl(p); }
   __device__ int kl(int p) const { return g.kl(p); }
-  __device__ bool valid(int p, int i, int kt) const { return g.ok && (kt % nchunk) * BK + g.kl(p) + i < nb; }
+  __device__ bool valid(int p, int i, int kt) const { return g.ok && ((g0 + kt) % nchunk) * BK + g.kl(p) + i < nb; }
   __device__ void fetch(int kt, double (&r)[RR]) const {
-    const int t = t0 + kt / nchunk, nu0 = (kt % nchunk) * BK;
+    const int t = (g0 + kt) / nchunk, nu0 = ((g0 + kt) % nchunk) * BK;
     const int qc = g.ok ? q : 0;
     r[R] = t < nw ? Ac[(long)qc * nw + t] : Bc[(long)qc * nw + (t - nw)];
 #pragma unroll
@@ -484,13 +486,14 @@ __device__ void fock_tile(const FockArgs& a, long t, char* smem) {
   const int mu0 = (int)(t % nmt) * Cfg::BM;
   const int q0 = (int)((t / nmt) % nnt) * Cfg::BN;
   const int s = (int)(t / ((long)nmt * nnt));
-  const int t0 = s * a.per, t1 = min(2 * nw, t0 + a.per);
+  const long S = 2L * nw * cdiv(nb, E::BK);   // slices over all slabs
+  const int g0 = (int)(S * s / a.nsplit), g1 = (int)(S * (s + 1) / a.nsplit);
   FockA<P, Cfg> la;
-  la.init((const IOT<P>*)a.Jn, (const IOT<P>*)a.Kn, nb, nw, t0, mu0);
+  la.init((const IOT<P>*)a.Jn, (const IOT<P>*)a.Kn, nb, nw, g0, mu0);
   FockB<P, Cfg> lb;
-  lb.init(a.Ac, a.Bc, a.C, nb, nw, a.nmo, t0, q0);
+  lb.init(a.Ac, a.Bc, a.C, nb, nw, a.nmo, g0, q0);
   typename E::template Acc<Cfg> acc;
-  gemm_mainloop<E, Cfg>(la, lb, (t1 - t0) * la.nchunk, acc, smem);
+  gemm_mainloop<E, Cfg>(la, lb, g1 - g0, acc, smem);
   double* Y = a.Yp + (long)s * nb * nw;
   acc.for_each([&](int m, int n, double v) {
     if (mu0 + m < nb && q0 + n < nw) Y[(long)(mu0 + m) * nw + q0 + n] = v;
@@ -1133,7 +1136,7 @@ static rif_status step1_jk(rif_ctx* c, const JkArgs& a) {
 // ---- workspace plan of one molecule (shared by the single and batched paths)
 struct Plan {
   int nb, na, nw, nmo, npairs, ncwo;
-  int jk_nsplit, fock_nsplit, fock_per, nparts, hc_split, lam_split, small_kc, yd_nsplit;
+  int jk_nsplit, fock_nsplit, nparts, hc_split, lam_split, small_kc, yd_nsplit;
   long yd_kc;
   size_t o_part, o_hcp, o_hc, o_a, o_b, o_yp, o_y, o_ep, o_lp, o_cs, o_ds, bytes;
   size_t o_ydp, o_zt, o_bt, bytes_direct;   // the gradient without per-MO AO matrices
@@ -1143,13 +1146,13 @@ struct Plan {
     const long w2 = (long)nw * nw;
     const long nx = cdiv(w2, 256);
     jk_nsplit = (int)std::max(1L, std::min((long)na, (1024L + nx - 1) / nx));
-    // fock split-K over the stacked slabs, sized so a 64x64-tile launch has
-    // about 4096 tiles (a 128x128 one about 1024: several per CU)
-    const int slabs = 2 * nw;
-    const long mt = cdiv(nb, 64), nt = cdiv(nw, 64);
-    int ns = std::max(1, std::min(slabs, cdiv(4096, mt * nt)));
-    fock_per = cdiv(slabs, ns);
-    fock_nsplit = cdiv(slabs, fock_per);
+    // fock split-K over the stacked slabs' slices, sized so the 128x128-tile
+    // launch fills the 512 slots of two workgroups per CU in one round (the
+    // 64x64 one then fills four per CU in about two); at most one split per
+    // 32-deep slice
+    const long t128 = (long)cdiv(nb, 128) * cdiv(nw, 128);
+    const long smax = 2L * nw * cdiv(nb, 32);
+    fock_nsplit = (int)std::max(1L, std::min(smax, 512L / t128));
     nparts = (int)nx;
     // the two small GEMMs (n_bf x n_omega outputs, k = n_bf): k split so a
     // launch has about 256 tiles of 64x64, at least two 16-deep slices each
@@ -1232,7 +1235,7 @@ static BuildArgs make_build_args(const Plan& pl, const rif_instance& in, int pre
                     (long)nb * nw, pl.hc_split, HCp, HC};
   A.energy = EnergyArgs{nw, pl.npairs, pl.ncwo, nb, nmo, pl.nparts, in.pair_of, in.occ, in.C, HC, Ep, in.energy,
                         flag};
-  A.fock = FockArgs{nb, nw, nmo, pl.fock_per, pl.fock_nsplit, in.Jn, in.Kn, Ac, Bc, in.C, Yp};
+  A.fock = FockArgs{nb, nw, nmo, pl.fock_nsplit, in.Jn, in.Kn, Ac, Bc, in.C, Yp};
   A.fred = FockRedArgs{nb, nw, pl.fock_nsplit, Yp, in.occ, HC, Y};
   A.lam = GemmArgs{nmo, nw, nb, in.C, (long)nmo, Y, (long)nw, Lp, (long)nw, pl.lam_split, pl.small_kc,
                    (long)nmo * nw};
