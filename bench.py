@@ -37,7 +37,7 @@ HBM_GBS = 8000.0
 # were taken on: a figure is reported only while those sources are unchanged.
 # The runs and their command lines are in profiles/.
 TRAFFIC = {
-    ("half_transform", "c6h12", "fp64"): {"src": "b60c3c8c6e83da1a", "fetch": 1174049318, "write": 348779520,
+    ("half_transform", "c6h12", "fp64"): {"src": "ed77525bf763e85e", "fetch": 1174070307, "write": 348779520,
                                          "profile": "profiles/fp64_c6h12_counters.md"},
 }
 

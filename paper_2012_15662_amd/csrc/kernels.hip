@@ -1177,11 +1177,13 @@ struct Plan {
     o_ds = cv.take<unsigned short>((size_t)3 * nw * round32(na));   // d^T pieces (split modes)
     bytes = cv.off;
     // direct gradient: split-K over (r, l), sized so a 64x64-tile launch has
-    // about 2048 tiles; each split a multiple of 32 deep
+    // at most 2048 tiles (two full rounds of four per CU; rounding up instead
+    // would spill a few tiles into a third round); each split a multiple of
+    // 32 deep
     {
       const long K = (long)na * nw, t64 = cdiv(nb, 64) * cdiv(nw, 64);
       const long slices = cdiv(K, 32L);
-      const long ns = std::max(1L, std::min(slices, (long)cdiv(2048L, t64)));
+      const long ns = std::max(1L, std::min(slices, 2048L / t64));
       yd_kc = 32L * cdiv(slices, ns);
       yd_nsplit = (int)cdiv(K, yd_kc);
     }
