@@ -135,6 +135,84 @@ def time_builds(ctx, b, Cd, H, occ, pm, inst, prec, steps, warmup, profile=False
     return el, out, prof
 
 
+def oracle_errors(out, ref):
+    """Energy (absolute, Eh) and gradient (normwise max|dG| / max|G|) errors of
+    one build against the FP64 oracle's, and whether the reduced-precision
+    target (1 uEh, 1e-6) holds."""
+    e = float(out["energy"].cpu()[0])
+    g = out["grad"].cpu().numpy()
+    dE = e - ref["energy"]
+    gerr = float(abs(g - ref["grad"]).max() / abs(ref["grad"]).max())
+    return {"dE_vs_oracle": dE, "dE_rel_vs_oracle": abs(dE) / abs(ref["energy"]), "grad_err_vs_oracle": gerr,
+            "within_1uEh_1e-6": bool(abs(dE) <= 1e-6 and gerr <= 1e-6)}
+
+
+def fastest_within_target(modes, base_rate):
+    """The fastest reduced-precision mode whose energy is within 1 uEh and
+    gradient within 1e-6 (normwise) of the oracle's (b pre-split where faster)."""
+    best = None
+    for name, m in modes.items():
+        if name == "fp64" or not m["within_1uEh_1e-6"]:
+            continue
+        for pre, rate in ((False, m["builds_s"]), (True, (m.get("presplit_b") or {}).get("builds_s"))):
+            if rate and (best is None or rate > best["builds_s"]):
+                best = {"mode": name, "b_presplit": pre, "builds_s": rate,
+                        "speedup_vs_fp64": round(rate / base_rate, 3), "dE_vs_oracle": m["dE_vs_oracle"],
+                        "grad_err_vs_oracle": m["grad_err_vs_oracle"]}
+    return best
+
+
+def precision_study(ctx, workload, steps):
+    """Every mode at one more workload (the cyclodecane-like molecule): builds/s
+    (b split on load and pre-split), error against the FP64 oracle, and the
+    FP64 half transform's roofline (HIP events over its timed builds)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from oracle import pnof7_ri as ri
+
+    inst = synth.workload(workload)
+    nb, na, nw, nmo = inst.n_bf, inst.n_aux, inst.n_omega, inst.n_mo
+    t0 = time.perf_counter()
+    ref = ri.build_instance(inst)
+    t_oracle = time.perf_counter() - t0
+    dev = "cuda:0"
+    b = torch.from_numpy(inst.b).to(dev)
+    Cd = [torch.from_numpy(inst.C).to(dev)]
+    H, occ = torch.from_numpy(inst.H).to(dev), torch.from_numpy(inst.occ).to(dev)
+    pm = torch.from_numpy(inst.pair_of.astype(np.int32)).to(dev)
+    inst.b = None
+    flops = build_flops(nb, na, nw, nmo)
+    kf = kernel_flops(nb, na, nw, nmo)
+    modes, base = {}, None
+    roof = None
+    for name, pv in MODES.items():
+        prof = "half_transform" if name == "fp64" else False
+        el, out, pr = time_builds(ctx, b, Cd, H, occ, pm, inst, pv, steps, 2, profile=prof)
+        rate = steps / el
+        if name == "fp64":
+            base = rate
+            n, ms = pr["half_transform"]
+            ach = kf["half_transform"] / (ms / n * 1e-3) / 1e12
+            roof = {"kernel": "half_transform", "bound": "mfma", "achieved": round(ach, 3), "peak": PEAK["f64"],
+                    "unit": "TFLOP/s", "frac": round(ach / PEAK["f64"], 4)}
+        o = ctx.build(b, Cd[0], H, occ, pm, inst.n_pairs, inst.n_cwo, prec=pv)
+        ctx.sync()
+        modes[name] = {"builds_s": round(rate, 2), "speedup": round(rate / base, 3),
+                       "tflops": round(flops * rate / 1e12, 2), **oracle_errors(o, ref)}
+        if name != "fp64":
+            bs = ctx.presplit_b(b, pv)
+            el4, _, _ = time_builds(ctx, b, Cd, H, occ, pm, inst, pv, steps, 2, b_split=bs)
+            modes[name]["presplit_b"] = {"builds_s": round(steps / el4, 2), "speedup": round(steps / el4 / base, 3)}
+            del bs
+    del b
+    torch.cuda.empty_cache()
+    return {"config": f"{workload}: n_bf={nb} n_aux={na} pairs={inst.n_pairs} ncwo={inst.n_cwo} n_omega={nw} "
+                      f"n_mo={nmo}, unrotated C", "steps": steps, "oracle_build_s": round(t_oracle, 2),
+            "roofline_fp64": roof, "modes": modes, "fastest_within_1uEh": fastest_within_target(modes, base)}
+
+
 def bench_batch(args):
     """64 uneven molecules (n_bf ~ U{60..400}, n_aux = 3 n_bf, pairs = n_bf//12,
     Ncwo = 2): one grouped launch per step, captured in a hipGraph and replayed.
@@ -146,18 +224,14 @@ def bench_batch(args):
     import synth
 
     prec = MODES[args.prec]
-    insts = synth.make_batch(64)
-    dev = "cuda:0"
     ctx = rif.Context(0)
     ctx.autotune(not args.no_tune)
+    # the molecules tests/test_gpu_batch64.py compares with the oracle
     items, flops = [], 0.0
-    for inst in insts:
-        inp = {"b": torch.from_numpy(inst.b).to(dev), "C": torch.from_numpy(inst.C).to(dev),
-               "H": torch.from_numpy(inst.H).to(dev), "occ": torch.from_numpy(inst.occ).to(dev),
-               "pair_of": torch.from_numpy(inst.pair_of.astype(np.int32)).to(dev)}
-        inst.b = None   # release host memory as we go
-        items.append((inp, inst.n_pairs, inst.n_cwo, None))
-        flops += build_flops(inst.n_bf, inst.n_aux, inst.n_omega, inst.n_mo)
+    for inp, npair, ncwo in synth.make_batch_device(64):
+        nb = inp["b"].shape[1]
+        items.append((inp, npair, ncwo, None))
+        flops += build_flops(nb, 3 * nb, npair * (1 + ncwo), nb)
     batch = ctx.batch(items, prec=prec)
     for _ in range(max(args.warmup, 1)):
         batch.run(use_graph=True)
@@ -212,7 +286,8 @@ def bench_batch(args):
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16", "fp16x3": "f16"}[args.prec],
         "data": "synthetic",
         "config": {"workload": "batch64: 64 molecules, n_bf ~ U{60..400} (seed 3), n_aux = 3 n_bf, "
-                               "pairs = n_bf//12, Ncwo = 2; one step = all 64 builds",
+                               "pairs = n_bf//12, Ncwo = 2, b drawn on the GPU (seeds 3000+i); "
+                               "one step = all 64 builds",
                    "precision": args.prec},
         "tflops": round(flops / per / 1e12, 2), "flops_per_step": flops,
         "sequential_builds_s": round(64 / el_seq, 2), "batch_speedup": round(el_seq / per, 3),
@@ -393,6 +468,11 @@ def bench_orbopt(args):
         "small_to_convergence": small_line,
         "cpu_baseline": cpu,
     }
+    # release the context (its rocBLAS handle, streams, events and arena)
+    # while the HIP runtime is fully up, not from a finaliser at exit
+    del d
+    ctx.close()
+    torch.cuda.synchronize()
     print(json.dumps(line))
 
 
@@ -452,6 +532,8 @@ def bench_prep(args):
         "solve_gemm_tflops": round(gemm_flops / (gemm_ms * 1e-3) / 1e12, 2) if gemm_ms else None,
         "cpu_baseline": cpu,
     }
+    ctx.close()
+    torch.cuda.synchronize()
     print(json.dumps(line))
 
 
@@ -474,6 +556,8 @@ def main():
                     help="run one 1 GiB device-to-device copy first (reference for HBM counters)")
     ap.add_argument("--no-modes", action="store_true", help="skip timing the other precision modes")
     ap.add_argument("--no-direct", action="store_true", help="skip timing rif_build_direct")
+    ap.add_argument("--no-c10h20", action="store_true",
+                    help="skip the precision study at the cyclodecane-like size")
     ap.add_argument("--no-small", action="store_true",
                     help="orbopt: skip the small molecule run to convergence")
     args = ap.parse_args()
@@ -573,19 +657,23 @@ def main():
         "energy_at_C0": e_main,
     }
     if not args.no_modes:
-        # the other arithmetic modes on the same workload: speed-up over this
-        # run and energy difference to it (errors against the oracle are in the tests)
+        # every arithmetic mode on the same workload: speed-up over this run,
+        # and error against the FP64 oracle at the unrotated C (energy absolute,
+        # gradient normwise), judged against the reduced-precision target
+        from oracle import pnof7_ri as ri
+        ref = ri.build_instance(inst, C=Cs[0])
         modes = {}
         for name, pv in MODES.items():
             if name == args.prec:
-                continue
-            n2 = max(5, args.steps // 2)
-            el2, _, _ = time_builds(ctx, b, Cd, H, occ, pm, inst, pv, n2, 2)
-            o2 = ctx.build(b, Cd[0], H, occ, pm, inst.n_pairs, inst.n_cwo, prec=pv)
-            ctx.sync()
-            modes[name] = {"builds_s": round(n2 / el2, 2), "speedup": round((n2 / el2) / builds_s, 3),
-                           "tflops": round(flops * n2 / el2 / 1e12, 2),
-                           "dE_vs_" + args.prec: float(o2["energy"].cpu()[0]) - e_main}
+                rate, o2 = builds_s, ref_out
+            else:
+                n2 = max(5, args.steps // 2)
+                el2, _, _ = time_builds(ctx, b, Cd, H, occ, pm, inst, pv, n2, 2)
+                rate = n2 / el2
+                o2 = ctx.build(b, Cd[0], H, occ, pm, inst.n_pairs, inst.n_cwo, prec=pv)
+                ctx.sync()
+            modes[name] = {"builds_s": round(rate, 2), "speedup": round(rate / builds_s, 3),
+                           "tflops": round(flops * rate / 1e12, 2), **oracle_errors(o2, ref)}
             if name != "fp64" and MODES[args.prec] == MODES["fp64"]:
                 # b stored once in this mode's pieces (rif_presplit_b); same results
                 bs = ctx.presplit_b(b, pv)
@@ -595,17 +683,10 @@ def main():
                                              "bytes": int(bs.numel())}
                 del bs
         line["modes"] = modes
-        # the fastest mode whose energy stays within 1 uEh of this run's
-        # (with b pre-split where that is faster)
-        best = None
-        for name, m in modes.items():
-            if abs(m["dE_vs_" + args.prec]) > 1e-6:
-                continue
-            for pre, rate in ((False, m["builds_s"]), (True, (m.get("presplit_b") or {}).get("builds_s"))):
-                if rate and (best is None or rate > best["builds_s"]):
-                    best = {"mode": name, "b_presplit": pre, "builds_s": rate,
-                            "speedup": round(rate / builds_s, 3), "dE": m["dE_vs_" + args.prec]}
-        line["fastest_within_1uEh"] = best
+        line["fastest_within_1uEh"] = fastest_within_target(modes, builds_s)
+        if not args.no_c10h20:
+            del ref
+            line["c10h20"] = precision_study(ctx, "c10h20", max(6, args.steps // 3))
     if not args.no_direct:
         # the same energy, lambda and G without the per-MO AO matrices
         el3, o3, prof3 = time_builds(ctx, b, Cd, H, occ, pm, inst, MODES[args.prec], args.steps, args.warmup,

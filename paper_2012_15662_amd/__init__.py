@@ -11,8 +11,11 @@ the call raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 __all__ = [
     "Context", "Batch", "Instance", "OnProblem", "OnSet", "OptParams", "OptResult", "RifError", "load_library", "LIB_PATH", "FP64", "FP32", "BF16X3", "BF16X6",
@@ -106,6 +109,20 @@ EXPORTS = {
 
 _lib = None
 
+# Live contexts and batches, released by an exit hook while the HIP runtime is
+# still up: a finaliser that runs during interpreter teardown could otherwise
+# call into the runtime after its own exit handlers.
+_live_batches: "weakref.WeakSet" = weakref.WeakSet()
+_live_contexts: "weakref.WeakSet" = weakref.WeakSet()
+
+
+@atexit.register
+def _release_all():
+    for b in list(_live_batches):
+        b.close()
+    for c in list(_live_contexts):
+        c.close()
+
 
 
 
@@ -166,13 +183,19 @@ class Context:
         if st != 0:
             raise RifError(st, "rif_create failed")
         self.h = h
+        _live_contexts.add(self)
 
     def close(self):
         if getattr(self, "h", None):
+            for b in list(_live_batches):   # a batch holds this context's stream
+                if b.ctx is self:
+                    b.close()
             self.lib.rif_destroy(self.h)
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return   # the exit hook has released every context still open
         try:
             self.close()
         except Exception:
@@ -536,16 +559,20 @@ class Batch:
         h = ctypes.c_void_p()
         ctx._chk(ctx.lib.rif_batch_create(ctx.h, len(items), arr, prec, functional, ctypes.byref(h)))
         self.h = h
+        _live_batches.add(self)
 
     def run(self, use_graph: bool = True):
         self.ctx._chk(self.ctx.lib.rif_batch_run(self.h, 1 if use_graph else 0))
 
     def close(self):
         if getattr(self, "h", None):
-            self.ctx.lib.rif_batch_destroy(self.h)
+            if getattr(self.ctx, "h", None):
+                self.ctx.lib.rif_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -31,7 +31,8 @@ import numpy as np
 
 __all__ = [
     "Instance", "WORKLOADS", "default_pair_map", "make_instance", "make_b",
-    "rotation_sequence", "batch_sizes", "make_batch", "make_metric", "make_three_centre",
+    "rotation_sequence", "batch_sizes", "make_batch", "make_batch_device", "make_instance_device",
+    "make_metric", "make_three_centre",
 ]
 
 # name -> (n_bf, n_aux, n_pairs, n_cwo, seed)
@@ -186,6 +187,15 @@ def make_instance_device(n_bf: int, n_aux: int, n_pairs: int, n_cwo: int, seed: 
          "H": torch.from_numpy(np.ascontiguousarray(H)).to(device), "occ": torch.from_numpy(occ).to(device),
          "pair_of": torch.from_numpy(pair_of.astype(np.int32)).to(device)}
     return t, n_pairs, n_cwo
+
+
+def make_batch_device(n_inst: int = 64, seed: int = 3, base: int = 3000, n_cwo: int = 2,
+                      lo: int = 60, hi: int = 400, device="cuda") -> list:
+    """The uneven batch with b drawn on the GPU (make_instance_device, seed
+    base+i): n_bf ~ U{lo..hi} (batch_sizes), n_aux = 3 n_bf, pairs = n_bf // 12.
+    Returns a list of (dict of device tensors, n_pairs, n_cwo)."""
+    return [make_instance_device(int(nb), 3 * int(nb), int(nb) // 12, n_cwo, base + i, device=device)
+            for i, nb in enumerate(batch_sizes(n_inst, seed, lo, hi))]
 
 
 def make_metric(n_aux: int, seed: int, cond: float = 1e10, n_negative: int = 0) -> np.ndarray:

@@ -92,7 +92,7 @@ def test_direct_agrees_with_build(ctx):
     ("fp32", 1, 1e-6, 1e-6),
     ("bf16x6", 3, 1e-6, 1e-6),
     ("bf16x3", 2, 1e-4, 1e-4),
-    ("fp16x3", 4, 2e-6, 1e-6),
+    ("fp16x3", 4, 1e-6, 1e-6),
 ])
 def test_direct_reduced_precision_full_size(ctx, mode, prec, tol_e, tol_g):
     """Cyclohexane-like workload (n_bf=348, n_aux=1044, 24 pairs, Ncwo=4)."""
