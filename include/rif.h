@@ -100,6 +100,20 @@ rif_status rif_transform(rif_ctx *ctx, int n_bf, int n_aux, int n_omega, int n_m
 rif_status rif_jk_mo(rif_ctx *ctx, int n_aux, int n_omega, const void *b_mo, const double *d,
                      rif_prec prec, double *J, double *K);
 
+/* rif_jk_mo for callers that cannot allocate (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same arguments, kernels
+ * and results (bitwise), with the per-slice partials in a static device array
+ * of 16 MiB per GPU instead of the context's workspace, which this call never
+ * grows.  No hipMalloc, hipFree or other allocation happens in the call.  That
+ * array holds 2 * s * n_omega^2 doubles, s = the slices of l (1 for
+ * n_omega >= 64): RIF_ENOMEM beyond it (n_omega above 1024).  Every context
+ * on one GPU shares that GPU's array, so two such calls that overlap on one
+ * GPU (on different streams) race; calls on one stream are ordered.  Event
+ * profiling (rif_profile_enable) is suspended during the call.  RIF_EHIP if
+ * the array's device address could not be resolved at rif_create. */
+rif_status rif_jk_mo_noalloc(rif_ctx *ctx, int n_aux, int n_omega, const void *b_mo, const double *d,
+                             rif_prec prec, double *J, double *K);
+
 /* Per-MO AO Coulomb and exchange matrices: Table 3 steps 3-4.
  *   b      [n_aux][n_bf][n_bf] FP64          (in)
  *   b_half [n_omega][n_aux][n_bf]            (in, as produced by rif_transform)

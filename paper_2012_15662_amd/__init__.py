@@ -71,6 +71,7 @@ EXPORTS = {
     "rif_set_workspace_limit": (_i, [_vp, ctypes.c_ulonglong]),
     "rif_transform": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _i, _vp, _vp, _vp]),
     "rif_jk_mo": (_i, [_vp, _i, _i, _vp, _vp, _i, _vp, _vp]),
+    "rif_jk_mo_noalloc": (_i, [_vp, _i, _i, _vp, _vp, _i, _vp, _vp]),
     "rif_jk_ao_per_mo": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _vp]),
     "pnof7_energy_grad": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i,
                                _vp, _vp, _vp]),
@@ -241,6 +242,19 @@ class Context:
         if K is None:
             K = torch.empty((n_omega, n_omega), dtype=torch.float64, device=d.device)
         self._chk(self.lib.rif_jk_mo(
+            self.h, n_aux, n_omega, _ptr(b_mo, "b_mo", dt, n_aux * n_omega * n_omega),
+            _ptr(d, "d", torch.float64, n_aux * n_omega), prec,
+            _ptr(J, "J", torch.float64, n_omega * n_omega),
+            _ptr(K, "K", torch.float64, n_omega * n_omega)))
+        return J, K
+
+    def jk_mo_noalloc(self, b_mo, d, J, K, prec=FP64):
+        """rif_jk_mo_noalloc: J and K into the caller's buffers with the
+        library's static scratch (nothing is allocated)."""
+        import torch
+        n_aux, n_omega, _ = b_mo.shape
+        dt = torch.float64 if prec == FP64 else torch.float32
+        self._chk(self.lib.rif_jk_mo_noalloc(
             self.h, n_aux, n_omega, _ptr(b_mo, "b_mo", dt, n_aux * n_omega * n_omega),
             _ptr(d, "d", torch.float64, n_aux * n_omega), prec,
             _ptr(J, "J", torch.float64, n_omega * n_omega),

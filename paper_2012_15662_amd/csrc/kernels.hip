@@ -1317,6 +1317,57 @@ rif_status op_jk_mo(rif_ctx* c, int prec, int na, int nw, const void* bmo, const
   RIF_PREC_SWITCH(prec, step1_jk<P>(c, a))
 }
 
+// ---- MO J/K without allocation (rif_jk_mo_noalloc) --------------------------
+// The per-slice partials live in this file-scope device array instead of the
+// context's arena.  Each GPU the library runs on holds its own copy until the
+// process ends.  In host code `scratch` names a host-side stand-in, so host
+// code uses only the device address that hipGetSymbolAddress returns for it
+// (resolved once per context, at rif_create, with the context's device current).
+constexpr size_t kStaticScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+rif_status op_static_scratch_init(rif_ctx* c) {
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    c->scratch = nullptr;
+    c->scratch_bytes = 0;
+    return fail(c, RIF_EHIP, std::string("hipGetSymbolAddress of the static scratch failed: ") + hipGetErrorString(e));
+  }
+  c->scratch = p;
+  c->scratch_bytes = kStaticScratchBytes;
+  return RIF_OK;
+}
+
+rif_status op_jk_mo_noalloc(rif_ctx* c, int prec, int na, int nw, const void* bmo, const double* d, double* J,
+                            double* K) {
+  if (!prec_ok(prec)) return fail(c, RIF_ENOTSUP, "precision mode not available");
+  if (!c->scratch) return fail(c, RIF_EHIP, "rif_jk_mo_noalloc: the static scratch could not be resolved");
+  const long w2 = (long)nw * nw;
+  const long nx = cdiv(w2, 256);
+  const int nsplit = (int)std::max(1L, std::min((long)na, (1024L + nx - 1) / nx));
+  const size_t need = sizeof(double) * 2 * (size_t)nsplit * (size_t)w2;
+  if (need > c->scratch_bytes)
+    return fail(c, RIF_ENOMEM, "rif_jk_mo_noalloc: needs " + std::to_string(need) + " bytes of scratch, more than its " +
+                                   std::to_string(c->scratch_bytes) + " (n_omega above 1024)");
+  // the same kernels and split as rif_jk_mo, on the static partials; no event
+  // pairs either (profiling is suspended for the call)
+  const JkArgs a{na, nw, nsplit, bmo, d, (double*)c->scratch, J, K};
+  const bool prof = c->prof;
+  c->prof = false;
+  rif_status st;
+  switch (prec) {
+    case kF64: st = step1_jk<kF64>(c, a); break;
+    case kF32: st = step1_jk<kF32>(c, a); break;
+    case kBF16x3: st = step1_jk<kBF16x3>(c, a); break;
+    case kBF16x6: st = step1_jk<kBF16x6>(c, a); break;
+    default: st = step1_jk<kF16x3>(c, a); break;
+  }
+  c->prof = prof;
+  return st;
+}
+
 rif_status op_jk_ao(rif_ctx* c, int prec, int nb, int na, int nw, const double* b, const void* bh,
                     const double* d, void* Jn, void* Kn) {
   if (!prec_ok(prec)) return fail(c, RIF_ENOTSUP, "precision mode not available");

@@ -140,6 +140,9 @@ rif_status rif_create(rif_ctx** out, int dev, void* stream) {
     delete c;
     return RIF_EHIP;
   }
+  // the static scratch of rif_jk_mo_noalloc on this device; a failure is kept
+  // (that entry point then reports it) and leaves every other call working
+  if (op_static_scratch_init(c) == RIF_OK) c->err.clear();
   *out = c;
   return RIF_OK;
 }
@@ -220,6 +223,15 @@ rif_status rif_jk_mo(rif_ctx* c, int na, int nw, const void* bmo, const double* 
   if (!bmo || !d || !J || !K) return fail(c, RIF_EINVAL, "rif_jk_mo: NULL pointer");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
   return op_jk_mo(c, (int)prec, na, nw, bmo, d, J, K);
+}
+
+rif_status rif_jk_mo_noalloc(rif_ctx* c, int na, int nw, const void* bmo, const double* d, rif_prec prec, double* J,
+                             double* K) {
+  if (!c) return RIF_EINVAL;
+  if (!dims_ok(na) || !dims_ok(nw)) return fail(c, RIF_EINVAL, "rif_jk_mo_noalloc: need n_aux > 0 and n_omega > 0");
+  if (!bmo || !d || !J || !K) return fail(c, RIF_EINVAL, "rif_jk_mo_noalloc: NULL pointer");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  return op_jk_mo_noalloc(c, (int)prec, na, nw, bmo, d, J, K);
 }
 
 rif_status rif_jk_ao_per_mo(rif_ctx* c, int nb, int na, int nw, const double* b, const void* bh,

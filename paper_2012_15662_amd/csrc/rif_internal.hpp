@@ -44,6 +44,10 @@ struct rif_ctx {
   // polls of one exchanged value before a cooperative kernel gives up
   // (rif_set_wait_limit; negative: every wait gives up at once)
   long long wait_limit = 1LL << 22;
+  // device address of the file-scope scratch array of rif_jk_mo_noalloc on
+  // this context's device (resolved at rif_create) and its size
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
 };
 
 namespace rif {
@@ -91,6 +95,11 @@ int pick_variant(rif_ctx* c, const char* kernel, std::initializer_list<long> sha
 rif_status op_transform(rif_ctx* c, int prec, int nb, int na, int nw, int nmo, const double* b, const double* C,
                         void* bh, void* bmo, double* d);
 rif_status op_jk_mo(rif_ctx* c, int prec, int na, int nw, const void* bmo, const double* d, double* J, double* K);
+// The same on a static device array (no allocation); op_static_scratch_init
+// resolves that array's device address for the context's current device.
+rif_status op_static_scratch_init(rif_ctx* c);
+rif_status op_jk_mo_noalloc(rif_ctx* c, int prec, int na, int nw, const void* bmo, const double* d, double* J,
+                            double* K);
 rif_status op_jk_ao(rif_ctx* c, int prec, int nb, int na, int nw, const double* b, const void* bh,
                     const double* d, void* Jn, void* Kn);
 rif_status op_energy_grad(rif_ctx* c, int prec, int functional, int nb, int nmo, int npairs, int ncwo,
