@@ -213,6 +213,77 @@ def precision_study(ctx, workload, steps):
             "roofline_fp64": roof, "modes": modes, "fastest_within_1uEh": fastest_within_target(modes, base)}
 
 
+def four_centre_study(ctx, sizes=(128, 192, 232, 288, 348), reps=4):
+    """RI against the conventional four-centre path (Table 1) on the same
+    integrals, FP64, one J/K build each: J, K, J^q and K^q for one C.
+    RI = rif_transform + rif_jk_mo + rif_jk_ao_per_mo; four-centre =
+    rif_jk_4c on integrals stored once (rif_eri4_from_b, timed apart as step
+    0).  Shapes follow the cyclohexane-like molecule: n_aux = 3 n_bf, Ncwo 4,
+    pairs = round(24 n_bf / 348).  Fits t ~ n_bf^k for both paths."""
+    import numpy as np
+    import torch
+
+    import synth
+
+    rows = []
+    for nb in sizes:
+        npair = max(1, int(round(24 * nb / 348)))
+        inst = synth.make_instance(nb, 3 * nb, npair, 4, 500 + nb)
+        w = inst.n_omega
+        b = torch.from_numpy(inst.b).cuda()
+        C = torch.from_numpy(inst.C).cuda()
+        inst.b = None
+
+        def ri_once(o):
+            o["b_half"], o["b_mo"], o["d"] = ctx.transform(b, C, w, 0, o.get("b_half"), o.get("b_mo"), o.get("d"))
+            o["J"], o["K"] = ctx.jk_mo(o["b_mo"], o["d"], 0, o.get("J"), o.get("K"))
+            o["Jn"], o["Kn"] = ctx.jk_ao_per_mo(b, o["b_half"], o["d"], 0, o.get("Jn"), o.get("Kn"))
+            return o
+
+        def timed(f, n):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(n):
+                f()
+            e1.record()
+            e1.synchronize()
+            return e0.elapsed_time(e1) / n
+
+        ro = {}
+        for _ in range(2):
+            ri_once(ro)
+        t_ri = timed(lambda: ri_once(ro), 3 * reps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eri = ctx.eri4_from_b(b)
+        torch.cuda.synchronize()
+        t_eri = (time.perf_counter() - t0) * 1e3
+        fo = ctx.jk_4c(eri, C, w)
+        t_4c = timed(lambda: ctx.jk_4c(eri, C, w, out=fo), reps)
+        ctx.sync()
+        diff = max(float((fo[k] - ro[k]).abs().max() / ro[k].abs().max()) for k in ("J", "K", "Jn", "Kn"))
+        rows.append({"n_bf": nb, "n_aux": 3 * nb, "n_omega": w, "ri_ms": round(t_ri, 4), "fourc_ms": round(t_4c, 3),
+                     "speedup": round(t_4c / t_ri, 2), "eri_step0_ms": round(t_eri, 1),
+                     "eri_gb": round(eri.numel() * 8 / 1e9, 2), "max_rel_diff_ri_vs_4c": diff})
+        print(f"four-centre n_bf={nb}: RI {t_ri:.3f} ms, 4c {t_4c:.2f} ms ({t_4c / t_ri:.1f}x)", file=sys.stderr,
+              flush=True)
+        del eri, fo, ro, b, C
+        torch.cuda.empty_cache()
+    def fit(rs):
+        x = np.log([r["n_bf"] for r in rs])
+        return {k: round(float(np.polyfit(x, np.log([r[k] for r in rs]), 1)[0]), 2) for k in ("ri_ms", "fourc_ms")}
+    big = fit([r for r in rows if r["n_bf"] >= 192])
+    every = fit(rows)
+    return {"config": "J, K, J^q, K^q for one C (FP64); n_aux = 3 n_bf, Ncwo 4, pairs = round(24 n_bf/348)",
+            "sizes": rows, "exponent_ri": big["ri_ms"], "exponent_fourc": big["fourc_ms"],
+            "exponent_all_sizes": every,
+            "exponent_note": "t ~ n_bf^k by least squares over n_bf >= 192 (below that the RI build is "
+                             "launch-latency bound); formal: RI n_bf^2 n_aux n_Omega, four-centre n_bf^4 n_Omega "
+                             "(n_aux, n_Omega proportional to n_bf here: 4 and 5)",
+            "paper_context": "paper (24 Xeon threads, DoNOF): PNOF7-RI vs PNOF7 12x per outer iteration "
+                             "(cyclopropane), 83x occupancy and 37x orbital optimisation (cyclononane)"}
+
+
 def bench_batch(args):
     """64 uneven molecules (n_bf ~ U{60..400}, n_aux = 3 n_bf, pairs = n_bf//12,
     Ncwo = 2): one grouped launch per step, captured in a hipGraph and replayed.
@@ -556,6 +627,7 @@ def main():
                     help="run one 1 GiB device-to-device copy first (reference for HBM counters)")
     ap.add_argument("--no-modes", action="store_true", help="skip timing the other precision modes")
     ap.add_argument("--no-direct", action="store_true", help="skip timing rif_build_direct")
+    ap.add_argument("--no-4c", action="store_true", help="skip the RI vs four-centre comparison")
     ap.add_argument("--no-c10h20", action="store_true",
                     help="skip the precision study at the cyclodecane-like size")
     ap.add_argument("--no-small", action="store_true",
@@ -704,6 +776,8 @@ def main():
             "contraction_ms": round(yd[1] / yd[0], 5) if yd else None,
             "contraction_tflops": round(2.0 * nb * nw * na * nw / (yd[1] / yd[0] * 1e-3) / 1e12, 2) if yd else None,
         }
+    if not args.no_4c:
+        line["four_centre"] = four_centre_study(ctx)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(inst, Cs, args.cpu_budget)
     ctx.close()

@@ -176,6 +176,33 @@ typedef struct rif_instance {
   const void *b_split;
 } rif_instance;
 
+/* The conventional four-centre path that the RI path replaces (Table 1,
+ * Eqs. (3)-(5)), FP64 only, to compare the two on the same integrals.
+ *
+ * Step 0: rif_eri4_from_b forms (mu nu|sigma lambda) = sum_l b^l_{mu nu}
+ * b^l_{sigma lambda} (the integrals the factors b of Eq. (9) fit, Eq. (6)) and
+ * stores them with the first pair packed:
+ *   eri [n_bf(n_bf+1)/2][n_bf][n_bf],  eri[(mu nu)][sigma][lambda] for mu <= nu,
+ *   (mu nu) = mu*n_bf - mu*(mu-1)/2 + (nu - mu)  (row-major upper triangle).
+ * rif_eri4_bytes gives its size (host function; 0 for bad sizes).  The call
+ * also takes n_aux * n_bf(n_bf+1)/2 doubles of workspace (b packed).
+ *
+ * Steps 1-3: rif_jk_4c, with P^q = c_q c_q^T (Eq. (4)),
+ *   Jn [n_omega][n_bf][n_bf]  J^q_{mu nu}    = sum P^q_{sigma lambda} (mu nu|sigma lambda)
+ *   Kn [n_omega][n_bf][n_bf]  K^q_{mu sigma} = sum P^q_{nu lambda} (mu nu|sigma lambda)
+ *   J, K [n_omega][n_omega]   J_pq = sum P^p_{mu nu} J^q_{mu nu}  (Eq. (3)),
+ *                             K_pq = sum P^p_{mu sigma} K^q_{mu sigma}  (Eq. (5))
+ * C [n_bf][n_mo]: Omega is its first n_omega columns.  Jn and Kn are written in
+ * full and exactly symmetric.  Workspace: n_omega * n_bf^2 (n_bf+1)/2 doubles
+ * (the integrals contracted with C over one index).  Device pointers owned by
+ * the caller; asynchronous on the context's stream.  RIF_EINVAL unless
+ * 0 < n_omega <= n_mo <= n_bf <= 2048, or for NULL pointers; RIF_ENOMEM if the
+ * workspace cannot be had. */
+unsigned long long rif_eri4_bytes(int n_bf);
+rif_status rif_eri4_from_b(rif_ctx *ctx, int n_bf, int n_aux, const double *b, double *eri);
+rif_status rif_jk_4c(rif_ctx *ctx, int n_bf, int n_omega, int n_mo, const double *eri, const double *C,
+                     double *Jn, double *Kn, double *J, double *K);
+
 /* b stored once for a reduced-precision mode (Sec. III: b is computed once
  * and kept in memory).  RIF_FP32: a float copy in b's layout.  RIF_BF16X3 /
  * RIF_BF16X6: 2 / 3 bf16 piece planes; RIF_FP16X3: 2 fp16 planes, hi and

@@ -79,6 +79,9 @@ EXPORTS = {
                               _i, _vp, _vp, _vp]),
     "rif_build": (_i, [_vp, ctypes.POINTER(Instance), _i, _i]),
     "rif_build_direct": (_i, [_vp, ctypes.POINTER(Instance), _i, _i]),
+    "rif_eri4_bytes": (ctypes.c_ulonglong, [_i]),
+    "rif_eri4_from_b": (_i, [_vp, _i, _i, _vp, _vp]),
+    "rif_jk_4c": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
     "rif_presplit_b_bytes": (ctypes.c_ulonglong, [_i, _i, _i]),
     "rif_presplit_b": (_i, [_vp, _i, _i, _vp, _i, _vp]),
     "rif_batch_create": (_i, [_vp, _i, ctypes.POINTER(Instance), _i, _i, ctypes.POINTER(_vp)]),
@@ -299,6 +302,39 @@ class Context:
             _ptr(energy, "energy", torch.float64, 1), _ptr(lam, "lambda", torch.float64, n_mo * n_omega),
             _ptr(grad, "grad", torch.float64, n_mo * n_mo)))
         return energy, lam, grad
+
+    # ---- the conventional four-centre path (Table 1) -----------------------
+    def eri4_from_b(self, b, eri=None):
+        """rif_eri4_from_b: (mu nu|sigma lambda) = sum_l b b with the first pair
+        packed, as a flat FP64 tensor of rif_eri4_bytes(n_bf) / 8 elements."""
+        import torch
+        n_aux, n_bf, _ = b.shape
+        n = int(self.lib.rif_eri4_bytes(n_bf)) // 8
+        if n == 0:
+            raise RifError(-1, "rif_eri4_bytes: bad n_bf")
+        if eri is None:
+            eri = torch.empty(n, dtype=torch.float64, device=b.device)
+        self._chk(self.lib.rif_eri4_from_b(self.h, n_bf, n_aux, _ptr(b, "b", torch.float64, n_aux * n_bf * n_bf),
+                                           _ptr(eri, "eri", torch.float64, n)))
+        return eri
+
+    def jk_4c(self, eri, C, n_omega, out=None):
+        """rif_jk_4c: Table 1 steps 1-3 from the packed integrals; returns a
+        dict with Jn, Kn [n_omega][n_bf][n_bf] and J, K [n_omega][n_omega]."""
+        import torch
+        n_bf, n_mo = C.shape
+        f64 = torch.float64
+        o = out if out is not None else {}
+        for k, shp in (("Jn", (n_omega, n_bf, n_bf)), ("Kn", (n_omega, n_bf, n_bf)), ("J", (n_omega, n_omega)),
+                       ("K", (n_omega, n_omega))):
+            if o.get(k) is None:
+                o[k] = torch.empty(shp, dtype=f64, device=C.device)
+        n = int(self.lib.rif_eri4_bytes(n_bf)) // 8
+        self._chk(self.lib.rif_jk_4c(
+            self.h, n_bf, n_omega, n_mo, _ptr(eri, "eri", f64, n), _ptr(C, "C", f64, n_bf * n_mo),
+            _ptr(o["Jn"], "Jn", f64, n_omega * n_bf * n_bf), _ptr(o["Kn"], "Kn", f64, n_omega * n_bf * n_bf),
+            _ptr(o["J"], "J", f64, n_omega * n_omega), _ptr(o["K"], "K", f64, n_omega * n_omega)))
+        return o
 
     # ---- one build: every hot-path step once -----------------------------
     def presplit_b(self, b, prec, out=None):

@@ -1304,6 +1304,12 @@ rif_status op_transform(rif_ctx* c, int prec, int nb, int na, int nw, int nmo, c
   RIF_PREC_SWITCH(prec, run_transform<P>(c, ps, h, m))
 }
 
+rif_status op_half_slabs_f64(rif_ctx* c, int nb, long nslab, int nw, int nmo, const double* slabs, const double* C,
+                             double* out) {
+  const HalfArgs h{nb, nw, nmo, nslab * nb, slabs, C, out, Planes{}, Planes{}, nullptr};
+  return step_half<kF64>(c, h);
+}
+
 rif_status op_jk_mo(rif_ctx* c, int prec, int na, int nw, const void* bmo, const double* d, double* J, double* K) {
   if (!prec_ok(prec)) return fail(c, RIF_ENOTSUP, "precision mode not available");
   const long w2 = (long)nw * nw;

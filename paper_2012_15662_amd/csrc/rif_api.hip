@@ -365,6 +365,30 @@ rif_status rif_build_direct(rif_ctx* c, const rif_instance* in, rif_prec prec, r
   return op_build_direct(c, (int)prec, (int)fn, *in);
 }
 
+unsigned long long rif_eri4_bytes(int nb) {
+  if (!dims_ok(nb) || nb > 2048) return 0;
+  return eri4_bytes(nb);
+}
+
+rif_status rif_eri4_from_b(rif_ctx* c, int nb, int na, const double* b, double* eri) {
+  if (!c) return RIF_EINVAL;
+  if (!dims_ok(nb) || !dims_ok(na) || nb > 2048 || (long)nb * nb > (1L << 30) || (long)nb * (nb + 1) / 2 >= (1L << 31))
+    return fail(c, RIF_EINVAL, "rif_eri4_from_b: need 0 < n_bf <= 2048 and n_aux > 0");
+  if (!b || !eri) return fail(c, RIF_EINVAL, "rif_eri4_from_b: NULL pointer");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  return op_eri4_from_b(c, nb, na, b, eri);
+}
+
+rif_status rif_jk_4c(rif_ctx* c, int nb, int nw, int nmo, const double* eri, const double* C, double* Jn, double* Kn,
+                     double* J, double* K) {
+  if (!c) return RIF_EINVAL;
+  if (!dims_ok(nb) || !dims_ok(nw) || !dims_ok(nmo) || nw > nmo || nmo > nb || nb > 2048)
+    return fail(c, RIF_EINVAL, "rif_jk_4c: need 0 < n_omega <= n_mo <= n_bf <= 2048");
+  if (!eri || !C || !Jn || !Kn || !J || !K) return fail(c, RIF_EINVAL, "rif_jk_4c: NULL pointer");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
+  return op_jk_4c(c, nb, nw, nmo, eri, C, Jn, Kn, J, K);
+}
+
 struct rif_batch {
   rif_ctx* c;
   void* impl;

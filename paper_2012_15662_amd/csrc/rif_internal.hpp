@@ -106,6 +106,17 @@ rif_status op_energy_grad(rif_ctx* c, int prec, int functional, int nb, int nmo,
                           const int* pair_of, const double* H, const double* C, const double* occ,
                           const double* J, const double* K, const void* Jn, const void* Kn, double* energy,
                           double* lambda, double* grad);
+// The FP64 half transform over any stack of symmetric n_bf x n_bf slabs:
+// out[q][s*n_bf + nu] = sum_mu C[mu][q] slabs[s][mu][nu], q < n_omega, s < nslab.
+rif_status op_half_slabs_f64(rif_ctx* c, int nb, long nslab, int nw, int nmo, const double* slabs, const double* C,
+                             double* out);
+// The conventional four-centre path of Table 1 (fourc.hip): the integrals with
+// the first pair packed, eri[(mu nu)][sigma][lambda] (mu <= nu), formed from b,
+// and steps 1-3 from them.
+unsigned long long eri4_bytes(int nb);
+rif_status op_eri4_from_b(rif_ctx* c, int nb, int na, const double* b, double* eri);
+rif_status op_jk_4c(rif_ctx* c, int nb, int nw, int nmo, const double* eri, const double* C, double* Jn, double* Kn,
+                    double* J, double* K);
 // ON optimisation and the warm-start MLP (on_mlp.hip)
 typedef rif_on_problem OnProblem;
 long on_work_doubles(int nw, int npairs, int ncwo);
