@@ -73,7 +73,10 @@ const char *rif_last_error(const rif_ctx *ctx);
 /* Replace the stream later calls launch on (NULL = the context's own). */
 rif_status rif_set_stream(rif_ctx *ctx, void *hip_stream);
 /* Wait for the context's stream, then report any deferred device-side
- * validation error (RIF_EINVAL with a message) and clear it. */
+ * validation error (RIF_EINVAL with a message) and clear it: occupations out
+ * of range or not summing to 1 per pair, a bad pair map, or a build whose
+ * energy or gradient came out non-finite (NaN/inf inputs, or in RIF_FP16X3 an
+ * operand of a split product of magnitude 65504 or more, past fp16's range). */
 rif_status rif_sync(rif_ctx *ctx);
 /* Cap on the context's workspace in bytes (0 = no cap).  A call that would
  * need more returns RIF_ENOMEM. */

@@ -130,7 +130,7 @@ struct FockRedArgs { int nb, nw, nsplit; const double *Yp, *occ, *HC; double* Y;
 // into nsplit ranges of kc; Zt, Bt (the mode's storage type) from k_ydz.
 struct YdzArgs { int na, nw; const double *Ac, *Bc, *d; void *Zt, *Bt; };
 struct YdArgs { int nb, na, nw, nsplit; long kc; const void *bh, *bmo, *Zt, *Bt; double* Yp; };
-struct GradArgs { int nmo, nw, lsplit; const double* lp; double *lam, *G; };
+struct GradArgs { int nmo, nw, lsplit; const double* lp; double *lam, *G; int* flag; };
 
 // Half transform, Eq. (12): bh[q][r] = sum_mu C[mu][q] b[l][mu][nu] with the
 // output column r = l*n_bf + nu flattened over (l, nu).  M = q, N = r (loads of
@@ -821,7 +821,10 @@ __device__ void energy_tile(const EnergyArgs& a, long, char* smem) {
     if (tid < s) red[tid] += red[tid + s];
     __syncthreads();
   }
-  if (tid == 0) a.energy[0] = red[0];
+  if (tid == 0) {
+    a.energy[0] = red[0];
+    if (!isfinite(red[0])) atomicOr(a.flag, kNonFinite);   // reported by rif_sync
+  }
   __syncthreads();
 }
 constexpr int kEnergySmem = 2048 * 8 + 2048 * 4 + kEnergyThreads * 8;
@@ -860,7 +863,9 @@ __device__ void grad_tile(const GradArgs& a, long t, char*) {
   const double lab = c < nw ? lam(r, c) : 0.0;
   const double lba = r < nw ? lam(c, r) : 0.0;
   if (c < nw) a.lam[(long)r * nw + c] = lab;
-  a.G[i] = 4.0 * (lab - lba);
+  const double g = 4.0 * (lab - lba);
+  a.G[i] = g;
+  if (!isfinite(g)) atomicOr(a.flag, kNonFinite);   // reported by rif_sync
 }
 
 // ---- kernel wrappers ---------------------------------------------------------
@@ -1241,7 +1246,7 @@ static BuildArgs make_build_args(const Plan& pl, const rif_instance& in, int pre
   A.fred = FockRedArgs{nb, nw, pl.fock_nsplit, Yp, in.occ, HC, Y};
   A.lam = GemmArgs{nmo, nw, nb, in.C, (long)nmo, Y, (long)nw, Lp, (long)nw, pl.lam_split, pl.small_kc,
                    (long)nmo * nw};
-  A.grad = GradArgs{nmo, nw, pl.lam_split, Lp, in.lambda, in.grad};
+  A.grad = GradArgs{nmo, nw, pl.lam_split, Lp, in.lambda, in.grad, flag};
   void* Zt = ws + pl.o_zt;
   void* Bt = ws + pl.o_bt;
   double* Ydp = (double*)(ws + pl.o_ydp);

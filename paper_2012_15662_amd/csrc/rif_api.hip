@@ -196,11 +196,15 @@ rif_status rif_sync(rif_ctx* c) {
     return fail(c, RIF_EHIP, "reading the status word failed");
   if (flag) {
     if (hipMemset(c->dflag, 0, sizeof(int)) != hipSuccess) return fail(c, RIF_EHIP, "hipMemset failed");
-    std::string m = "invalid occupations:";
+    std::string m;
+    if (flag & (kBadOcc | kBadSum | kBadMap | kBadCount)) m += "invalid occupations:";
     if (flag & kBadOcc) m += " an ON outside [0,1];";
     if (flag & kBadSum) m += " a pair whose ONs do not sum to 1;";
     if (flag & kBadMap) m += " a pair map entry out of range or a strong orbital g not in pair g;";
     if (flag & kBadCount) m += " a pair without exactly 1 + n_cwo orbitals;";
+    if (flag & kNonFinite)
+      m += std::string(m.empty() ? "" : " ") + "a non-finite energy or gradient (NaN or infinite inputs, or in "
+           "RIF_FP16X3 an operand of a split product of magnitude 65504 or more);";
     return fail(c, RIF_EINVAL, m);
   }
   return RIF_OK;

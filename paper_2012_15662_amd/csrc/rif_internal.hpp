@@ -53,7 +53,7 @@ struct rif_ctx {
 namespace rif {
 
 // Bits of the device status word set by device-side validation.
-enum : int { kBadOcc = 1, kBadSum = 2, kBadMap = 4, kBadCount = 8 };
+enum : int { kBadOcc = 1, kBadSum = 2, kBadMap = 4, kBadCount = 8, kNonFinite = 16 };
 
 // Fails the current call with a message.
 rif_status fail(rif_ctx* c, rif_status s, const std::string& msg);

@@ -85,18 +85,33 @@ def test_every_tile_variant(ctx, mode, variant):
 
 
 def test_fp16x3_range(ctx):
-    """fp16's largest finite value is 65504: operands below it are carried to
-    about 2^-22 (one element of b at 6e4 still matches the oracle), one above
-    it makes the affected outputs non-finite instead of silently wrong."""
+    """fp16's largest finite value is 65504.  An element of b at 6e4 is still
+    carried to about 2^-22 (b_half and J^q match the oracle), but J^q then
+    holds entries near 1.6e8, which overflow fp16 as operands of the split
+    Fock product: the gradient comes out infinite, the energy (which needs
+    only b_half, b_mo, J and K) stays right, and rif_sync reports it.  At 7e4
+    b itself overflows and the energy is not finite either.  Never silently
+    wrong."""
     import paper_2012_15662_amd as rif
     inst = synth.make_instance(40, 60, 3, 1, 5)
     inst.b[7, 3, 5] = inst.b[7, 5, 3] = 6.0e4
-    e, _, _ = errors(ctx, inst, rif.FP16X3)
+    ref = ri.build_instance(inst)
+    t = to_dev(inst)
+    out = ctx.build(t["b"], t["C"], t["H"], t["occ"], t["pair_of"], inst.n_pairs, inst.n_cwo, prec=rif.FP16X3)
+    with pytest.raises(rif.RifError) as err:
+        ctx.sync()
+    assert err.value.status == -1 and "non-finite" in str(err.value)
+    e = {k: relerr(host(out[k]), ref[k]) for k in ("b_half", "Jn")}
     print("b element 6e4", " ".join(f"{k}={v:.2e}" for k, v in e.items()), flush=True)
     assert e["b_half"] < 1e-6 and e["Jn"] < 1e-6
+    assert abs(float(host(out["energy"])[0]) - ref["energy"]) < 1e-6 * abs(ref["energy"])
+    assert not np.isfinite(host(out["grad"])).all()
     inst.b[7, 3, 5] = inst.b[7, 5, 3] = 7.0e4
     t = to_dev(inst)
     out = ctx.build(t["b"], t["C"], t["H"], t["occ"], t["pair_of"], inst.n_pairs, inst.n_cwo, prec=rif.FP16X3)
-    ctx.sync()
+    with pytest.raises(rif.RifError) as err:
+        ctx.sync()
+    assert err.value.status == -1 and "non-finite" in str(err.value)
     assert not np.isfinite(host(out["b_half"])).all()
     assert not np.isfinite(host(out["energy"])[0])
+    ctx.sync()   # the report is cleared: the next sync is clean

@@ -183,6 +183,20 @@ def test_full_size_ill_conditioned_metric(ctx):
     lhs = bm[:, xs].T @ bm[:, xs]
     rhs = Tm[:, xs].T @ np.linalg.solve(Gt, Tm[:, xs])
     assert np.max(np.abs(lhs - rhs)) <= 1e-5 * np.max(np.abs(rhs))
+    # Backward error of the solve with the GPU's own factors: b^T = D~^-1/2 L^-1 P^T T
+    # with L^-1 formed by forward substitution, then one GEMM, so the residual of
+    # P L D~^1/2 b^T = T obeys |T_pi - L D~^1/2 b^T| <= c n eps |L| |L^-1| |T_pi|
+    # elementwise, however small the pivots (sampled columns, c = 4)
+    _, Dh, _ = mt.corrected_blocks(D, info["steps"], delta)
+    cols = rng.choice(nb * nb, 400, replace=False)
+    Tp = Tm[perm][:, cols]
+    R = Tp - L @ (Dh @ bm[:, cols])
+    bound = 4.0 * na * np.finfo(float).eps * (np.abs(L) @ (np.abs(np.linalg.inv(L)) @ np.abs(Tp)))
+    ratio = np.max(np.abs(R) / bound)
+    print("full-size backward error: max |R| / (4 n eps |L||L^-1||T|) =", ratio,
+          " normwise |R|/(|L||D^1/2 b^T|) =", np.max(np.abs(R)) / np.max(np.abs(L) @ np.abs(Dh @ bm[:, cols])),
+          flush=True)
+    assert ratio <= 1.0
 
 
 def test_prepared_b_feeds_the_build(ctx):
