@@ -17,8 +17,11 @@
 //                 the FP32 MFMA engine: forward, backward, softmax/loss, Adam.
 #include <math.h>
 
+#include <algorithm>
+
 #include "mfma_engine.hpp"
 #include "rif_internal.hpp"
+#include "wave.hpp"
 
 namespace rif {
 
@@ -325,52 +328,65 @@ __global__ __launch_bounds__(kOnThreads) void k_on_opt(const OnProblem* __restri
 
 // ---- features, targets and warm start ------------------------------------
 
-// Row block of problem i starts at P.row0; one row per pair.
+// Row block of problem i starts at P.row0; one row per pair.  One wave per
+// (pair g, problem): the pair's weak orbitals (ascending index, the first
+// kKmax) found by a ballot over the orbitals, and each mean field
+// m_x = sum_{u strong, u != g} (2 J_xu - K_xu) as a lane-parallel FP64 sum with
+// a fixed-order wave reduction.
 __global__ __launch_bounds__(64) void k_on_feat(const OnProblem* __restrict__ probs, float* __restrict__ X,
                                                 float* __restrict__ T, float* __restrict__ M,
                                                 const float* __restrict__ mu, const float* __restrict__ sigma) {
-  const OnProblem& P = probs[blockIdx.x];
+  const OnProblem& P = probs[blockIdx.y];
+  const int g = blockIdx.x;
   const int nw = P.n_omega, np_ = P.n_pairs, nc = P.n_cwo;
-  for (int g = threadIdx.x; g < np_; g += 64) {
-    float f[kNin];
-    for (int i = 0; i < kNin; ++i) f[i] = 0.f;
-    float t[kNout], m[kNout];
-    for (int i = 0; i < kNout; ++i) { t[i] = 0.f; m[i] = 0.f; }
-    auto mf = [&](int x) {
-      double s = 0.0;
-      for (int u = 0; u < np_; ++u)
-        if (u != g) s += 2.0 * P.J[(long)x * nw + u] - P.K[(long)x * nw + u];
-      return s;
-    };
-    const int s0 = g;
-    f[0] = (float)P.Hpp[s0];
-    f[1] = (float)P.J[(long)s0 * nw + s0];
-    f[2] = (float)mf(s0);
-    t[0] = P.occ ? (float)P.occ[s0] : 0.f;
-    m[0] = 1.f;
-    int k = 0;
-    for (int p = np_; p < nw && k < kKmax; ++p) {
-      if (on_pair(P.pair_of, p, np_, nc) != g) continue;
-      f[3 + 5 * k + 0] = (float)(P.Hpp[p] - P.Hpp[s0]);
-      f[3 + 5 * k + 1] = (float)P.J[(long)p * nw + p];
-      f[3 + 5 * k + 2] = (float)P.K[(long)s0 * nw + p];
-      f[3 + 5 * k + 3] = (float)P.J[(long)s0 * nw + p];
-      f[3 + 5 * k + 4] = (float)mf(p);
-      f[3 + 5 * kKmax + k] = 1.f;
-      t[1 + k] = P.occ ? (float)P.occ[p] : 0.f;
-      m[1 + k] = 1.f;
-      ++k;
+  if (g >= np_) return;   // the whole wave
+  const int lane = threadIdx.x;
+  int weak[kKmax];
+  int k = 0;
+  for (int p0 = np_; p0 < nw && k < kKmax; p0 += 64) {
+    const int p = p0 + lane;
+    unsigned long long m = __ballot(p < nw && on_pair(P.pair_of, p, np_, nc) == g);
+    while (m && k < kKmax) {
+      weak[k++] = p0 + __ffsll((long long)m) - 1;
+      m &= m - 1;
     }
-    const long row = P.row0 + g;
-    for (int i = 0; i < kNin; ++i) {
-      float z = f[i];
-      if (mu && sigma && sigma[i] > 0.f) z = (z - mu[i]) / sigma[i];
-      X[row * kNin + i] = z;
-    }
-    for (int i = 0; i < kNout; ++i) {
-      if (T) T[row * kNout + i] = t[i];
-      if (M) M[row * kNout + i] = m[i];
-    }
+  }
+  auto mf = [&](int x) {
+    double s = 0.0;
+    for (int u = lane; u < np_; u += 64)
+      if (u != g) s += 2.0 * P.J[(long)x * nw + u] - P.K[(long)x * nw + u];
+    return wave_sum_dpp(s);
+  };
+  float f[kNin];
+  for (int i = 0; i < kNin; ++i) f[i] = 0.f;
+  float t[kNout], m[kNout];
+  for (int i = 0; i < kNout; ++i) { t[i] = 0.f; m[i] = 0.f; }
+  const int s0 = g;
+  f[0] = (float)P.Hpp[s0];
+  f[1] = (float)P.J[(long)s0 * nw + s0];
+  f[2] = (float)mf(s0);
+  t[0] = P.occ ? (float)P.occ[s0] : 0.f;
+  m[0] = 1.f;
+  for (int q = 0; q < k; ++q) {
+    const int p = weak[q];
+    f[3 + 5 * q + 0] = (float)(P.Hpp[p] - P.Hpp[s0]);
+    f[3 + 5 * q + 1] = (float)P.J[(long)p * nw + p];
+    f[3 + 5 * q + 2] = (float)P.K[(long)s0 * nw + p];
+    f[3 + 5 * q + 3] = (float)P.J[(long)s0 * nw + p];
+    f[3 + 5 * q + 4] = (float)mf(p);
+    f[3 + 5 * kKmax + q] = 1.f;
+    t[1 + q] = P.occ ? (float)P.occ[p] : 0.f;
+    m[1 + q] = 1.f;
+  }
+  const long row = P.row0 + g;
+  for (int i = lane; i < kNin; i += 64) {
+    float z = f[i];
+    if (mu && sigma && sigma[i] > 0.f) z = (z - mu[i]) / sigma[i];
+    X[row * kNin + i] = z;
+  }
+  for (int i = lane; i < kNout; i += 64) {
+    if (T) T[row * kNout + i] = t[i];
+    if (M) M[row * kNout + i] = m[i];
   }
 }
 
@@ -628,8 +644,10 @@ rif_status op_on_features(rif_ctx* c, int n, const OnProblem* probs, float* X, f
   OnProblem* d = nullptr;
   rif_status st = upload_problems(c, n, probs, &d);
   if (st) return st;
+  int maxp = 1;
+  for (int i = 0; i < n; ++i) maxp = std::max(maxp, probs[i].n_pairs);
   ProfScope ps(c, "on_features");
-  hipLaunchKernelGGL(k_on_feat, dim3(n), dim3(64), 0, c->stream, d, X, T, M, mu, sigma);
+  hipLaunchKernelGGL(k_on_feat, dim3((unsigned)maxp, (unsigned)n), dim3(64), 0, c->stream, d, X, T, M, mu, sigma);
   return check_launch(c, "on_features");
 }
 

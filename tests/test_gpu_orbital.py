@@ -148,6 +148,24 @@ def test_full_loop_converges_to_a_stationary_point(ctx):
     assert res["outer"] == len(ref["energies"])
 
 
+def test_loop_reports_when_it_does_not_converge(ctx):
+    """A mid-size molecule (n_bf=60, n_aux=150, 4 pairs, Ncwo=2) with a gradient
+    tolerance the plain iteration does not reach within its limits: the loop
+    returns status 1 (iteration limit), with every inner iteration recorded, a
+    finite energy and max|G| above the tolerance, and orbitals still
+    orthonormal."""
+    inst = synth.make_instance(60, 150, 4, 2, 33)
+    print("case loop not converging n_bf=60 n_aux=150 pairs=4 ncwo=2 seed=33", flush=True)
+    kw = dict(max_outer=2, max_inner=40, tol_grad=1e-10, tol_energy=1e-12, on_tol=1e-10)
+    res, he, hg, C, occ = run_loop(ctx, inst, inst.C, inst.occ, **kw)
+    print("gpu loop", res, flush=True)
+    assert res["status"] == 1
+    assert res["outer"] == 2 and res["inner_total"] == 80 and len(he) == 80
+    assert np.isfinite(res["energy"]) and res["max_grad"] > kw["tol_grad"]
+    assert he[-1] == res["energy"] and hg[-1] == res["max_grad"]
+    assert np.allclose(C.T @ C, np.eye(inst.n_mo), atol=1e-11)
+
+
 def fci_two_electrons(h, eri):
     n = h.shape[0]
     I = np.eye(n)
