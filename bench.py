@@ -534,13 +534,13 @@ def bench_orbopt(args):
         torch.cuda.synchronize()
         return res, he, hg, time.perf_counter() - t0
 
-    inst = synth.workload("c6h12")
+    inst = synth.workload(args.orb_size)
     d = upload(inst)
     run(inst, d, max_outer=1, max_inner=3, tol_grad=1e-14)          # tile tuning, solver set-up
     res, he, hg, wall = run(inst, d, max_outer=1, max_inner=args.steps, tol_grad=1e-14)
     n = res["inner_total"]
     per_ms = (res["ms_build"] + res["ms_orbital"]) / n
-    print(f"c6h12: {n} inner iterations, build {res['ms_build'] / n:.3f} ms, orbital step "
+    print(f"{args.orb_size}: {n} inner iterations, build {res['ms_build'] / n:.3f} ms, orbital step "
           f"{res['ms_orbital'] / max(1, n - 1):.3f} ms, ON step {res['ms_on']:.2f} ms; E {he[0]:.6f} -> {he[-1]:.6f}, "
           f"max|G| {hg[0]:.2e} -> {hg[-1]:.2e}", file=sys.stderr, flush=True)
 
@@ -570,12 +570,15 @@ def bench_orbopt(args):
         "value": round(1e3 / per_ms, 3), "unit": "inner iterations/s", "n_gpus": 1, "steps": n,
         "warmup": 3, "ms_per_step": round(per_ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "orbopt: c6h12 n_bf=348 n_aux=1044 pairs=24 ncwo=4 n_mo=348, fixed ONs after one ON step"},
+        "config": {"workload": f"orbopt: {args.orb_size} n_bf={inst.n_bf} n_aux={inst.n_aux} pairs={inst.n_pairs} "
+                               f"ncwo={inst.n_cwo} n_mo={inst.n_mo}, fixed ONs after one ON step"},
         "split_ms": {"build_with_maxG": round(res["ms_build"] / n, 4),
                      "orbital_step": round(res["ms_orbital"] / max(1, n - 1), 4),
                      "on_step_once": round(res["ms_on"], 3)},
         "wall_s": round(wall, 3), "energy_first": he[0], "energy_last": he[-1], "max_grad_first": hg[0],
-        "max_grad_last": hg[-1],
+        "max_grad_last": hg[-1], "max_grad_min": min(hg), "energy_min": min(he),
+        "trajectory": [{"iteration": i, "energy": he[i], "max_grad": hg[i]}
+                       for i in sorted(set([0, 9, 99, 499, 999, 1999, 4999, len(he) - 1])) if i < len(he)],
         "small_to_convergence": small_line,
         "cpu_baseline": cpu,
     }
@@ -670,6 +673,8 @@ def main():
     ap.add_argument("--no-4c", action="store_true", help="skip the RI vs four-centre comparison")
     ap.add_argument("--no-c10h20", action="store_true",
                     help="skip the precision study at the cyclodecane-like size")
+    ap.add_argument("--orb-size", default="c6h12", choices=["tiny", "c6h12", "c10h20"],
+                    help="orbopt: the molecule whose inner iterations are run")
     ap.add_argument("--no-small", action="store_true",
                     help="orbopt: skip the small molecule run to convergence")
     args = ap.parse_args()

@@ -208,13 +208,20 @@ rif_status rif_jk_4c(rif_ctx *ctx, int n_bf, int n_omega, int n_mo, const double
 
 /* b stored once for a reduced-precision mode (Sec. III: b is computed once
  * and kept in memory).  RIF_FP32: a float copy in b's layout.  RIF_BF16X3 /
- * RIF_BF16X6: 2 / 3 bf16 piece planes; RIF_FP16X3: 2 fp16 planes, hi and
- * lo * 2^11 (each the same split arithmetic as the kernels' staging), plane s at out + s * n_aux * n_bf * ld with
- * ld = n_bf rounded up to a multiple of 32; element (l*n_bf + nu, mu) of a
- * plane holds piece s of b[l][nu][mu] (b symmetric in mu, nu), zero from mu =
- * n_bf up to ld.  rif_presplit_b_bytes gives the size of out (host function,
- * no GPU call; 0 for RIF_FP64 or bad sizes).  Asynchronous.  RIF_EINVAL for
- * sizes or NULL pointers, RIF_ENOTSUP for RIF_FP64. */
+ * RIF_BF16X6: P = 2 / 3 bf16 piece planes; RIF_FP16X3: P = 2 fp16 planes, hi
+ * and lo * 2^11 (each the same split arithmetic as the kernels' staging), in
+ * two regions of out (16-bit elements):
+ *   - for the half transform: plane s at out + s * n_aux * n_bf * ld with ld =
+ *     n_bf rounded up to a multiple of 32; element (l*n_bf + nu, mu) of a plane
+ *     holds piece s of b[l][nu][mu] (b symmetric in mu, nu), zero from mu =
+ *     n_bf up to ld;
+ *   - for J^q (Table 3 step 4), after the first region (at out + P * n_aux *
+ *     n_bf * ld): plane s at + s * n_bf^2 * lj with lj = n_aux rounded up to a
+ *     multiple of 32; element (mu*n_bf + nu, l) holds piece s of b[l][mu][nu],
+ *     zero from l = n_aux up to lj.
+ * rif_presplit_b_bytes gives the size of out (host function, no GPU call; 0
+ * for RIF_FP64 or bad sizes).  Asynchronous.  RIF_EINVAL for sizes or NULL
+ * pointers, RIF_ENOTSUP for RIF_FP64. */
 unsigned long long rif_presplit_b_bytes(int n_bf, int n_aux, rif_prec prec);
 rif_status rif_presplit_b(rif_ctx *ctx, int n_bf, int n_aux, const double *b, rif_prec prec, void *out);
 

@@ -86,7 +86,9 @@ struct HalfArgs { int nb, nw, nmo; long nr; const double* b; const double* C; vo
 // FP32 mode: a float copy.
 struct BSplitArgs { const double* b; long nr; int nb, ld; void* out; long ps; };
 struct MoArgs { int nb, na, nw, nmo; const void* bh; const double* C; void* bmo; double* d; Planes Cs; };
-struct JaoArgs { int nb, na, nw; const double* b; const double* d; void* Jn; Planes Ds; };
+// Bj: b pre-split for J^q (piece planes with rows r = mu*n_bf + nu and
+// k = l contiguous), or unset (split on load).
+struct JaoArgs { int nb, na, nw; const double* b; const double* d; void* Jn; Planes Ds; Planes Bj; };
 // Pre-split of X (element (x, k) at X[k*sk + x]) into NPC bf16 planes
 // out[s*ps + x*ld + k], zero from k = K up to ld.
 struct PSplitArgs { const double* X; long sk; int nx, K, ld; unsigned short* out; long ps; };
@@ -291,6 +293,54 @@ __device__ void jao_tile(const JaoArgs& a, long t, char* smem) {
     la.init(a.d, nw, na, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
   XCS<P, double, Cfg::BN, Cfg::NT> lb;
   lb.init(a.b, B2, na, [&](int x, long& o) {
+    const int mu = mu0 + x / TNU, nu = nu0 + x % TNU;
+    o = (long)mu * nb + nu;
+    return mu < nb && nu < nb;
+  });
+  typename E::template Acc<Cfg> acc;
+  gemm_mainloop<E, Cfg>(la, lb, cdiv(na, E::BK), acc, smem);
+  IOT<P>* Jn = (IOT<P>*)a.Jn;
+  acc.for_each([&](int m, int n, double v) {
+    const int q = q0 + m, mu = mu0 + n / TNU, nu = nu0 + n % TNU;
+    if (q < nw && mu < nb && nu < nb) {
+      IOT<P>* J = Jn + (long)q * B2;
+      if (mu <= nu) J[(long)mu * nb + nu] = (IOT<P>)v;
+      if (mu < nu) J[(long)nu * nb + mu] = (IOT<P>)v;
+    }
+  });
+}
+
+// The same J^q tile with b read as pre-split piece planes (split modes):
+// B element (x = (mu, nu) of the block, k = l) at plane row mu*n_bf + nu, and
+// d^T from its piece planes, so neither operand is split here.  The pieces are
+// the staging path's own split of the same values, so the results are bitwise
+// those of jao_tile.
+template <int P, class Cfg>
+__host__ __device__ inline long jaop_tiles(const JaoArgs& a) { return jao_tiles<P, Cfg>(a); }
+template <int P, class Cfg>
+__device__ void jaop_tile(const JaoArgs& a, long t, char* smem) {
+  using E = typename EngineOf<P>::type;
+  constexpr int TNU = kJaoTNU, TMU = Cfg::BN / TNU;
+  const int nb = a.nb, na = a.na, nw = a.nw;
+  const int nbj = cdiv(nb, TNU), nbi = cdiv(nb, TMU);
+  const long nq = cdiv(nw, Cfg::BM);
+  const int qt = (int)(t % nq);
+  long r = t / nq;
+  int bi = 0;
+  for (; bi < nbi; ++bi) {
+    const int n = nbj - jao_first_col(bi, TMU, TNU);
+    if (r < n) break;
+    r -= n;
+  }
+  if (bi >= nbi) return;
+  const int bj = jao_first_col(bi, TMU, TNU) + (int)r;
+  const int mu0 = bi * TMU, nu0 = bj * TNU;
+  const int q0 = qt * Cfg::BM;
+  const long B2 = (long)nb * nb;
+  PCS<P, Cfg::BM, Cfg::NT> la;
+  la.init(a.Ds.p, a.Ds.ps, a.Ds.ld, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
+  PCS<P, Cfg::BN, Cfg::NT> lb;
+  lb.init(a.Bj.p, a.Bj.ps, a.Bj.ld, [&](int x, long& o) {
     const int mu = mu0 + x / TNU, nu = nu0 + x % TNU;
     o = (long)mu * nb + nu;
     return mu < nb && nu < nb;
@@ -655,6 +705,39 @@ __device__ void bsplit_tile(const BSplitArgs& a, long t, char*) {
   }
 }
 
+// b pre-split for J^q: plane s, row r = mu*n_bf + nu (every mu, nu), k = l
+// contiguous; element (r, l) is piece s of b[l][mu][nu], zero from l = n_aux up
+// to ld (a multiple of 32).  64 x 64 (r, l) tiles transposed through LDS: b is
+// read along r, the pieces written along l, each pair (l, l+1) split by the
+// staging path's arithmetic.
+struct BSplitJArgs { const double* b; long nrow; int na, ld; unsigned short* out; long ps; };
+template <int P>
+__global__ __launch_bounds__(256) void k_bsplitj(BSplitJArgs a) {
+  constexpr int NPC = kPieces<P>;
+  __shared__ double t[64][65];
+  const long r0 = (long)blockIdx.x * 64;
+  const int l0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int y = ty; y < 64; y += 4) {
+    const int l = l0 + y;
+    const long r = r0 + tx;
+    t[y][tx] = (l < a.na && r < a.nrow) ? a.b[(long)l * a.nrow + r] : 0.0;
+  }
+  __syncthreads();
+  const int pl = threadIdx.x & 31, ry = threadIdx.x >> 5;
+  const int l = l0 + 2 * pl;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int y = ry + 8 * j;
+    const long r = r0 + y;
+    if (r >= a.nrow || l >= a.ld) continue;
+    unsigned pc[NPC];
+    split_mode<P>(t[2 * pl][y], t[2 * pl + 1][y], pc);
+#pragma unroll
+    for (int s = 0; s < NPC; ++s) *(unsigned*)(a.out + s * a.ps + r * a.ld + l) = pc[s];
+  }
+}
+
 // ---- element-wise and reduction steps (256-thread tiles) -------------------
 
 // MO J/K partial sums over a contiguous range of l (fixed split), then a
@@ -917,6 +1000,7 @@ RIF_STEP_KERNELS(half, HalfArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
 RIF_STEP_KERNELS(halfp, HalfArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
 RIF_STEP_KERNELS(mo, MoArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
 RIF_STEP_KERNELS(jao, JaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE)
+RIF_STEP_KERNELS(jaop, JaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE)
 RIF_STEP_KERNELS(kao, KaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE)
 RIF_STEP_KERNELS(gemm, GemmArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
 RIF_STEP_KERNELS(fock, FockArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
@@ -995,6 +1079,7 @@ template <class Cfg> static double useful_half(const HalfArgs& a) { return (doub
 template <class Cfg> static double useful_halfp(const HalfArgs& a) { return useful_half<Cfg>(a); }
 template <class Cfg> static double useful_mo(const MoArgs& a) { return (double)a.nw / (cdiv(a.nw, Cfg::BN) * Cfg::BN); }
 template <class Cfg> static double useful_jao(const JaoArgs& a) { return (double)a.nw / (cdiv(a.nw, Cfg::BM) * Cfg::BM); }
+template <class Cfg> static double useful_jaop(const JaoArgs& a) { return useful_jao<Cfg>(a); }
 template <class Cfg> static double useful_kao(const KaoArgs& a) {
   const long nbk = cdiv(a.nb, Cfg::BM);
   return (double)a.nb * (a.nb + 1) / 2 / (nbk * (nbk + 1) / 2 * (double)Cfg::BM * Cfg::BM);
@@ -1045,6 +1130,14 @@ static rif_status step_half_any(rif_ctx* c, const HalfArgs& a) {
 }
 RIF_GEMM_STEP(mo, MoArgs, "mo_transform", 4, a.nb, a.na, a.nw, a.nmo)
 RIF_GEMM_STEP(jao, JaoArgs, "jao", 4, a.nb, a.na, a.nw)
+RIF_GEMM_STEP(jaop, JaoArgs, "jao_presplit", 4, a.nb, a.na, a.nw)
+// J^q from the pre-split b where the build has it (split modes), else split on load.
+template <int P>
+static rif_status step_jao_any(rif_ctx* c, const JaoArgs& a) {
+  if constexpr (kPieces<P> > 0)
+    if (a.Bj.p) return step_jaop<P>(c, a);
+  return step_jao<P>(c, a);
+}
 RIF_GEMM_STEP(kao, KaoArgs, "kao", 2, a.nb, a.na, a.nw)
 RIF_GEMM_STEP(fock, FockArgs, "fock", 4, a.nb, a.nw, a.nmo, a.nsplit)
 // The direct contraction has few q (n_omega) and many nu (n_bf) columns: its
@@ -1234,7 +1327,13 @@ static BuildArgs make_build_args(const Plan& pl, const rif_instance& in, int pre
   }
   A.mo = MoArgs{nb, na, nw, nmo, in.b_half, in.C, in.b_mo, in.d, cs};
   A.jk = JkArgs{na, nw, pl.jk_nsplit, in.b_mo, in.d, part, in.J, in.K};
-  A.jao = JaoArgs{nb, na, nw, in.b, in.d, in.Jn, ds};
+  A.jao = JaoArgs{nb, na, nw, in.b, in.d, in.Jn, ds, Planes{nullptr, 0, 0}};
+  if (in.b_split && (prec == RIF_BF16X3 || prec == RIF_BF16X6 || prec == RIF_FP16X3)) {
+    const long npc = prec == RIF_BF16X6 ? 3 : 2;
+    const int lj = round32(na);
+    const unsigned short* j0 = (const unsigned short*)in.b_split + npc * (long)na * nb * round32(nb);
+    A.jao.Bj = Planes{j0, (long)nb * nb * lj, lj};
+  }
   A.kao = KaoArgs{nb, na, nw, in.b_half, in.Kn};
   A.hc = GemmArgs{nb, nw, nb, in.H, (long)nb, in.C, (long)nmo, HCp, (long)nw,
                   pl.hc_split, pl.small_kc, (long)nb * nw};
@@ -1443,8 +1542,8 @@ static rif_status run_build(rif_ctx* c, const BuildArgs& A) {
         (st = hip(hipEventRecord(e_side, side))))
       return st;
   }
-  if ((kPlanesHalfJao<P> && (st = step_psplit<P>(c, A.psd))) || (st = step_jao<P>(c, A.jao)) ||
-      (st = step_kao<P>(c, A.kao)))
+  if (((kPlanesHalfJao<P> || (kPieces<P> > 0 && A.jao.Bj.p)) && (st = step_psplit<P>(c, A.psd))) ||
+      (st = step_jao_any<P>(c, A.jao)) || (st = step_kao<P>(c, A.kao)))
     return st;
   if ((st = hip(hipStreamWaitEvent(main, e_side, 0))) || (st = step1_coef(c, A.coef)) ||
       (st = hip(hipEventRecord(e_coef, main))))
@@ -1522,8 +1621,11 @@ rif_status op_build(rif_ctx* c, int prec, int functional, const rif_instance& in
 unsigned long long presplit_b_bytes(int nb, int na, int prec) {
   const unsigned long long nr = (unsigned long long)na * nb;
   if (prec == RIF_FP32) return nr * nb * 4ull;
-  if (prec == RIF_BF16X3 || prec == RIF_BF16X6 || prec == RIF_FP16X3)
-    return (prec == RIF_BF16X6 ? 3ull : 2ull) * nr * (unsigned long long)round32(nb) * 2ull;
+  if (prec == RIF_BF16X3 || prec == RIF_BF16X6 || prec == RIF_FP16X3) {
+    const unsigned long long npc = prec == RIF_BF16X6 ? 3ull : 2ull;
+    return npc * nr * (unsigned long long)round32(nb) * 2ull +                        // half transform
+           npc * (unsigned long long)nb * nb * (unsigned long long)round32(na) * 2ull;  // J^q
+  }
   return 0;
 }
 
@@ -1550,6 +1652,18 @@ rif_status op_presplit_b(rif_ctx* c, int prec, int nb, int na, const double* b, 
       break;
     default:
       return fail(c, RIF_ENOTSUP, "rif_presplit_b: FP32, BF16x3, BF16x6 or FP16x3 only");
+  }
+  rif_status st = check_launch(c, "presplit_b");
+  if (st || prec == RIF_FP32) return st;
+  // the second region: b in J^q's operand order
+  const long npc = prec == RIF_BF16X6 ? 3 : 2;
+  const int lj = round32(na);
+  const BSplitJArgs aj{b, (long)nb * nb, na, lj, (unsigned short*)out + npc * (long)na * nb * ld, (long)nb * nb * lj};
+  const dim3 grid((unsigned)cdiv((long)nb * nb, 64), (unsigned)cdiv(lj, 64));
+  switch (prec) {
+    case RIF_BF16X3: hipLaunchKernelGGL((k_bsplitj<kBF16x3>), grid, dim3(256), 0, c->stream, aj); break;
+    case RIF_BF16X6: hipLaunchKernelGGL((k_bsplitj<kBF16x6>), grid, dim3(256), 0, c->stream, aj); break;
+    default: hipLaunchKernelGGL((k_bsplitj<kF16x3>), grid, dim3(256), 0, c->stream, aj); break;
   }
   return check_launch(c, "presplit_b");
 }

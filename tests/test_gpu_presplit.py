@@ -60,7 +60,7 @@ def test_piece_planes_sum_to_b(ctx, mode, prec, npc):
     t = to_dev(inst)
     raw = host(ctx.presplit_b(t["b"], prec)).view(np.uint16)
     nb, na, ld = inst.n_bf, inst.n_aux, 64
-    planes = raw.reshape(npc, na * nb, ld)
+    planes = raw[:npc * na * nb * ld].reshape(npc, na * nb, ld)
     assert np.all(planes[:, :, nb:] == 0)
     total = sum(bf16_to_f32(planes[s, :, :nb]).astype(np.float64) for s in range(npc))
     ref = inst.b.reshape(na * nb, nb)          # row l*n_bf + nu, column mu (b symmetric)
@@ -80,7 +80,7 @@ def test_fp16_planes_sum_to_b(ctx):
     t = to_dev(inst)
     raw = host(ctx.presplit_b(t["b"], rif.FP16X3)).view(np.uint16)
     nb, na, ld = inst.n_bf, inst.n_aux, 64
-    planes = raw.reshape(2, na * nb, ld)
+    planes = raw[:2 * na * nb * ld].reshape(2, na * nb, ld)
     assert np.all(planes[:, :, nb:] == 0)
     hi = planes[0, :, :nb].view(np.float16).astype(np.float64)
     lo = planes[1, :, :nb].view(np.float16).astype(np.float64)
@@ -101,8 +101,9 @@ def test_fp32_copy_and_errors(ctx):
     with pytest.raises(rif.RifError):
         ctx.presplit_b(t["b"], rif.FP64)
     assert ctx.lib.rif_presplit_b_bytes(20, 30, rif.FP64) == 0
-    assert ctx.lib.rif_presplit_b_bytes(20, 30, rif.BF16X6) == 3 * 30 * 20 * 32 * 2
-    assert ctx.lib.rif_presplit_b_bytes(20, 30, rif.FP16X3) == 2 * 30 * 20 * 32 * 2
+    # the half-transform region, then the J^q region (n_aux rounded up to 32)
+    assert ctx.lib.rif_presplit_b_bytes(20, 30, rif.BF16X6) == 3 * 30 * 20 * 32 * 2 + 3 * 20 * 20 * 32 * 2
+    assert ctx.lib.rif_presplit_b_bytes(20, 30, rif.FP16X3) == 2 * 30 * 20 * 32 * 2 + 2 * 20 * 20 * 32 * 2
 
 
 @pytest.mark.parametrize("prec", [1, 3, 4])
@@ -123,3 +124,20 @@ def test_batch_with_presplit_b(ctx, prec):
     for oa, ob in zip(ba.outs, bb.outs):
         for k in ("energy", "lam", "grad", "Jn", "Kn"):
             assert np.array_equal(host(oa[k]), host(ob[k])), k
+
+
+@pytest.mark.parametrize("mode,prec,npc", [("bf16x3", 2, 2), ("bf16x6", 3, 3), ("fp16x3", 4, 2)])
+def test_jq_planes_hold_b_by_aux_index(ctx, mode, prec, npc):
+    """The second region: plane s, row mu*n_bf + nu, k = l contiguous (n_aux
+    rounded up to 32, zero beyond), each element the same pieces as the first
+    region's copy of the same b value (one split, two layouts)."""
+    inst = synth.make_instance(37, 45, 2, 1, 7)
+    t = to_dev(inst)
+    raw = host(ctx.presplit_b(t["b"], prec)).view(np.uint16)
+    nb, na, ld, lj = inst.n_bf, inst.n_aux, 64, 64
+    first = raw[:npc * na * nb * ld].reshape(npc, na, nb, ld)[:, :, :, :nb]     # [s][l][nu][mu]
+    second = raw[npc * na * nb * ld:].reshape(npc, nb, nb, lj)                 # [s][mu][nu][l]
+    assert raw.size == npc * na * nb * ld + npc * nb * nb * lj
+    assert np.all(second[:, :, :, na:] == 0)
+    # second[s][mu][nu][l] = piece s of b[l][mu][nu] = first[s][l][nu][mu]
+    assert np.array_equal(second[:, :, :, :na], first.transpose(0, 3, 2, 1))
