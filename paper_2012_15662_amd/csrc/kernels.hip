@@ -66,6 +66,13 @@ constexpr bool kPlanesMo = kPieces<P> > 0;
 template <int P>
 constexpr bool kPlanesHalfJao = kPieces<P> == 2;
 constexpr int round32(int k) { return (k + 31) / 32 * 32; }
+// Slices of global loads in flight in the two-piece modes' GEMMs whose
+// operands are read without splitting VALU work or fit the register budget
+// with a second load set (pre-split half transform and J^q, MO transform,
+// K^q): two, since one slice's MFMA work is shorter than a load's latency.
+// Elsewhere, and with three pieces, the second set would spill.
+template <int P>
+constexpr int kDeep = kPieces<P> == 2 ? 2 : 1;
 
 // ---------------------------------------------------------------------------
 // Per-step argument blocks.  Each step is written once as a tile function
@@ -177,7 +184,7 @@ __device__ void half_tile_with(const HalfArgs& a, long t, char* smem) {
   else
     lb.init(a.bf, nb, nb, slab_off);
   typename E::template Acc<Cfg> acc;
-  gemm_mainloop<E, Cfg>(la, lb, cdiv(nb, E::BK), acc, smem);
+  gemm_mainloop<E, Cfg, kBPre ? kDeep<P> : 1>(la, lb, cdiv(nb, E::BK), acc, smem);
   acc.for_each([&](int m, int n, double v) {
     const int q = q0 + m;
     const long r = r0 + n;
@@ -229,7 +236,7 @@ __device__ void mo_tile(const MoArgs& a, long t, char* smem) {
   else
     lb.init(a.C, a.nmo, nb, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
   typename E::template Acc<Cfg> acc;
-  gemm_mainloop<E, Cfg>(la, lb, cdiv(nb, E::BK), acc, smem);
+  gemm_mainloop<E, Cfg, kDeep<P>>(la, lb, cdiv(nb, E::BK), acc, smem);
   acc.for_each([&](int m, int n, double v) {
     const long s = s0 + m;
     const int q = q0 + n;
@@ -346,7 +353,7 @@ __device__ void jaop_tile(const JaoArgs& a, long t, char* smem) {
     return mu < nb && nu < nb;
   });
   typename E::template Acc<Cfg> acc;
-  gemm_mainloop<E, Cfg>(la, lb, cdiv(na, E::BK), acc, smem);
+  gemm_mainloop<E, Cfg, kDeep<P>>(la, lb, cdiv(na, E::BK), acc, smem);
   IOT<P>* Jn = (IOT<P>*)a.Jn;
   acc.for_each([&](int m, int n, double v) {
     const int q = q0 + m, mu = mu0 + n / TNU, nu = nu0 + n % TNU;
@@ -405,7 +412,7 @@ __device__ void kao_tile(const KaoArgs& a, long t, char* smem) {
   // registers for the extra loop copies) always compute whole blocks.
   constexpr bool kPlan = P == kF64 || P == kF32;
   if (!kPlan || (!diag && fim == FB && fjm == FB)) {
-    gemm_mainloop<E, Cfg>(la, lb, cdiv(na, E::BK), acc, smem);
+    gemm_mainloop<E, Cfg, kDeep<P>>(la, lb, cdiv(na, E::BK), acc, smem);
     acc.for_each(store);
     return;
   }

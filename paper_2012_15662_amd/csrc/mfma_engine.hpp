@@ -674,7 +674,12 @@ template <> struct EngineOf<kF16x3> { using type = EngSplit<2, true>; };
 // out [A stage 0][A stage 1][B stage 0][B stage 1].  mma(SA, SB, acc)
 // consumes one staged slice.  With b_is_a (square tiles whose two operands
 // are the same panel) only A is loaded and staged, and mma reads it twice.
-template <class E, class Cfg, class LA, class LB, class MMA>
+// DEPTH slices of global loads are in flight: with DEPTH = 2 the registers
+// alternate between two sets, so the loads of slice kt+2 are issued while
+// slice kt+1 is still being staged (a split engine's slice holds a few
+// hundred cycles of MFMA work, shorter than a load's latency from HBM).  It
+// costs the registers of one more set.
+template <class E, class Cfg, int DEPTH = 1, class LA, class LB, class MMA>
 __device__ __forceinline__ void gemm_mainloop_with(LA& la, LB& lb, int nk, typename E::template Acc<Cfg>& acc,
                                                    char* smem_generic, bool b_is_a, MMA&& mma) {
   constexpr int SA = E::template stage_bytes<Cfg::BM>();
@@ -692,38 +697,74 @@ __device__ __forceinline__ void gemm_mainloop_with(LA& la, LB& lb, int nk, typen
   if (nk <= 0) return;
   la.fetch(0, ra);
   if (!b_is_a) lb.fetch(0, rb);
-  E::template stash<Cfg::BM>(As[0], la, ra, 0);
-  if (!b_is_a) E::template stash<Cfg::BN>(Bs[0], lb, rb, 0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    const bool more = kt + 1 < nk;
-    if (more) {
-      // issue the next slice's global loads ahead of other waves' MFMAs, so they
-      // are in flight for the whole slice
-      __builtin_amdgcn_s_setprio(1);
-      la.fetch(kt + 1, ra);
-      if (!b_is_a) lb.fetch(kt + 1, rb);
-      __builtin_amdgcn_s_setprio(0);
-    }
-    mma(As[cur], Bs[cur], acc);
-    if ((kt + 1) % E::CHUNK == 0) acc.flush();
-    if (more) {
-      E::template stash<Cfg::BM>(As[cur ^ 1], la, ra, kt + 1);
-      if (!b_is_a) E::template stash<Cfg::BN>(Bs[cur ^ 1], lb, rb, kt + 1);
-    }
+  static_assert(DEPTH == 1 || DEPTH == 2, "prefetch depth");
+  if constexpr (DEPTH == 2) {
+    // Every step issues its loads and staging writes on every path (past the
+    // end they re-read slice nk-1 and stage unused data into the idle buffer),
+    // and the loop runs an even number of steps (a last step past nk skips only
+    // its MFMAs).  The in-order load counter then lets each wait cover exactly
+    // the older set.
+    typename LA::type ra2[LA::RR];
+    typename LB::type rb2[LB::RR];
+    la.fetch(nk > 1 ? 1 : 0, ra2);
+    if (!b_is_a) lb.fetch(nk > 1 ? 1 : 0, rb2);
+    E::template stash<Cfg::BM>(As[0], la, ra, 0);
+    if (!b_is_a) E::template stash<Cfg::BN>(Bs[0], lb, rb, 0);
     __syncthreads();
+    // slice kt: loads of slice kt+2 into the set that held slice kt (staged
+    // already), MFMAs on stage kt&1, then slice kt+1 staged from the other set
+    auto step = [&](int kt, typename LA::type (&fa)[LA::RR], typename LB::type (&fb)[LB::RR],
+                    const typename LA::type (&sa)[LA::RR], const typename LB::type (&sb)[LB::RR]) {
+      const int cur = kt & 1;
+      const int kf = kt + 2 < nk ? kt + 2 : nk - 1;
+      __builtin_amdgcn_s_setprio(1);
+      la.fetch(kf, fa);
+      if (!b_is_a) lb.fetch(kf, fb);
+      __builtin_amdgcn_s_setprio(0);
+      if (kt < nk) mma(As[cur], Bs[cur], acc);
+      if ((kt + 1) % E::CHUNK == 0) acc.flush();
+      E::template stash<Cfg::BM>(As[cur ^ 1], la, sa, kt + 1);
+      if (!b_is_a) E::template stash<Cfg::BN>(Bs[cur ^ 1], lb, sb, kt + 1);
+      __syncthreads();
+    };
+    for (int kt = 0; kt < nk; kt += 2) {
+      step(kt, ra, rb, ra2, rb2);
+      step(kt + 1, ra2, rb2, ra, rb);
+    }
+  } else {
+    E::template stash<Cfg::BM>(As[0], la, ra, 0);
+    if (!b_is_a) E::template stash<Cfg::BN>(Bs[0], lb, rb, 0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int cur = kt & 1;
+      const bool more = kt + 1 < nk;
+      if (more) {
+        // issue the next slice's global loads ahead of other waves' MFMAs, so
+        // they are in flight for the whole slice
+        __builtin_amdgcn_s_setprio(1);
+        la.fetch(kt + 1, ra);
+        if (!b_is_a) lb.fetch(kt + 1, rb);
+        __builtin_amdgcn_s_setprio(0);
+      }
+      mma(As[cur], Bs[cur], acc);
+      if ((kt + 1) % E::CHUNK == 0) acc.flush();
+      if (more) {
+        E::template stash<Cfg::BM>(As[cur ^ 1], la, ra, kt + 1);
+        if (!b_is_a) E::template stash<Cfg::BN>(Bs[cur ^ 1], lb, rb, kt + 1);
+      }
+      __syncthreads();
+    }
   }
   acc.flush();
 }
 
-template <class E, class Cfg, class LA, class LB>
+template <class E, class Cfg, int DEPTH = 1, class LA, class LB>
 __device__ __forceinline__ void gemm_mainloop(LA& la, LB& lb, int nk, typename E::template Acc<Cfg>& acc,
                                               char* smem_generic) {
-  gemm_mainloop_with<E, Cfg>(la, lb, nk, acc, smem_generic, false,
-                             [&](const lds_char* SA, const lds_char* SB, typename E::template Acc<Cfg>& c) {
-                               E::template mma<Cfg>(SA, SB, c, regular_plan<Cfg>());
-                             });
+  gemm_mainloop_with<E, Cfg, DEPTH>(la, lb, nk, acc, smem_generic, false,
+                                    [&](const lds_char* SA, const lds_char* SB, typename E::template Acc<Cfg>& c) {
+                                      E::template mma<Cfg>(SA, SB, c, regular_plan<Cfg>());
+                                    });
 }
 
 }  // namespace rif
