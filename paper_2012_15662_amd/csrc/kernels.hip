@@ -57,6 +57,8 @@ __device__ __forceinline__ void split_mode(double d0, double d1, unsigned (&pc)[
 }
 template <int P, int BX, int NT>
 using PCS = PieceSrc<kPieces<P> ? kPieces<P> : 1, BX, 32, NT>;
+template <int P, int BX, int NT>
+using PDMA = PieceDma<kPieces<P> ? kPieces<P> : 1, BX, NT>;
 // Which split-mode operands come from piece planes (measured): C_Omega in the
 // MO transform in both modes; C_Omega in the half transform and d in J^q only
 // with two pieces (with three, the 16-wave tiles spill under the 128-VGPR cap
@@ -157,34 +159,38 @@ __device__ void half_tile_with(const HalfArgs& a, long t, char* smem) {
   const int nb = a.nb, nw = a.nw;
   const long nr = a.nr, B2 = (long)nb * nb;
   IOT<P>* bh = (IOT<P>*)a.bh;
-  // A: C_Omega^T (x = q, k = mu), from piece planes in the split modes (in
-  // BF16x6 only when b is pre-split too: then neither operand is split here)
-  constexpr bool kAPlanes = kPlanesHalfJao<P> || (kBPre && kPieces<P> > 0);
-  typename std::conditional<kAPlanes, PCS<P, Cfg::BM, Cfg::NT>, XCS<P, double, Cfg::BM, Cfg::NT>>::type la;
-  if constexpr (kAPlanes)
-    la.init(a.Cs.p, a.Cs.ps, a.Cs.ld, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
-  else
-    la.init(a.C, a.nmo, nb, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
-  // B: column r = l*n_bf + nu of b[l][mu][nu] at k = mu: x-contiguous within a
-  // slab; pre-split: piece-plane row r (k = mu contiguous, b symmetric) or the
-  // FP32 copy at b's offsets
-  auto slab_off = [&](int x, long& o) {
-    const long r = r0 + x, l = r / nb;
-    o = l * B2 + (r - l * nb);
-    return r < nr;
-  };
-  using LB = typename std::conditional<
-      !kBPre, XCS<P, double, Cfg::BN, Cfg::NT>,
-      typename std::conditional<(kPieces<P> > 0), PCS<P, Cfg::BN, Cfg::NT>, XCS<P, float, Cfg::BN, Cfg::NT>>::type>::type;
-  LB lb;
-  if constexpr (!kBPre)
-    lb.init(a.b, nb, nb, slab_off);
-  else if constexpr (kPieces<P> > 0)
-    lb.init(a.Bs.p, a.Bs.ps, a.Bs.ld, [&](int x, long& o) { o = r0 + x; return r0 + x < nr; });
-  else
-    lb.init(a.bf, nb, nb, slab_off);
   typename E::template Acc<Cfg> acc;
-  gemm_mainloop<E, Cfg, kBPre ? kDeep<P> : 1>(la, lb, cdiv(nb, E::BK), acc, smem);
+  if constexpr (kBPre && kPieces<P> > 0) {
+    // A: C_Omega^T (x = q, k = mu) from its per-call piece planes; B: column
+    // r = l*n_bf + nu, piece-plane row r of the pre-split b (k = mu
+    // contiguous, b symmetric).  Both staged by direct global -> LDS loads.
+    PDMA<P, Cfg::BM, Cfg::NT> la;
+    la.init(a.Cs.p, a.Cs.ps, a.Cs.ld, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
+    PDMA<P, Cfg::BN, Cfg::NT> lb;
+    lb.init(a.Bs.p, a.Bs.ps, a.Bs.ld, [&](int x, long& o) { o = r0 + x; return r0 + x < nr; });
+    gemm_mainloop_dma<E, Cfg>(la, lb, cdiv(nb, E::BK), acc, smem);
+  } else {
+    // A: C_Omega^T (x = q, k = mu), from piece planes in the two-piece modes
+    typename std::conditional<kPlanesHalfJao<P>, PCS<P, Cfg::BM, Cfg::NT>, XCS<P, double, Cfg::BM, Cfg::NT>>::type la;
+    if constexpr (kPlanesHalfJao<P>)
+      la.init(a.Cs.p, a.Cs.ps, a.Cs.ld, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
+    else
+      la.init(a.C, a.nmo, nb, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
+    // B: column r = l*n_bf + nu of b[l][mu][nu] at k = mu: x-contiguous within
+    // a slab (FP64 b, or FP32 mode's pre-made float copy at b's offsets)
+    auto slab_off = [&](int x, long& o) {
+      const long r = r0 + x, l = r / nb;
+      o = l * B2 + (r - l * nb);
+      return r < nr;
+    };
+    using LB = typename std::conditional<kBPre, XCS<P, float, Cfg::BN, Cfg::NT>, XCS<P, double, Cfg::BN, Cfg::NT>>::type;
+    LB lb;
+    if constexpr (kBPre)
+      lb.init(a.bf, nb, nb, slab_off);
+    else
+      lb.init(a.b, nb, nb, slab_off);
+    gemm_mainloop<E, Cfg>(la, lb, cdiv(nb, E::BK), acc, smem);
+  }
   acc.for_each([&](int m, int n, double v) {
     const int q = q0 + m;
     const long r = r0 + n;
@@ -319,9 +325,9 @@ __device__ void jao_tile(const JaoArgs& a, long t, char* smem) {
 
 // The same J^q tile with b read as pre-split piece planes (split modes):
 // B element (x = (mu, nu) of the block, k = l) at plane row mu*n_bf + nu, and
-// d^T from its piece planes, so neither operand is split here.  The pieces are
-// the staging path's own split of the same values, so the results are bitwise
-// those of jao_tile.
+// d^T from its piece planes, so neither operand is split here; both are staged
+// by direct global -> LDS loads.  The pieces are the staging path's own split
+// of the same values, so the results are bitwise those of jao_tile.
 template <int P, class Cfg>
 __host__ __device__ inline long jaop_tiles(const JaoArgs& a) { return jao_tiles<P, Cfg>(a); }
 template <int P, class Cfg>
@@ -344,16 +350,17 @@ __device__ void jaop_tile(const JaoArgs& a, long t, char* smem) {
   const int mu0 = bi * TMU, nu0 = bj * TNU;
   const int q0 = qt * Cfg::BM;
   const long B2 = (long)nb * nb;
-  PCS<P, Cfg::BM, Cfg::NT> la;
+  static_assert(kPieces<P> > 0, "J^q from piece planes in the split modes only");
+  PDMA<P, Cfg::BM, Cfg::NT> la;
   la.init(a.Ds.p, a.Ds.ps, a.Ds.ld, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
-  PCS<P, Cfg::BN, Cfg::NT> lb;
+  PDMA<P, Cfg::BN, Cfg::NT> lb;
   lb.init(a.Bj.p, a.Bj.ps, a.Bj.ld, [&](int x, long& o) {
     const int mu = mu0 + x / TNU, nu = nu0 + x % TNU;
     o = (long)mu * nb + nu;
     return mu < nb && nu < nb;
   });
   typename E::template Acc<Cfg> acc;
-  gemm_mainloop<E, Cfg, kDeep<P>>(la, lb, cdiv(na, E::BK), acc, smem);
+  gemm_mainloop_dma<E, Cfg>(la, lb, cdiv(na, E::BK), acc, smem);
   IOT<P>* Jn = (IOT<P>*)a.Jn;
   acc.for_each([&](int m, int n, double v) {
     const int q = q0 + m, mu = mu0 + n / TNU, nu = nu0 + n % TNU;
@@ -1004,10 +1011,13 @@ constexpr int gemm_wpe() {
 #define GEMM_SMEM smem_bytes<typename EngineOf<P>::type, Cfg>()
 #define GEMM_WPE (gemm_wpe<P, Cfg>())
 RIF_STEP_KERNELS(half, HalfArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
-RIF_STEP_KERNELS(halfp, HalfArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
+// the pre-split half transform and J^q stage piece planes directly (split modes)
+#define GEMM_SMEM_DMA \
+  (kPieces<P> > 0 ? smem_bytes_dma<typename EngineOf<P>::type, Cfg>() : smem_bytes<typename EngineOf<P>::type, Cfg>())
+RIF_STEP_KERNELS(halfp, HalfArgs, GEMM_SMEM_DMA, Cfg::NT, false, GEMM_WPE)
 RIF_STEP_KERNELS(mo, MoArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
 RIF_STEP_KERNELS(jao, JaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE)
-RIF_STEP_KERNELS(jaop, JaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE)
+RIF_STEP_KERNELS(jaop, JaoArgs, GEMM_SMEM_DMA, Cfg::NT, true, GEMM_WPE)
 RIF_STEP_KERNELS(kao, KaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE)
 RIF_STEP_KERNELS(gemm, GemmArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
 RIF_STEP_KERNELS(fock, FockArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)

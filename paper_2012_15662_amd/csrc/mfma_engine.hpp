@@ -503,6 +503,54 @@ struct PieceSrc {
       for (int s = 0; s < NPC; ++s) r[p * NPC + s] = *(const u32x2*)(rp[p] + s * pstride + kt * BK);
   }
 };
+// Operand already split into NPC piece planes (layout as for PieceSrc),
+// staged by direct global -> LDS loads (global_load_lds_dwordx4): a lane moves
+// one 16-byte chunk (8 k of one row of one plane) to LDS at its wave's base
+// address + 16 * lane, so staging takes no registers.  The units of a stage
+// (NPC * BX rows * 4 chunks) are numbered in LDS order; thread u moves units
+// u, u + NT, ..., and unit (plane s, row x, slot c') holds chunk
+// c' ^ ((x / 4) % 4) of the row (the split engines' swizzle).  Rows beyond the
+// operand read row 0 instead; their products reach only output rows or
+// columns that are never stored, so they need no zeroing.
+template <int NPC_, int BX, int NT>
+struct PieceDma {
+  static constexpr int NPC = NPC_;
+  static constexpr int UNITS = NPC * BX * 4;
+  static constexpr int NU = (UNITS + NT - 1) / NT;
+  static_assert(UNITS % 64 == 0 && NT % 64 == 0, "whole waves");
+  const unsigned short* src[NU];
+  // row(x, o) sets o = the plane row of operand column x and returns whether it exists
+  template <class Row>
+  __device__ void init(const unsigned short* planes, long pstride, long ld, Row row) {
+#pragma unroll
+    for (int i = 0; i < NU; ++i) {
+      const int u = (int)threadIdx.x + i * NT;
+      const int uc = u < UNITS ? u : UNITS - 1;
+      const int sp = uc / (BX * 4), v = uc % (BX * 4), x = v / 4, c = (v % 4) ^ ((x >> 2) & 3);
+      long o = 0;
+      const bool ok = row(x, o);
+      src[i] = planes + sp * pstride + (ok ? o : 0) * ld + c * 8;
+    }
+  }
+  // loads this wave issues per slice (the same in every slice)
+  __device__ int count() const {
+    const int w0 = (int)(threadIdx.x & ~63u);
+    int n = 0;
+#pragma unroll
+    for (int i = 0; i < NU; ++i) n += w0 + i * NT < UNITS;
+    return n;
+  }
+  // slice kt (32 k) into the stage at S
+  __device__ void issue(int kt, lds_char* S) const {
+    const int w0 = (int)(threadIdx.x & ~63u);
+#pragma unroll
+    for (int i = 0; i < NU; ++i)
+      if (w0 + i * NT < UNITS)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src[i] + kt * 32),
+                                         (__attribute__((address_space(3))) void*)(S + (w0 + i * NT) * 16), 16, 0, 0);
+  }
+};
+
 template <class L, class = void>
 struct is_presplit : std::false_type {};
 template <class L>
@@ -765,6 +813,82 @@ __device__ __forceinline__ void gemm_mainloop(LA& la, LB& lb, int nk, typename E
                                     [&](const lds_char* SA, const lds_char* SB, typename E::template Acc<Cfg>& c) {
                                       E::template mma<Cfg>(SA, SB, c, regular_plan<Cfg>());
                                     });
+}
+
+// s_waitcnt vmcnt(n) for a wave-uniform n (0..31; larger n waits for 31),
+// other counters untouched.  vmcnt's six bits sit at [3:0] and [15:14].
+__device__ __forceinline__ void wait_vmcnt(int n) {
+#define RIF_VMCNT(k) __builtin_amdgcn_s_waitcnt(((k) & 15) | (7 << 4) | (15 << 8) | (((k) >> 4) << 14))
+#define RIF_VMCNT_CASE(k) case k: RIF_VMCNT(k); break;
+  switch (n) {
+    RIF_VMCNT_CASE(0) RIF_VMCNT_CASE(1) RIF_VMCNT_CASE(2) RIF_VMCNT_CASE(3) RIF_VMCNT_CASE(4)
+    RIF_VMCNT_CASE(5) RIF_VMCNT_CASE(6) RIF_VMCNT_CASE(7) RIF_VMCNT_CASE(8) RIF_VMCNT_CASE(9)
+    RIF_VMCNT_CASE(10) RIF_VMCNT_CASE(11) RIF_VMCNT_CASE(12) RIF_VMCNT_CASE(13) RIF_VMCNT_CASE(14)
+    RIF_VMCNT_CASE(15) RIF_VMCNT_CASE(16) RIF_VMCNT_CASE(17) RIF_VMCNT_CASE(18) RIF_VMCNT_CASE(19)
+    RIF_VMCNT_CASE(20) RIF_VMCNT_CASE(21) RIF_VMCNT_CASE(22) RIF_VMCNT_CASE(23) RIF_VMCNT_CASE(24)
+    RIF_VMCNT_CASE(25) RIF_VMCNT_CASE(26) RIF_VMCNT_CASE(27) RIF_VMCNT_CASE(28) RIF_VMCNT_CASE(29)
+    RIF_VMCNT_CASE(30)
+    default: RIF_VMCNT(31); break;
+  }
+#undef RIF_VMCNT_CASE
+#undef RIF_VMCNT
+}
+
+// Stages that fit in LDS for the direct-load main loop (at most 4).
+template <class E, class Cfg>
+constexpr int dma_stages() {
+  constexpr int st = E::template stage_bytes<Cfg::BM>() + E::template stage_bytes<Cfg::BN>();
+  return 163840 / st >= 4 ? 4 : 163840 / st;
+}
+template <class E, class Cfg>
+constexpr int smem_bytes_dma() {
+  return dma_stages<E, Cfg>() * (E::template stage_bytes<Cfg::BM>() + E::template stage_bytes<Cfg::BN>());
+}
+
+// Main loop for two PieceDma operands: S = dma_stages() LDS stages, S-1
+// slices of loads in flight.  Per slice kt: wait for this wave's loads of
+// slice kt (the loads of the S-2 later slices stay in flight), a plain
+// s_barrier (so every wave's loads of slice kt have landed and every wave is
+// done reading the stage about to be refilled), the loads of slice kt+S-1
+// into that stage, then the MFMAs of slice kt.  The barrier carries no
+// memory fence: a fence would wait for every load in flight.  Past the last
+// slice the loads re-read slice nk-1 into a stage nobody reads, which keeps
+// the count of loads per slice fixed for the waits.
+template <class E, class Cfg, class LA, class LB>
+__device__ __forceinline__ void gemm_mainloop_dma(const LA& la, const LB& lb, int nk,
+                                                  typename E::template Acc<Cfg>& acc, char* smem_generic) {
+  constexpr int S = dma_stages<E, Cfg>();
+  static_assert(S >= 2, "two stages at least");
+  constexpr int SA = E::template stage_bytes<Cfg::BM>();
+  constexpr int ST = SA + E::template stage_bytes<Cfg::BN>();
+  lds_char* smem = (lds_char*)smem_generic;
+  acc.zero();
+  if (nk <= 0) return;
+  const int per_slice = la.count() + lb.count();
+#pragma unroll
+  for (int j = 0; j < S - 1; ++j) {
+    const int k = j < nk ? j : nk - 1;
+    la.issue(k, smem + j * ST);
+    lb.issue(k, smem + j * ST + SA);
+  }
+  for (int kt = 0; kt < nk; ++kt) {
+    wait_vmcnt((S - 2) * per_slice);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    const int kf = kt + S - 1 < nk ? kt + S - 1 : nk - 1;
+    lds_char* sf = smem + ((kt + S - 1) % S) * ST;
+    la.issue(kf, sf);
+    lb.issue(kf, sf + SA);
+    const lds_char* sc = smem + (kt % S) * ST;
+    E::template mma<Cfg>(sc, sc + SA, acc, regular_plan<Cfg>());
+    if ((kt + 1) % E::CHUNK == 0) acc.flush();
+  }
+  acc.flush();
+  // no load may still write LDS when the workgroup moves on
+  wait_vmcnt(0);
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
 }
 
 }  // namespace rif

@@ -54,6 +54,43 @@ def test_build_with_presplit_b_is_bitwise_equal(ctx, mode, prec, shape):
         assert np.array_equal(host(da[k]), host(db[k])), k
 
 
+@pytest.mark.parametrize("mode,prec", [("bf16x3", 2), ("bf16x6", 3), ("fp16x3", 4)])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_presplit_every_tile_variant(ctx, mode, prec, variant):
+    """Each tile shape of the kernels that stage piece planes straight into
+    LDS (half transform, J^q), against the same build splitting b on load."""
+    inst = synth.make_instance(130, 259, 7, 3, 14 + variant)
+    print("case presplit variant", mode, variant, flush=True)
+    t = to_dev(inst)
+    bs = ctx.presplit_b(t["b"], prec)
+    ctx.set_tile_variant(variant)
+    try:
+        a = ctx.build(t["b"], t["C"], t["H"], t["occ"], t["pair_of"], inst.n_pairs, inst.n_cwo, prec=prec)
+        b = ctx.build(t["b"], t["C"], t["H"], t["occ"], t["pair_of"], inst.n_pairs, inst.n_cwo, prec=prec,
+                      b_split=bs)
+        ctx.sync()
+    finally:
+        ctx.set_tile_variant(-1)
+    for k in ("b_half", "Jn", "Kn", "energy", "lam", "grad"):
+        assert np.array_equal(host(a[k]), host(b[k])), k
+
+
+@pytest.mark.parametrize("mode,prec", [("bf16x6", 3), ("fp16x3", 4)])
+def test_presplit_bitwise_at_cyclohexane_size(ctx, mode, prec):
+    """The launch shapes the bench times; their ragged last tiles stage
+    operand rows past the end, which may reach only discarded outputs."""
+    inst = synth.workload("c6h12")
+    print("case presplit cyclohexane-like", mode, flush=True)
+    t = to_dev(inst)
+    bs = ctx.presplit_b(t["b"], prec)
+    a = ctx.build(t["b"], t["C"], t["H"], t["occ"], t["pair_of"], inst.n_pairs, inst.n_cwo, prec=prec)
+    b = ctx.build(t["b"], t["C"], t["H"], t["occ"], t["pair_of"], inst.n_pairs, inst.n_cwo, prec=prec, b_split=bs)
+    ctx.sync()
+    for k in ("b_half", "Jn", "Kn", "energy", "lam", "grad"):
+        assert np.array_equal(host(a[k]), host(b[k])), k
+    del bs, a, b
+
+
 @pytest.mark.parametrize("mode,prec,npc", [("bf16x3", 2, 2), ("bf16x6", 3, 3)])
 def test_piece_planes_sum_to_b(ctx, mode, prec, npc):
     inst = synth.make_instance(37, 20, 2, 1, 5)
