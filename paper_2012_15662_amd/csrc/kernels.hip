@@ -1034,7 +1034,8 @@ RIF_STEP_KERNELS(bsplit, BSplitArgs, 16, 256, false, 1)
 
 // ---------------------------------------------------------------------------
 // Launchers.  Each GEMM-shaped step exists in four tile variants per mode:
-//   0: 128x128   1: 64x64   2: 128x64   3: 64x128   (outputs per workgroup)
+//   0: 128x128   1: 64x64   2: 128x64   3: 64x128 (FP64/FP32) or a second
+//   128x128 wave layout (split engines)   (outputs per workgroup)
 // pick_variant() chooses one per (step, mode, shape): a wave-quantisation
 // model by default, or the fastest measured one when autotuning is on.
 
@@ -1045,11 +1046,14 @@ template <> struct Vars<16> {  // FP64 / FP32 engines: 8 waves (measured ~10% ov
   using V2 = TileCfg<128, 64, 16, 32, 32>;
   using V3 = TileCfg<64, 128, 16, 32, 32>;
 };
-template <> struct Vars<32> {  // BF16 split engines: 16-wave 128x128 (four waves per SIMD), then 8/4-wave tiles
+// Split engines: 128x128 as 16 waves of 32x32 (four waves per SIMD) or 8 waves
+// of 64x32 (fewer fragment reads from LDS per MFMA, two waves per SIMD), then
+// the 4-wave 64x64 and 128x64 tiles.
+template <> struct Vars<32> {
   using V0 = TileCfg<128, 128, 32, 32, 32>;
   using V1 = TileCfg<64, 64, 32, 32, 32>;
   using V2 = TileCfg<128, 64, 32, 64, 32>;
-  using V3 = TileCfg<64, 128, 32, 32, 64>;
+  using V3 = TileCfg<128, 128, 32, 64, 32>;
 };
 struct Cfg256 { static constexpr int NT = 256; };  // element-wise steps
 struct CfgEnergy { static constexpr int NT = kEnergyThreads; };
