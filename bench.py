@@ -37,7 +37,7 @@ HBM_GBS = 8000.0
 # were taken on: a figure is reported only while those sources are unchanged.
 # The runs and their command lines are in profiles/.
 TRAFFIC = {
-    ("half_transform", "c6h12", "fp64"): {"src": "ed77525bf763e85e", "fetch": 1174070307, "write": 348779520,
+    ("half_transform", "c6h12", "fp64"): {"src": "e59d0958d4665b7b", "fetch": 1174012408, "write": 348779520,
                                          "profile": "profiles/fp64_c6h12_counters.md"},
 }
 
@@ -59,9 +59,12 @@ def traffic_of(kernel, workload, prec):
 
 
 def kernel_flops(nb, na, nw, nmo):
-    """Algorithmic flops per launch of each kernel (symmetric outputs counted once)."""
+    """Algorithmic flops per launch of each kernel (symmetric outputs counted once);
+    the pre-split kernels (b stored pre-split) do the same arithmetic."""
     return {
         "half_transform": 2.0 * na * nb * nb * nw,
+        "half_transform_presplit": 2.0 * na * nb * nb * nw,
+        "jao_presplit": 1.0 * na * nw * nb * (nb + 1),
         "mo_transform": 2.0 * na * nb * nw * nw,
         "jk_mo_partial": 4.0 * na * nw * nw,
         "jao": 1.0 * na * nw * nb * (nb + 1),
@@ -669,6 +672,8 @@ def main():
     ap.add_argument("--calib", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM counters)")
     ap.add_argument("--no-modes", action="store_true", help="skip timing the other precision modes")
+    ap.add_argument("--presplit", action="store_true",
+                    help="with a reduced-precision --prec: b stored pre-split (rif_presplit_b) in the timed builds")
     ap.add_argument("--no-direct", action="store_true", help="skip timing rif_build_direct")
     ap.add_argument("--no-4c", action="store_true", help="skip the RI vs four-centre comparison")
     ap.add_argument("--no-c10h20", action="store_true",
@@ -717,16 +722,19 @@ def main():
         del src, dst
     ctx = rif.Context(0)
     ctx.autotune(not args.no_tune)
+    if args.presplit and args.prec == "fp64":
+        raise SystemExit("--presplit needs a reduced-precision --prec")
+    bsp = ctx.presplit_b(b, MODES[args.prec]) if args.presplit else None
     # per-kernel breakdown from its own untimed pass: event pairs around every
     # launch cost about 4% of a build, so the timed loop records only the
     # dominant kernel's launches, whose average the roofline uses
     n_prof = max(5, min(args.steps, 30))
     _, _, prof = time_builds(ctx, b, Cd, H, occ, pm, inst, MODES[args.prec], n_prof, args.warmup,
-                             profile=True)
+                             profile=True, b_split=bsp)
     dom = max(prof, key=lambda k: prof[k][1])
     el, out, prof_dom = time_builds(ctx, b, Cd, H, occ, pm, inst, MODES[args.prec], args.steps, 1,
-                                    profile=dom)
-    ref_out = ctx.build(b, Cd[0], H, occ, pm, inst.n_pairs, inst.n_cwo, prec=MODES[args.prec])
+                                    profile=dom, b_split=bsp)
+    ref_out = ctx.build(b, Cd[0], H, occ, pm, inst.n_pairs, inst.n_cwo, prec=MODES[args.prec], b_split=bsp)
     ctx.sync()
     e_main = float(ref_out["energy"].cpu()[0])   # energy at the unrotated C
 
@@ -758,7 +766,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: n_bf={nb} n_aux={na} pairs={inst.n_pairs} "
                                f"ncwo={inst.n_cwo} n_omega={nw} n_mo={nmo}, 30 rotated C",
-                   "precision": args.prec},
+                   "precision": args.prec, **({"b_presplit": True} if args.presplit else {})},
         "tflops": round(flops * builds_s / 1e12, 3),
         "flops_per_build": flops,
         "roofline": {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 3),
