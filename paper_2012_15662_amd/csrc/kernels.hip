@@ -123,10 +123,6 @@ struct CoefArgs {
   const int* pair_of;
   const double *occ, *J, *K;
   double *Ac, *Bc, *Ep;
-  long nhc;              // also: HC = sum of the hc_split partials HCp (nhc elements each)
-  int hc_split;
-  const double* HCp;
-  double* HC;
 };
 struct EnergyArgs {
   int nw, npairs, ncwo, nb, nmo, nparts;
@@ -840,15 +836,6 @@ __device__ void coef_tile(const CoefArgs& a, long t, char* smem) {
     __syncthreads();
   }
   if (tid == 0) a.Ep[t] = red[0];
-  __syncthreads();
-  // HC = sum of the k-split partials of H C_Omega (fixed order), spread over
-  // this step's threads
-  const long nthr = coef_tiles<P, Cfg>(a) * 256;
-  for (long i = t * 256 + tid; i < a.nhc; i += nthr) {
-    double v = 0.0;
-    for (int s = 0; s < a.hc_split; ++s) v += a.HCp[s * a.nhc + i];
-    a.HC[i] = v;
-  }
 }
 
 // H_pp = c_p^T H c_p, the energy (coefficient partials + 2 sum n_p H_pp, fixed
@@ -1255,9 +1242,9 @@ static rif_status step1_jk(rif_ctx* c, const JkArgs& a) {
 // ---- workspace plan of one molecule (shared by the single and batched paths)
 struct Plan {
   int nb, na, nw, nmo, npairs, ncwo;
-  int jk_nsplit, fock_nsplit, nparts, hc_split, lam_split, small_kc, yd_nsplit;
+  int jk_nsplit, fock_nsplit, nparts, lam_split, small_kc, yd_nsplit;
   long yd_kc;
-  size_t o_part, o_hcp, o_hc, o_a, o_b, o_yp, o_y, o_ep, o_lp, o_cs, o_ds, bytes;
+  size_t o_part, o_hc, o_a, o_b, o_yp, o_y, o_ep, o_lp, o_cs, o_ds, bytes;
   size_t o_ydp, o_zt, o_bt, bytes_direct;   // the gradient without per-MO AO matrices
   Plan(int nb_, int na_, int npairs_, int ncwo_, int nmo_) {
     nb = nb_; na = na_; npairs = npairs_; ncwo = ncwo_; nmo = nmo_;
@@ -1273,18 +1260,19 @@ struct Plan {
     const long smax = 2L * nw * cdiv(nb, 32);
     fock_nsplit = (int)std::max(1L, std::min(smax, 512L / t128));
     nparts = (int)nx;
-    // the two small GEMMs (n_bf x n_omega outputs, k = n_bf): k split so a
-    // launch has about 256 tiles of 64x64, at least two 16-deep slices each
+    // lambda = C^T Y (n_mo x n_omega, k = n_bf) sits on the main chain: k split
+    // so its launch has about 256 tiles of 64x64, at least two 16-deep slices
+    // each.  H C_Omega runs on the side stream, in the shadow of the half
+    // transform, and writes HC in one piece (no partials to add up later).
     {
       const long tiles = cdiv(nb, 64) * cdiv(nw, 64);
       const int slices = cdiv(nb, 16);
       const int want = (int)std::max(1L, std::min((long)std::max(1, slices / 2), (long)cdiv(256, tiles)));
       small_kc = 16 * cdiv(slices, want);
-      hc_split = lam_split = cdiv(nb, small_kc);
+      lam_split = cdiv(nb, small_kc);
     }
     Carve cv;
     o_part = cv.take<double>(2L * jk_nsplit * w2);
-    o_hcp = cv.take<double>((size_t)hc_split * nb * nw);
     o_hc = cv.take<double>((size_t)nb * nw);
     o_a = cv.take<double>((size_t)w2);
     o_b = cv.take<double>((size_t)w2);
@@ -1325,7 +1313,6 @@ static BuildArgs make_build_args(const Plan& pl, const rif_instance& in, int pre
   BuildArgs A;
   const int nb = pl.nb, na = pl.na, nw = pl.nw, nmo = pl.nmo;
   double* part = (double*)(ws + pl.o_part);
-  double* HCp = (double*)(ws + pl.o_hcp);
   double* HC = (double*)(ws + pl.o_hc);
   double* Ac = (double*)(ws + pl.o_a);
   double* Bc = (double*)(ws + pl.o_b);
@@ -1356,10 +1343,8 @@ static BuildArgs make_build_args(const Plan& pl, const rif_instance& in, int pre
     A.jao.Bj = Planes{j0, (long)nb * nb * lj, lj};
   }
   A.kao = KaoArgs{nb, na, nw, in.b_half, in.Kn};
-  A.hc = GemmArgs{nb, nw, nb, in.H, (long)nb, in.C, (long)nmo, HCp, (long)nw,
-                  pl.hc_split, pl.small_kc, (long)nb * nw};
-  A.coef = CoefArgs{functional, nw, pl.npairs, pl.ncwo, in.pair_of, in.occ, in.J, in.K, Ac, Bc, Ep,
-                    (long)nb * nw, pl.hc_split, HCp, HC};
+  A.hc = GemmArgs{nb, nw, nb, in.H, (long)nb, in.C, (long)nmo, HC, (long)nw, 1, nb, (long)nb * nw};
+  A.coef = CoefArgs{functional, nw, pl.npairs, pl.ncwo, in.pair_of, in.occ, in.J, in.K, Ac, Bc, Ep};
   A.energy = EnergyArgs{nw, pl.npairs, pl.ncwo, nb, nmo, pl.nparts, in.pair_of, in.occ, in.C, HC, Ep, in.energy,
                         flag};
   A.fock = FockArgs{nb, nw, nmo, pl.fock_nsplit, in.Jn, in.Kn, Ac, Bc, in.C, Yp};
