@@ -40,7 +40,16 @@ extern "C" {
 
 typedef struct rif_ctx rif_ctx;
 
-typedef enum {
+/* Under C++ the enums below take int as their underlying type, so every int
+ * a caller passes (from C, or through a foreign-function layer) is a valid
+ * value of the type; the calls reject the values they do not know. */
+#ifdef __cplusplus
+#define RIF_ENUM enum : int
+#else
+#define RIF_ENUM enum
+#endif
+
+typedef RIF_ENUM {
   RIF_OK = 0,
   RIF_EINVAL = -1,  /* bad shape, NULL pointer, invalid occupations */
   RIF_ENOMEM = -2,  /* workspace allocation failed or exceeds the cap */
@@ -48,7 +57,7 @@ typedef enum {
   RIF_ENOTSUP = -4  /* precision or feature not available */
 } rif_status;
 
-typedef enum {
+typedef RIF_ENUM {
   RIF_FP64 = 0,
   RIF_FP32 = 1,
   RIF_BF16X3 = 2,   /* two bf16 pieces, three products */
@@ -60,7 +69,7 @@ typedef enum {
                        finite. */
 } rif_prec;
 
-typedef enum { RIF_PNOF7 = 0, RIF_PNOF5 = 1 } rif_functional;
+typedef RIF_ENUM { RIF_PNOF7 = 0, RIF_PNOF5 = 1 } rif_functional;
 
 /* Create a context on HIP device `hip_device`.  `hip_stream` is a hipStream_t
  * to launch on (e.g. the caller's current stream); NULL makes the context
@@ -388,7 +397,7 @@ rif_status rif_orbital_step(rif_ctx *ctx, int n_bf, int n_mo, int n_omega, const
  * each, at least 16 workgroups, more where the rows do not fit).  Results of the two solvers agree to rounding,
  * eigenvectors up to sign.  RIF_EINVAL for an unknown kind or groups outside
  * [0, 4096]. */
-typedef enum { RIF_EIG_AUTO = 0, RIF_EIG_SYEVD = 1, RIF_EIG_TRD = 2 } rif_eigensolver;
+typedef RIF_ENUM { RIF_EIG_AUTO = 0, RIF_EIG_SYEVD = 1, RIF_EIG_TRD = 2 } rif_eigensolver;
 rif_status rif_set_eigensolver(rif_ctx *ctx, int kind, int groups);
 
 /* Bound on the waits inside the one-launch kernels (the tridiagonal reduction

@@ -267,7 +267,7 @@ rif_status pnof_energy_grad(rif_ctx* c, rif_functional fn, int nb, int nmo, int 
 
 static rif_status check_instance(rif_ctx* c, const rif_instance* in, const char* who, bool need_ao = true) {
   if (!in) return fail(c, RIF_EINVAL, std::string(who) + ": NULL instance");
-  const long nw = (long)in->n_pairs * (1 + in->n_cwo);
+  const long nw = (long)in->n_pairs * (1 + (long)in->n_cwo);   // no int overflow for any inputs
   if (!dims_ok(in->n_bf) || !dims_ok(in->n_aux) || !dims_ok(in->n_mo) || !dims_ok(in->n_pairs) || in->n_cwo < 1 ||
       nw > in->n_mo || in->n_mo > in->n_bf)
     return fail(c, RIF_EINVAL, std::string(who) + ": need n_pairs (1 + n_cwo) <= n_mo <= n_bf, n_aux > 0");
@@ -362,7 +362,7 @@ rif_status rif_build_direct(rif_ctx* c, const rif_instance* in, rif_prec prec, r
   if (!c) return RIF_EINVAL;
   rif_status st = check_instance(c, in, "rif_build_direct", false);
   if (st) return st;
-  if ((long)in->n_aux * in->n_pairs * (1 + in->n_cwo) >= (1L << 31))
+  if ((long)in->n_aux * in->n_pairs * (1 + (long)in->n_cwo) >= (1L << 31))
     return fail(c, RIF_EINVAL, "rif_build_direct: need n_aux * n_omega < 2^31");
   if (fn != RIF_PNOF7 && fn != RIF_PNOF5) return fail(c, RIF_EINVAL, "rif_build_direct: unknown functional");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, RIF_EHIP, "hipSetDevice failed");
@@ -455,7 +455,7 @@ static rif_status check_on(rif_ctx* c, int n, const rif_on_problem* p, bool need
   if (n <= 0 || !p) return fail(c, RIF_EINVAL, std::string(who) + ": need n_prob > 0 and a problem array");
   for (int i = 0; i < n; ++i) {
     const rif_on_problem& q = p[i];
-    if (q.n_pairs <= 0 || q.n_cwo < 1 || q.n_cwo > 14 || q.n_omega != q.n_pairs * (1 + q.n_cwo) || q.row0 < 0)
+    if (q.n_pairs <= 0 || q.n_cwo < 1 || q.n_cwo > 14 || q.n_omega != (long)q.n_pairs * (1 + q.n_cwo) || q.row0 < 0)
       return fail(c, RIF_EINVAL, std::string(who) + ": need n_omega = n_pairs (1 + n_cwo), 1 <= n_cwo <= 14");
     if (q.functional != RIF_PNOF7 && q.functional != RIF_PNOF5)
       return fail(c, RIF_EINVAL, std::string(who) + ": unknown functional");
