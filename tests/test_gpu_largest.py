@@ -10,7 +10,8 @@ Jn, Kn, lambda and G is compared, and so is the energy: FP64 to 1e-10 relative
 (normwise for arrays). The direct gradient is held to the same bound. The
 reduced-precision modes are compared on the energy and gradient only:
 1 uEh and 1e-6 normwise for FP32 and BF16x6, 5 uEh and 1e-6 for FP16x3 (2.0 uEh
-here), 1e-4 for BF16x3.
+here), 1e-4 for BF16x3.  Builds that read b stored pre-split (FP16x3, BF16x6)
+must equal the ones that split b on load, bitwise.
 """
 import time
 
@@ -103,3 +104,20 @@ def test_documented_miss(case, mode, prec, bound_e, bound_g):
     e, _ = build_errors(c, t, npair, ncwo, ref, prec, keys=("J", "K", "grad"))
     print(mode, "largest (documented miss)", " ".join(f"{k}={v:.2e}" for k, v in e.items()), flush=True)
     assert e["dE"] < bound_e and e["grad"] < bound_g
+
+
+@pytest.mark.parametrize("mode,prec", [("fp16x3", 4), ("bf16x6", 3)])
+def test_presplit_bitwise_at_largest_size(case, mode, prec):
+    """b stored pre-split (24 or 36 GB of piece planes here, rows of 3e6 and
+    1e6 with 64-bit offsets) gives bitwise the build that splits b on load."""
+    import torch
+    c, t, npair, ncwo, ref = case
+    bs = c.presplit_b(t["b"], prec)
+    a = c.build(t["b"], t["C"], t["H"], t["occ"], t["pair_of"], npair, ncwo, prec=prec)
+    b = c.build(t["b"], t["C"], t["H"], t["occ"], t["pair_of"], npair, ncwo, prec=prec, b_split=bs)
+    c.sync()
+    for k in ("b_half", "Jn", "Kn", "energy", "lam", "grad"):
+        assert torch.equal(a[k], b[k]), k
+    print(mode, "largest: pre-split build bitwise equal", flush=True)
+    del bs, a, b
+    torch.cuda.empty_cache()
