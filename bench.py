@@ -506,6 +506,10 @@ def bench_onwarm(args):
     print(json.dumps(line))
 
 
+EIG_NAMES = {0: "auto (reduction + divide and conquer)", 1: "rocSOLVER dsyevd",
+             2: "reduction + rocSOLVER dstedc", 3: "reduction + divide and conquer"}
+
+
 def bench_orbopt(args):
     """Orbital optimisation by iterative diagonalisation of F^lambda (the inner
     iterations of Fig. 1) on the cyclohexane-like workload: one ON step, then
@@ -521,6 +525,7 @@ def bench_orbopt(args):
     ctx = rif.Context(0)
     if not args.no_tune:
         ctx.autotune(True)
+    ctx.set_eigensolver(args.eig)
 
     def upload(inst):
         d = {k: torch.from_numpy(np.ascontiguousarray(getattr(inst, k))).cuda() for k in ("b", "C", "H", "occ")}
@@ -574,7 +579,8 @@ def bench_orbopt(args):
         "warmup": 3, "ms_per_step": round(per_ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"orbopt: {args.orb_size} n_bf={inst.n_bf} n_aux={inst.n_aux} pairs={inst.n_pairs} "
-                               f"ncwo={inst.n_cwo} n_mo={inst.n_mo}, fixed ONs after one ON step"},
+                               f"ncwo={inst.n_cwo} n_mo={inst.n_mo}, fixed ONs after one ON step",
+                   "eigensolver": EIG_NAMES[args.eig]},
         "split_ms": {"build_with_maxG": round(res["ms_build"] / n, 4),
                      "orbital_step": round(res["ms_orbital"] / max(1, n - 1), 4),
                      "on_step_once": round(res["ms_on"], 3)},
@@ -678,6 +684,9 @@ def main():
     ap.add_argument("--no-4c", action="store_true", help="skip the RI vs four-centre comparison")
     ap.add_argument("--no-c10h20", action="store_true",
                     help="skip the precision study at the cyclodecane-like size")
+    ap.add_argument("--eig", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="orbopt eigensolver: 0 automatic (3 where it fits), 1 rocSOLVER dsyevd, "
+                         "2 one-launch reduction + rocSOLVER dstedc, 3 one-launch reduction + own divide and conquer")
     ap.add_argument("--orb-size", default="c6h12", choices=["tiny", "c6h12", "c10h20"],
                     help="orbopt: the molecule whose inner iterations are run")
     ap.add_argument("--no-small", action="store_true",

@@ -371,8 +371,10 @@ rif_status rif_prepare_b(rif_ctx *ctx, int n_bf, int n_aux, const double *T, con
  *   eps_in  [n_mo] diagonal of F^lambda, or NULL for lambda_pp
  *   C       [n_bf][n_mo] in/out: replaced by C V, V the eigenvectors
  *   eps_out [n_mo] eigenvalues, ascending (may be eps_in)
- *   info    device int or NULL: 0; > 0 rocSOLVER's failure count; -1 a
- *           timed-out wait of the one-launch reduction (rif_set_wait_limit)
+ *   info    device int or NULL: 0; > 0 the tridiagonal eigensolver did not
+ *           converge (rocSOLVER's failure count, or 1 from the library's own
+ *           divide and conquer); -1 a timed-out wait of the one-launch
+ *           reduction (rif_set_wait_limit)
  * The eigen-decomposition runs on the context's stream with its workspace in
  * the context arena (solver chosen by rif_set_eigensolver); the rotation is an
  * FP64 MFMA GEMM.  info = -1 reports a timed-out wait inside the tridiagonal
@@ -382,22 +384,27 @@ rif_status rif_orbital_step(rif_ctx *ctx, int n_bf, int n_mo, int n_omega, const
                             const double *eps_in, double *C, double *eps_out, int *info);
 
 /* Eigensolver of the orbital step (and of rif_pnof_optimize), per context:
- *   RIF_EIG_TRD    Householder reduction to tridiagonal form T = Q^T F Q in ONE
+ *   RIF_EIG_DC     Householder reduction to tridiagonal form T = Q^T F Q in ONE
  *                  cooperative launch (rows of F and of Q held in LDS across
  *                  `groups` workgroups, which exchange v and p of each column
- *                  through polled single-write slots), then rocSOLVER dstedc
- *                  (divide and conquer on T) and C <- (C Q) Z as two FP64 MFMA
- *                  GEMMs.  Needs the rows of F and Q to fit 150 KB of LDS per
+ *                  through polled single-write slots), then the library's own
+ *                  divide and conquer on T (Cuppen's tearing down to leaves of
+ *                  at most 32 rows solved by implicit QR, rank-one merges with
+ *                  the secular roots found by bisection and Gu and Eisenstat's
+ *                  recomputed update vector, each merge's eigenvector product
+ *                  an FP64 MFMA GEMM), and C <- (C Q) Z as two FP64 MFMA GEMMs.
+ *                  Needs the rows of F and Q to fit 150 KB of LDS per
  *                  workgroup with at most 256 workgroups, one per CU (n_mo up
  *                  to about 1200); the orbital step returns RIF_ENOTSUP
  *                  otherwise.
+ *   RIF_EIG_TRD    the same reduction, then rocSOLVER dstedc on T.
  *   RIF_EIG_SYEVD  rocSOLVER dsyevd (its own blocked reduction).
- *   RIF_EIG_AUTO   TRD where it fits, else SYEVD (the default).
+ *   RIF_EIG_AUTO   DC where it fits, else SYEVD (the default).
  * groups: workgroups of the reduction, 0 for the default (about three rows
- * each, at least 16 workgroups, more where the rows do not fit).  Results of the two solvers agree to rounding,
+ * each, at least 16 workgroups, more where the rows do not fit).  Results of the solvers agree to rounding,
  * eigenvectors up to sign.  RIF_EINVAL for an unknown kind or groups outside
  * [0, 4096]. */
-typedef RIF_ENUM { RIF_EIG_AUTO = 0, RIF_EIG_SYEVD = 1, RIF_EIG_TRD = 2 } rif_eigensolver;
+typedef RIF_ENUM { RIF_EIG_AUTO = 0, RIF_EIG_SYEVD = 1, RIF_EIG_TRD = 2, RIF_EIG_DC = 3 } rif_eigensolver;
 rif_status rif_set_eigensolver(rif_ctx *ctx, int kind, int groups);
 
 /* Bound on the waits inside the one-launch kernels (the tridiagonal reduction

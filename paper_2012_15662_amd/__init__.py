@@ -19,7 +19,7 @@ import weakref
 
 __all__ = [
     "Context", "Batch", "Instance", "OnProblem", "OnSet", "OptParams", "OptResult", "RifError", "load_library", "LIB_PATH", "FP64", "FP32", "BF16X3", "BF16X6",
-    "FP16X3", "PNOF7", "PNOF5", "EIG_AUTO", "EIG_SYEVD", "EIG_TRD", "EXPORTS",
+    "FP16X3", "PNOF7", "PNOF5", "EIG_AUTO", "EIG_SYEVD", "EIG_TRD", "EIG_DC", "EXPORTS",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(HERE, "librif.so")
 
 FP64, FP32, BF16X3, BF16X6, FP16X3 = 0, 1, 2, 3, 4
 PNOF7, PNOF5 = 0, 1
-EIG_AUTO, EIG_SYEVD, EIG_TRD = 0, 1, 2
+EIG_AUTO, EIG_SYEVD, EIG_TRD, EIG_DC = 0, 1, 2, 3
 _STATUS = {0: "RIF_OK", -1: "RIF_EINVAL", -2: "RIF_ENOMEM", -3: "RIF_EHIP", -4: "RIF_ENOTSUP"}
 
 _vp, _i, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
@@ -496,8 +496,10 @@ class Context:
         self._chk(self.lib.rif_set_wait_limit(self.h, int(polls)))
 
     def set_eigensolver(self, kind=EIG_AUTO, groups=0):
-        """rif_set_eigensolver: EIG_TRD (one-launch tridiagonal reduction, then
-        rocSOLVER dstedc/dormtr), EIG_SYEVD (rocSOLVER dsyevd) or EIG_AUTO."""
+        """rif_set_eigensolver: EIG_DC (one-launch tridiagonal reduction, then the
+        library's divide and conquer), EIG_TRD (the same reduction, then
+        rocSOLVER dstedc), EIG_SYEVD (rocSOLVER dsyevd) or EIG_AUTO (DC where
+        it fits, else SYEVD)."""
         self._chk(self.lib.rif_set_eigensolver(self.h, int(kind), int(groups)))
 
     def orbital_step(self, lam, C, n_omega, eps_in=None, eps_out=None, info=None):

@@ -5,9 +5,9 @@
 //   k_maxabs     max |x| over an array, NaN counted as +inf (two passes)
 //   op_orbital_step   F^lambda -> eigenvectors -> C <- C V.  Eigensolver: the
 //                     one-launch tridiagonal reduction forming Q (eig.hip),
-//                     rocSOLVER dstedc (divide and conquer on T), and
-//                     C <- (C Q) Z as two GEMMs; or rocSOLVER dsyevd throughout
-//                     (rif_set_eigensolver)
+//                     divide and conquer on T (tdc.hip, or rocSOLVER dstedc),
+//                     and C <- (C Q) Z as two GEMMs; or rocSOLVER dsyevd
+//                     throughout (rif_set_eigensolver)
 //   op_optimize       ON optimisation at fixed orbitals, then inner iterations
 //                     (build -> max|G| -> orbital step) at fixed ONs, repeated;
 //                     the builds skip J^q/K^q when no Jn/Kn buffers are given
@@ -123,31 +123,71 @@ rif_status op_maxabs(rif_ctx* c, long n, const double* x, double* part, double* 
 __global__ void k_trd_info(const int* err, int* info) {
   if (threadIdx.x == 0 && *err != 0) *info = -1;
 }
+// own divide and conquer: -1 for a timed-out wait of the reduction, 1 for a
+// leaf that did not converge, else 0
+__global__ void k_tdc_info(const int* err_trd, const int* err_dc, int* info) {
+  if (threadIdx.x == 0) *info = *err_trd != 0 ? -1 : (*err_dc != 0 ? 1 : 0);
+}
 
 rif_status op_orbital_step(rif_ctx* c, int nb, int nmo, int nw, const double* lam, const double* eps_in,
                            double* C, double* eps_out, int* info) {
-  rocblas_handle h;
-  rif_status st = blas_handle(c, &h);
-  if (st) return st;
   const int n = nmo;
-  // eigensolver: own tridiagonal reduction (forming Q) + rocSOLVER dstedc, or dsyevd
-  const int G = c->eig_kind == RIF_EIG_SYEVD ? 0 : trd_groups(c, n, c->eig_groups);
-  if (c->eig_kind == RIF_EIG_TRD && G == 0)
+  // eigensolver: own tridiagonal reduction (forming Q), then own divide and
+  // conquer (AUTO, DC) or rocSOLVER dstedc (TRD); or rocSOLVER dsyevd
+  const int kind = c->eig_kind;
+  const int G = kind == RIF_EIG_SYEVD || n > tdc_max_n() ? 0 : trd_groups(c, n, c->eig_groups);
+  if ((kind == RIF_EIG_TRD || kind == RIF_EIG_DC) && G == 0)
     return fail(c, RIF_ENOTSUP, "tridiagonal reduction: n_mo does not fit the cooperative launch");
   const bool trd = G > 0;
+  const bool own = trd && kind != RIF_EIG_TRD;
+  rocblas_handle h = nullptr;
+  rif_status st;
+  if (!own && (st = blas_handle(c, &h))) return st;
   Carve cv;
   const size_t oF = cv.take<double>((size_t)n * n), oV = cv.take<double>((size_t)n * n);
   const size_t oCt = cv.take<double>((size_t)nb * n), oE = cv.take<double>((size_t)n), oI = cv.take<int>(1);
-  size_t oQ = 0, oWt = 0, oS = 0, oErr = 0;
+  size_t oQ = 0, oWt = 0, oS = 0, oErr = 0, oZ1 = 0, oDc = 0, oErrDc = 0;
   if (trd) {
     oQ = cv.take<double>((size_t)n * n);
     oWt = cv.take<double>((size_t)n * nb);
     oS = cv.take<char>(trd_scratch_bytes(n));
     oErr = cv.take<int>(1);
   }
+  if (own) {
+    oZ1 = cv.take<double>((size_t)n * n);
+    oDc = cv.take<char>(tdc_scratch_bytes(n));
+    oErrDc = cv.take<int>(1);
+  }
   if ((st = ws_reserve(c, cv.off))) return st;
   auto at = [&](size_t o) { return (char*)c->ws + o; };
   int* dinfo = info ? info : (int*)at(oI);
+  if (own) {
+    double *F = (double*)at(oF), *E = (double*)at(oE);
+    {
+      ProfScope ps(c, "flam");
+      hipLaunchKernelGGL(k_flam, dim3((unsigned)(((long)n * n + 255) / 256)), dim3(256), 0, c->stream, n, nw, lam,
+                         eps_in, F);
+      if ((st = check_launch(c, "flam"))) return st;
+    }
+    {
+      ProfScope ps(c, "tridiagonal");
+      if ((st = op_trd(c, n, G, F, (double*)at(oQ), eps_out, E, at(oS), (int*)at(oErr)))) return st;
+    }
+    {
+      ProfScope ps(c, "eigensolver");
+      // rows of F become the eigenvectors of T
+      if ((st = op_tdc(c, n, eps_out, E, F, (double*)at(oZ1), at(oDc), (int*)at(oErrDc)))) return st;
+      hipLaunchKernelGGL(k_tdc_info, dim3(1), dim3(64), 0, c->stream, (const int*)at(oErr), (const int*)at(oErrDc),
+                         dinfo);
+      if ((st = check_launch(c, "tdc_info"))) return st;
+    }
+    ProfScope ps(c, "rotate");
+    double *V = (double*)at(oV), *Ct = (double*)at(oCt), *Wt = (double*)at(oWt);
+    if ((st = transpose(c, n, n, F, n, V, n))) return st;
+    if ((st = transpose(c, nb, n, C, n, Ct, nb))) return st;
+    if ((st = op_gemm_kn(c, n, nb, n, (const double*)at(oQ), n, Ct, nb, Wt, nb))) return st;
+    return op_gemm_kn(c, nb, n, n, Wt, nb, V, n, C, n);
+  }
   // F is symmetric, so its row-major array is also its column-major one.  On
   // return, column j of the column-major F is eigenvector j of F (dsyevd) or
   // of T (dstedc, eigenvalues into eps_out, which holds T's diagonal).

@@ -308,8 +308,8 @@ rif_status rif_orbital_step(rif_ctx* c, int nb, int nmo, int nw, const double* l
 
 rif_status rif_set_eigensolver(rif_ctx* c, int kind, int groups) {
   if (!c) return RIF_EINVAL;
-  if (kind < RIF_EIG_AUTO || kind > RIF_EIG_TRD || groups < 0 || groups > 4096)
-    return fail(c, RIF_EINVAL, "rif_set_eigensolver: need kind in {0, 1, 2} and 0 <= groups <= 4096");
+  if (kind < RIF_EIG_AUTO || kind > RIF_EIG_DC || groups < 0 || groups > 4096)
+    return fail(c, RIF_EINVAL, "rif_set_eigensolver: need kind in {0, 1, 2, 3} and 0 <= groups <= 4096");
   c->eig_kind = kind;
   c->eig_groups = groups;
   return RIF_OK;

@@ -30,15 +30,15 @@ def ctx():
     c.close()
 
 
-def test_orbital_step_reports_a_timed_out_reduction(ctx):
+@pytest.mark.parametrize("kind", [2, 3])   # the reduction, then dstedc or the library's divide and conquer
+def test_orbital_step_reports_a_timed_out_reduction(ctx, kind):
     import torch
-    import paper_2012_15662_amd as rif
-    print("case waits: orbital step", flush=True)
+    print("case waits: orbital step, eigensolver", kind, flush=True)
     inst = synth.make_instance(37, 101, 3, 2, 11)
     t = to_dev(inst)
     out = ctx.build(t["b"], t["C"], t["H"], t["occ"], t["pair_of"], inst.n_pairs, inst.n_cwo)
     W = inst.occ.size
-    ctx.set_eigensolver(rif.EIG_TRD)
+    ctx.set_eigensolver(kind)
     info = torch.full((1,), 7, dtype=torch.int32, device="cuda")
     C_ref = t["C"].clone()
     w_ref = ctx.orbital_step(out["lam"], C_ref, W, info=info)
@@ -58,15 +58,16 @@ def test_orbital_step_reports_a_timed_out_reduction(ctx):
     assert np.array_equal(host(C), host(C_ref))
 
 
-def test_optimisation_loop_fails_on_a_timed_out_reduction(ctx):
+@pytest.mark.parametrize("kind", [2, 3])
+def test_optimisation_loop_fails_on_a_timed_out_reduction(ctx, kind):
     import torch
     import paper_2012_15662_amd as rif
-    print("case waits: optimisation loop", flush=True)
+    print("case waits: optimisation loop, eigensolver", kind, flush=True)
     inst = synth.make_instance(20, 40, 2, 1, 41)
     t = to_dev(inst)
     occ = t["occ"].clone()
     gamma = torch.zeros(inst.n_pairs * inst.n_cwo, dtype=torch.float64, device="cuda")
-    ctx.set_eigensolver(rif.EIG_TRD)
+    ctx.set_eigensolver(kind)
     ctx.set_wait_limit(-1)
     try:
         with pytest.raises(rif.RifError) as e:
