@@ -525,7 +525,7 @@ def bench_orbopt(args):
     ctx = rif.Context(0)
     if not args.no_tune:
         ctx.autotune(True)
-    ctx.set_eigensolver(args.eig)
+    ctx.set_eigensolver(args.eig, args.eig_groups)
 
     def upload(inst):
         d = {k: torch.from_numpy(np.ascontiguousarray(getattr(inst, k))).cuda() for k in ("b", "C", "H", "occ")}
@@ -687,6 +687,8 @@ def main():
     ap.add_argument("--eig", type=int, default=0, choices=[0, 1, 2, 3],
                     help="orbopt eigensolver: 0 automatic (3 where it fits), 1 rocSOLVER dsyevd, "
                          "2 one-launch reduction + rocSOLVER dstedc, 3 one-launch reduction + own divide and conquer")
+    ap.add_argument("--eig-groups", type=int, default=0,
+                    help="orbopt: workgroups of the one-launch tridiagonal reduction (0: default)")
     ap.add_argument("--orb-size", default="c6h12", choices=["tiny", "c6h12", "c10h20"],
                     help="orbopt: the molecule whose inner iterations are run")
     ap.add_argument("--no-small", action="store_true",

@@ -197,8 +197,9 @@ class Context:
             self.lib.rif_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # the default argument keeps the check reachable after module teardown
+        if _finalizing():
             return   # the exit hook has released every context still open
         try:
             self.close()
@@ -622,8 +623,8 @@ class Batch:
                 self.ctx.lib.rif_batch_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()

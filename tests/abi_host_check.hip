@@ -125,7 +125,8 @@ int main() {
   EXPECT(rif_prepare_b(c, 10, 10, nullptr, p, 0.0, p, ibuf, p, p, ibuf), RIF_EINVAL);
   EXPECT(rif_orbital_step(c, 10, 10, 11, p, p, p, p, ibuf), RIF_EINVAL);
   EXPECT(rif_orbital_step(c, 10, 10, 5, p, p, nullptr, p, ibuf), RIF_EINVAL);
-  EXPECT(rif_set_eigensolver(c, 3, 0), RIF_EINVAL);
+  EXPECT(rif_set_eigensolver(c, 4, 0), RIF_EINVAL);
+  EXPECT(rif_set_eigensolver(c, 3, 0), RIF_OK);
   EXPECT(rif_set_eigensolver(c, 1, 5000), RIF_EINVAL);
   EXPECT(rif_set_eigensolver(c, 2, 64), RIF_OK);
   {
