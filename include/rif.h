@@ -400,8 +400,9 @@ rif_status rif_orbital_step(rif_ctx *ctx, int n_bf, int n_mo, int n_omega, const
  *   RIF_EIG_TRD    the same reduction, then rocSOLVER dstedc on T.
  *   RIF_EIG_SYEVD  rocSOLVER dsyevd (its own blocked reduction).
  *   RIF_EIG_AUTO   DC where it fits, else SYEVD (the default).
- * groups: workgroups of the reduction, 0 for the default (about three rows
- * each, at least 16 workgroups, more where the rows do not fit).  Results of the solvers agree to rounding,
+ * groups: workgroups of the reduction, 0 for the default (four rows each, one
+ * per wave, at least 16 workgroups, more where the rows do not fit).  Results
+ * of the solvers agree to rounding,
  * eigenvectors up to sign.  RIF_EINVAL for an unknown kind or groups outside
  * [0, 4096]. */
 typedef RIF_ENUM { RIF_EIG_AUTO = 0, RIF_EIG_SYEVD = 1, RIF_EIG_TRD = 2, RIF_EIG_DC = 3 } rif_eigensolver;

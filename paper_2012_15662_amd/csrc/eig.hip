@@ -248,12 +248,12 @@ int trd_groups(rif_ctx* c, int n, int want) {
     (void)hipGetLastError();
     return 0;
   }
-  // `want` workgroups if given, else about three rows each (at least 16
-  // workgroups: more shorten each one's share of a column, fewer shorten the
-  // waits); more if the rows do not fit the LDS budget; at most one per CU and
-  // one per row
+  // `want` workgroups if given, else four rows each, one per wave (at least
+  // 16 workgroups: more shorten each one's share of a column, fewer shorten
+  // the waits; measured best at 348, 580 and 1000 rows); more if the rows do
+  // not fit the LDS budget; at most one per CU and one per row
   const int gmax = std::min(ncu, n);
-  int G = want > 0 ? want : std::max(std::min(16, n), (n + 2) / 3);
+  int G = want > 0 ? want : std::max(std::min(16, n), (n + 3) / 4);
   G = std::min(G, gmax);
   while (G <= gmax && trd_lds(n, G) > kTrdLds) ++G;
   return G <= gmax ? G : 0;
