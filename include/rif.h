@@ -373,8 +373,9 @@ rif_status rif_prepare_b(rif_ctx *ctx, int n_bf, int n_aux, const double *T, con
  *   eps_out [n_mo] eigenvalues, ascending (may be eps_in)
  *   info    device int or NULL: 0; > 0 the tridiagonal eigensolver did not
  *           converge (rocSOLVER's failure count, or 1 from the library's own
- *           divide and conquer); -1 a timed-out wait of the one-launch
- *           reduction (rif_set_wait_limit)
+ *           divide and conquer, which also reports a non-finite F that way);
+ *           -1 a timed-out wait of the one-launch reduction
+ *           (rif_set_wait_limit)
  * The eigen-decomposition runs on the context's stream with its workspace in
  * the context arena (solver chosen by rif_set_eigensolver); the rotation is an
  * FP64 MFMA GEMM.  info = -1 reports a timed-out wait inside the tridiagonal

@@ -614,8 +614,10 @@ struct YdB {  // element (q, k): value in r[i], coefficient Bt[q][r] in r[R + i]
   const T *bmo, *Zt, *Bt;
   int na, nw, q;
   long k0, kend;
+  double inv_na;
   __device__ void init(const T* bmo_, const T* Zt_, const T* Bt_, int na_, int nw_, long k0_, long kend_, int q0) {
     bmo = bmo_; Zt = Zt_; Bt = Bt_; na = na_; nw = nw_; k0 = k0_; kend = kend_;
+    inv_na = 1.0 / na;
     g.x = threadIdx.x % Cfg::BN; g.kg = threadIdx.x / Cfg::BN;
     q = q0 + g.x; g.ok = q < nw;
   }
@@ -631,7 +633,9 @@ struct YdB {  // element (q, k): value in r[i], coefficient Bt[q][r] in r[R + i]
         long k = k0 + (long)kt * BK + g.kl(p) + i;
         k = k < kend ? k : kend - 1;
         const int kk = (int)k;   // k < n_aux * n_omega < 2^31
-        const int rr = kk / na, l = kk - rr * na;
+        // r = kk / n_aux from the reciprocal (off by at most one), then exact
+        int rr = (int)((double)kk * inv_na), l = kk - rr * na;
+        if (l < 0) { --rr; l += na; } else if (l >= na) { ++rr; l -= na; }
         const T* src = rr == qc ? Zt + (long)l * nw + qc : bmo + ((long)l * nw + rr) * nw + qc;
         r[p * KV + i] = *src;
         r[R + p * KV + i] = Bt[(long)qc * nw + rr];

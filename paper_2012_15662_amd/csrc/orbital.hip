@@ -124,7 +124,7 @@ __global__ void k_trd_info(const int* err, int* info) {
   if (threadIdx.x == 0 && *err != 0) *info = -1;
 }
 // own divide and conquer: -1 for a timed-out wait of the reduction, 1 for a
-// leaf that did not converge, else 0
+// non-finite T or a leaf that did not converge, else 0
 __global__ void k_tdc_info(const int* err_trd, const int* err_dc, int* info) {
   if (threadIdx.x == 0) *info = *err_trd != 0 ? -1 : (*err_dc != 0 ? 1 : 0);
 }

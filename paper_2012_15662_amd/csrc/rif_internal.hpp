@@ -168,11 +168,12 @@ rif_status op_trd(rif_ctx* c, int n, int G, const double* F, double* Q, double* 
 
 // Eigen-decomposition of a symmetric tridiagonal matrix by divide and conquer
 // (tdc.hip): d (n, in: diagonal, out: eigenvalues ascending), e (n-1), Z0 and
-// Z1 n x n each; on return row c of Z0 is eigenvector c.  A leaf that fails
-// to converge sets *err (cleared at the start).  2 <= n <= tdc_max_n().
+// Z1 n x n each; on return row c of Z0 is eigenvector c.  *err (cleared at
+// the start) is set by a non-finite entry of T (T is then taken as zero) or a
+// leaf that fails to converge.  2 <= n <= tdc_max_n().
 size_t tdc_scratch_bytes(int n);
 int tdc_max_n();
-rif_status op_tdc(rif_ctx* c, int n, double* d, const double* e, double* Z0, double* Z1, void* scratch, int* err);
+rif_status op_tdc(rif_ctx* c, int n, double* d, double* e, double* Z0, double* Z1, void* scratch, int* err);
 
 // Orbital optimisation (orbital.hip)
 rif_status op_maxabs(rif_ctx* c, long n, const double* x, double* part, double* out);

@@ -261,6 +261,9 @@ __global__ __launch_bounds__(256) void k_tdc_deflate(TdcArgs a, int t, const dou
     const double x = a.d[lo + i];
     din[i] = x;
     mx = fmax(mx, fabs(x));
+    sd[i] = 0.0;   // every slot valid even if two ranks collided
+    sz[i] = 0.0;
+    src[i] = i;
   }
   red[tid] = mx;
   __syncthreads();
@@ -610,16 +613,16 @@ __global__ __launch_bounds__(256) void k_tdc_bmat(TdcArgs a, int t) {
   double* B = a.B + (long)lo * n + lo;
   if (w < k) {
     const double zj = a.zh[lo + w], dj = a.dk[lo + w];
-    double* row = B + (long)a.ndrow[lo + w] * n;
+    double* row = B + (long)min(max(a.ndrow[lo + w], 0), s - 1) * n;   // (clamp: a source row)
     for (int c = lane; c < s; c += 64) {
       const int i = a.colsrc[lo + c];
       double v = 0.0;
-      if (i >= 0) v = zj / ((dj - a.dk[lo + a.org[lo + i]]) - a.tau[lo + i]) * a.invn[lo + i];
+      if (i >= 0 && i < k) v = zj / ((dj - a.dk[lo + a.org[lo + i]]) - a.tau[lo + i]) * a.invn[lo + i];
       row[c] = v;
     }
   } else {
     const int u = w - k;
-    double* row = B + (long)a.dvrow[lo + u] * n;
+    double* row = B + (long)min(max(a.dvrow[lo + u], 0), s - 1) * n;
     for (int c = lane; c < s; c += 64) row[c] = a.colsrc[lo + c] == -(u + 1) ? 1.0 : 0.0;
   }
 }
@@ -676,12 +679,28 @@ __global__ __launch_bounds__(TdcTile::NT) void k_tdc_gemm(int n, int t, const do
   });
 }
 
-__global__ __launch_bounds__(256) void k_tdc_zero(long count, double* x, double* y, int* err) {
+// Both eigenvector arrays to zero; workgroup 0 also checks T: a non-finite
+// entry sets the error flag and T to zero, so that every later step works on
+// finite values (the call then reports the failure).
+__global__ __launch_bounds__(256) void k_tdc_zero(long count, double* x, double* y, int n, double* d, double* e,
+                                                  int* err) {
   for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < count; i += (long)gridDim.x * 256) {
     x[i] = 0.0;
     y[i] = 0.0;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *err = 0;
+  if (blockIdx.x != 0) return;
+  bool bad = false;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    bad = bad || !isfinite(d[i]);
+    if (i + 1 < n) bad = bad || !isfinite(e[i]);
+  }
+  bad = __syncthreads_or(bad);
+  if (bad)
+    for (int i = threadIdx.x; i < n; i += 256) {
+      d[i] = 0.0;
+      if (i + 1 < n) e[i] = 0.0;
+    }
+  if (threadIdx.x == 0) *err = bad ? 1 : 0;
 }
 
 size_t deflate_lds(int s) { return (size_t)s * (3 * sizeof(double) + 4 * sizeof(int)); }
@@ -692,7 +711,7 @@ size_t tdc_scratch_bytes(int n) {   // B, then 10 double and 9 int arrays of n
 }
 int tdc_max_n() { return kTdcMaxN; }
 
-rif_status op_tdc(rif_ctx* c, int n, double* d, const double* e, double* Z0, double* Z1, void* scratch, int* err) {
+rif_status op_tdc(rif_ctx* c, int n, double* d, double* e, double* Z0, double* Z1, void* scratch, int* err) {
   if (n < 2 || n > kTdcMaxN) return fail(c, RIF_ENOTSUP, "tridiagonal divide and conquer: n outside [2, 2048]");
   TdcArgs a{};
   a.n = n;
@@ -733,7 +752,7 @@ rif_status op_tdc(rif_ctx* c, int n, double* d, const double* e, double* Z0, dou
   {
     const long cnt = (long)n * n;
     hipLaunchKernelGGL(k_tdc_zero, dim3((unsigned)std::min(1024L, (cnt + 255) / 256)), dim3(256), 0, c->stream, cnt,
-                       Z0, Z1, a.err);
+                       Z0, Z1, n, d, e, a.err);
     if ((st = check_launch(c, "tdc_zero"))) return st;
     hipLaunchKernelGGL(k_tdc_leaf, dim3(1u << T), dim3(64), 0, c->stream, a, T, cur);
     if ((st = check_launch(c, "tdc_leaf"))) return st;

@@ -15,8 +15,9 @@ library's divide and conquer (kind 3) runs on the same matrices and on
 tridiagonal ones (which the reduction passes through unchanged) chosen for
 its merge paths: Toeplitz and glued Wilkinson matrices (many rotation
 deflations), decoupled and weakly coupled clusters (deflation by small update
-components), a zero coupling at a split point, and sizes around the leaf size
-of 32 rows and the merge tree's uneven splits.
+components), a zero coupling at a split point, sizes around the leaf size
+of 16 rows and the merge tree's uneven splits, and a non-finite F, which it
+reports as info = 1 without disturbing the next call.
 """
 import numpy as np
 import pytest
@@ -205,3 +206,25 @@ def test_size_limits(ctx):
     for kind in (2, 3):
         w, V = diagonalise(ctx, F, kind)
         check(F, w, V)
+
+
+@pytest.mark.parametrize("where", ["off-diagonal NaN", "diagonal inf"])
+def test_divide_and_conquer_reports_non_finite_input(ctx, where):
+    import torch
+    print("case eig dc non-finite:", where, flush=True)
+    n = 40
+    F = random_sym(n, 5)
+    lam = np.tril(F, -1)
+    eps = np.ascontiguousarray(np.diag(F)).copy()
+    if where == "off-diagonal NaN":
+        lam[7, 3] = np.nan
+    else:
+        eps[11] = np.inf
+    C = torch.eye(n, dtype=torch.float64, device="cuda")
+    info = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+    ctx.set_eigensolver(3)
+    ctx.orbital_step(torch.from_numpy(lam).cuda(), C, n, eps_in=torch.from_numpy(eps).cuda(), info=info)
+    ctx.sync()
+    assert int(host(info)[0]) == 1
+    w, V = diagonalise(ctx, F, 3)   # the next call is unaffected
+    check(F, w, V)
