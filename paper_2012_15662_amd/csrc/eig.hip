@@ -37,7 +37,7 @@
 // ordering between different values is needed.  Every wait is bounded: past
 // the poll limit, or once another workgroup has flagged a timeout, the
 // workgroup flags it and returns, so every wave exits.  Within a workgroup the
-// waves share out the rows (wave w takes rows t0 + w, t0 + w + 4, ..., t0 the
+// waves share out the rows (wave w takes rows t0 + w, t0 + w + 8, ..., t0 the
 // first row still active) and every reduction is formed whole in each wave.
 #include <algorithm>
 #include <string>
@@ -48,7 +48,7 @@
 namespace rif {
 
 namespace {
-constexpr int kTrdThreads = 256;
+constexpr int kTrdThreads = 512;   // eight waves, one row of A and Q each by default
 constexpr int kTrdWaves = kTrdThreads / 64;
 constexpr size_t kTrdLds = 150 * 1024;        // dynamic LDS per workgroup, at most
 constexpr size_t kTrdLdsDefault = 64 * 1024;  // beyond this the kernel needs the attribute raised
@@ -248,12 +248,13 @@ int trd_groups(rif_ctx* c, int n, int want) {
     (void)hipGetLastError();
     return 0;
   }
-  // `want` workgroups if given, else four rows each, one per wave (at least
-  // 16 workgroups: more shorten each one's share of a column, fewer shorten
-  // the waits; measured best at 348, 580 and 1000 rows); more if the rows do
-  // not fit the LDS budget; at most one per CU and one per row
+  // `want` workgroups if given, else one row per wave (at least 16
+  // workgroups: more shorten each one's share of a column, fewer shorten the
+  // waits; eight waves of one row measured best at 348, 580 and 1000 rows);
+  // more if the rows do not fit the LDS budget; at most one per CU and one per
+  // row
   const int gmax = std::min(ncu, n);
-  int G = want > 0 ? want : std::max(std::min(16, n), (n + 3) / 4);
+  int G = want > 0 ? want : std::max(std::min(16, n), (n + kTrdWaves - 1) / kTrdWaves);
   G = std::min(G, gmax);
   while (G <= gmax && trd_lds(n, G) > kTrdLds) ++G;
   return G <= gmax ? G : 0;
