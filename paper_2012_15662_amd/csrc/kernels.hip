@@ -89,7 +89,15 @@ constexpr int kDeep = kPieces<P> == 2 ? 2 : 1;
 struct Planes { const unsigned short* p; long ps; int ld; };
 // Bs / bf: b given pre-split (bf16 piece planes with rows r = l*n_bf + nu, or
 // an FP32 copy in b's layout); unset (null) means b is split on load.
-struct HalfArgs { int nb, nw, nmo; long nr; const double* b; const double* C; void* bh; Planes Cs; Planes Bs; const float* bf; };
+// dma: FP64 operands staged by direct global -> LDS loads in the 128 x 128
+// tile (set when every row of b and C starts 16-byte aligned and n_omega is even).
+struct HalfArgs {
+  int nb, nw, nmo; long nr; const double* b; const double* C; void* bh; Planes Cs; Planes Bs; const float* bf;
+  int dma;
+};
+inline int half_dma_ok(int nb, int nmo, int nw, const double* b, const double* C) {
+  return nb % 2 == 0 && nmo % 2 == 0 && nw % 2 == 0 && ((uintptr_t)b | (uintptr_t)C) % 16 == 0;
+}
 // b pre-split once per call: element (r, mu) = b[r*n_bf + mu] (row r = l*n_bf + nu;
 // b symmetric) into the mode's pieces, rows zero-filled from n_bf up to ld;
 // FP32 mode: a float copy.
@@ -97,11 +105,14 @@ struct BSplitArgs { const double* b; long nr; int nb, ld; void* out; long ps; };
 struct MoArgs { int nb, na, nw, nmo; const void* bh; const double* C; void* bmo; double* d; Planes Cs; };
 // Bj: b pre-split for J^q (piece planes with rows r = mu*n_bf + nu and
 // k = l contiguous), or unset (split on load).
-struct JaoArgs { int nb, na, nw; const double* b; const double* d; void* Jn; Planes Ds; Planes Bj; };
+// dma: FP64 operands staged by direct global -> LDS loads in the 128 x 128
+// tile (rows of b and d 16-byte aligned).
+struct JaoArgs { int nb, na, nw; const double* b; const double* d; void* Jn; Planes Ds; Planes Bj; int dma; };
 // Pre-split of X (element (x, k) at X[k*sk + x]) into NPC bf16 planes
 // out[s*ps + x*ld + k], zero from k = K up to ld.
 struct PSplitArgs { const double* X; long sk; int nx, K, ld; unsigned short* out; long ps; };
-struct KaoArgs { int nb, na, nw; const void* bh; void* Kn; };
+// dma: FP64 b_half staged by direct global -> LDS loads (rows 16-byte aligned).
+struct KaoArgs { int nb, na, nw; const void* bh; void* Kn; int dma; };
 // Split over k: out + s*ostride receives the partial product over
 // k in [s*kc, min(K, (s+1)*kc)), s < ksplit.
 struct GemmArgs {
@@ -156,6 +167,25 @@ __device__ void half_tile_with(const HalfArgs& a, long t, char* smem) {
   const long nr = a.nr, B2 = (long)nb * nb;
   IOT<P>* bh = (IOT<P>*)a.bh;
   typename E::template Acc<Cfg> acc;
+  auto slab_off = [&](int x, long& o) {   // column r = l*n_bf + nu of b at k = mu = 0
+    const long r = r0 + x, l = r / nb;
+    o = l * B2 + (r - l * nb);
+    return r < nr;
+  };
+  if constexpr (P == kF64 && !kBPre && Cfg::BM == 128 && Cfg::BN == 128) {
+    if (a.dma) {
+      XcDma64<Cfg::NT, E::BK, E::PAD> la, lb;
+      la.init(a.C, a.nmo, nb, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
+      lb.init(a.b, nb, nb, slab_off);
+      gemm_mainloop_dma<E, Cfg, 2>(la, lb, cdiv(nb, E::BK), acc, smem);
+      acc.for_each([&](int m, int n, double v) {
+        const int q = q0 + m;
+        const long r = r0 + n;
+        if (q < nw && r < nr) bh[(long)q * nr + r] = (IOT<P>)v;
+      });
+      return;
+    }
+  }
   if constexpr (kBPre && kPieces<P> > 0) {
     // A: C_Omega^T (x = q, k = mu) from its per-call piece planes; B: column
     // r = l*n_bf + nu, piece-plane row r of the pre-split b (k = mu
@@ -174,11 +204,6 @@ __device__ void half_tile_with(const HalfArgs& a, long t, char* smem) {
       la.init(a.C, a.nmo, nb, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
     // B: column r = l*n_bf + nu of b[l][mu][nu] at k = mu: x-contiguous within
     // a slab (FP64 b, or FP32 mode's pre-made float copy at b's offsets)
-    auto slab_off = [&](int x, long& o) {
-      const long r = r0 + x, l = r / nb;
-      o = l * B2 + (r - l * nb);
-      return r < nr;
-    };
     using LB = typename std::conditional<kBPre, XCS<P, float, Cfg::BN, Cfg::NT>, XCS<P, double, Cfg::BN, Cfg::NT>>::type;
     LB lb;
     if constexpr (kBPre)
@@ -294,20 +319,33 @@ __device__ void jao_tile(const JaoArgs& a, long t, char* smem) {
   const int mu0 = bi * TMU, nu0 = bj * TNU;
   const int q0 = qt * Cfg::BM;
   const long B2 = (long)nb * nb;
-  // A: d^T (x = q, k = l), from piece planes in the split modes
-  typename std::conditional<kPlanesHalfJao<P>, PCS<P, Cfg::BM, Cfg::NT>, XCS<P, double, Cfg::BM, Cfg::NT>>::type la;
-  if constexpr (kPlanesHalfJao<P>)
-    la.init(a.Ds.p, a.Ds.ps, a.Ds.ld, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
-  else
-    la.init(a.d, nw, na, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
-  XCS<P, double, Cfg::BN, Cfg::NT> lb;
-  lb.init(a.b, B2, na, [&](int x, long& o) {
+  auto b_off = [&](int x, long& o) {   // element (mu, nu) of the block in slab l = 0
     const int mu = mu0 + x / TNU, nu = nu0 + x % TNU;
     o = (long)mu * nb + nu;
     return mu < nb && nu < nb;
-  });
+  };
   typename E::template Acc<Cfg> acc;
-  gemm_mainloop<E, Cfg>(la, lb, cdiv(na, E::BK), acc, smem);
+  bool staged = false;
+  if constexpr (P == kF64 && Cfg::BM == 128 && Cfg::BN == 128) {
+    if (a.dma) {   // both operands by direct global -> LDS loads
+      XcDma64<Cfg::NT, E::BK, E::PAD> la, lb;
+      la.init(a.d, nw, na, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
+      lb.init(a.b, B2, na, b_off);
+      gemm_mainloop_dma<E, Cfg, 2>(la, lb, cdiv(na, E::BK), acc, smem);
+      staged = true;
+    }
+  }
+  if (!staged) {
+    // A: d^T (x = q, k = l), from piece planes in the split modes
+    typename std::conditional<kPlanesHalfJao<P>, PCS<P, Cfg::BM, Cfg::NT>, XCS<P, double, Cfg::BM, Cfg::NT>>::type la;
+    if constexpr (kPlanesHalfJao<P>)
+      la.init(a.Ds.p, a.Ds.ps, a.Ds.ld, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
+    else
+      la.init(a.d, nw, na, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
+    XCS<P, double, Cfg::BN, Cfg::NT> lb;
+    lb.init(a.b, B2, na, b_off);
+    gemm_mainloop<E, Cfg>(la, lb, cdiv(na, E::BK), acc, smem);
+  }
   IOT<P>* Jn = (IOT<P>*)a.Jn;
   acc.for_each([&](int m, int n, double v) {
     const int q = q0 + m, mu = mu0 + n / TNU, nu = nu0 + n % TNU;
@@ -411,6 +449,30 @@ __device__ void kao_tile(const KaoArgs& a, long t, char* smem) {
   constexpr int FB = Cfg::BM / 16;
   const int fim = min(FB, cdiv(nb - mu0, 16)), fjm = min(FB, cdiv(nb - nu0, 16));
   const bool diag = bi == bj;
+  if constexpr (P == kF64 && (Cfg::BM == 128 || Cfg::BM == 64)) {
+    if (a.dma) {   // b_half by direct global -> LDS loads; a diagonal block stages one panel
+      XcDma64<Cfg::NT, E::BK, E::PAD, Cfg::BM> da, db;
+      da.init((const double*)X, nb, na, [&](int x, long& o) { o = mu0 + x; return mu0 + x < nb; });
+      db.init((const double*)X, nb, na, [&](int x, long& o) { o = nu0 + x; return nu0 + x < nb; });
+      if (!diag && fim == FB && fjm == FB) {
+        gemm_mainloop_dma<E, Cfg, 2>(da, db, cdiv(na, E::BK), acc, smem);
+        acc.for_each(store);
+        return;
+      }
+      const WavePlan w =
+          make_wave_plan<Cfg>([&](int I, int J) { return I < fim && J < fjm && (!diag || I <= J); });
+      with_rows<Cfg::TM>(w.ni, [&](auto rows) {
+        constexpr int NI = decltype(rows)::value;
+        gemm_mainloop_dma_with<E, Cfg, 2>(da, db, cdiv(na, E::BK), acc, smem, diag,
+                                          [&](const lds_char* SA, const lds_char* SB,
+                                              typename E::template Acc<Cfg>& c) {
+                                            E::template mma_rows<Cfg, NI>(SA, SB, c, w);
+                                          });
+      });
+      acc.for_each(w, store);
+      return;
+    }
+  }
   // The split-BF16 engines (VALU-bound by operand splitting, and short of
   // registers for the extra loop copies) always compute whole blocks.
   constexpr bool kPlan = P == kF64 || P == kF32;
@@ -1330,7 +1392,8 @@ static BuildArgs make_build_args(const Plan& pl, const rif_instance& in, int pre
   A.psc = PSplitArgs{in.C, (long)nmo, nw, nb, lc, Cs, (long)nw * lc};
   A.psd = PSplitArgs{in.d, (long)nw, nw, na, ldd, Ds, (long)nw * ldd};
   const Planes cs{Cs, (long)nw * lc, lc}, ds{Ds, (long)nw * ldd, ldd};
-  A.half = HalfArgs{nb, nw, nmo, (long)na * nb, in.b, in.C, in.b_half, cs, Planes{nullptr, 0, 0}, nullptr};
+  A.half = HalfArgs{nb, nw, nmo, (long)na * nb, in.b, in.C, in.b_half, cs, Planes{nullptr, 0, 0}, nullptr,
+                    half_dma_ok(nb, nmo, nw, in.b, in.C)};
   if (in.b_split && (prec == RIF_BF16X3 || prec == RIF_BF16X6 || prec == RIF_FP16X3)) {
     const int lb = round32(nb);
     A.half.Bs = Planes{(const unsigned short*)in.b_split, (long)na * nb * lb, lb};
@@ -1339,14 +1402,15 @@ static BuildArgs make_build_args(const Plan& pl, const rif_instance& in, int pre
   }
   A.mo = MoArgs{nb, na, nw, nmo, in.b_half, in.C, in.b_mo, in.d, cs};
   A.jk = JkArgs{na, nw, pl.jk_nsplit, in.b_mo, in.d, part, in.J, in.K};
-  A.jao = JaoArgs{nb, na, nw, in.b, in.d, in.Jn, ds, Planes{nullptr, 0, 0}};
+  A.jao = JaoArgs{nb, na, nw, in.b, in.d, in.Jn, ds, Planes{nullptr, 0, 0},
+                  nb % 2 == 0 && nw % 2 == 0 && ((uintptr_t)in.b | (uintptr_t)in.d) % 16 == 0};
   if (in.b_split && (prec == RIF_BF16X3 || prec == RIF_BF16X6 || prec == RIF_FP16X3)) {
     const long npc = prec == RIF_BF16X6 ? 3 : 2;
     const int lj = round32(na);
     const unsigned short* j0 = (const unsigned short*)in.b_split + npc * (long)na * nb * round32(nb);
     A.jao.Bj = Planes{j0, (long)nb * nb * lj, lj};
   }
-  A.kao = KaoArgs{nb, na, nw, in.b_half, in.Kn};
+  A.kao = KaoArgs{nb, na, nw, in.b_half, in.Kn, nb % 2 == 0 && (uintptr_t)in.b_half % 16 == 0};
   A.hc = GemmArgs{nb, nw, nb, in.H, (long)nb, in.C, (long)nmo, HC, (long)nw, 1, nb, (long)nb * nw};
   A.coef = CoefArgs{functional, nw, pl.npairs, pl.ncwo, in.pair_of, in.occ, in.J, in.K, Ac, Bc, Ep};
   A.energy = EnergyArgs{nw, pl.npairs, pl.ncwo, nb, nmo, pl.nparts, in.pair_of, in.occ, in.C, HC, Ep, in.energy,
@@ -1413,14 +1477,15 @@ rif_status op_transform(rif_ctx* c, int prec, int nb, int na, int nw, int nmo, c
   unsigned short* Cs = (unsigned short*)((char*)c->ws + o_cs);
   const Planes cs{Cs, (long)nw * lc, lc};
   const PSplitArgs ps{C, (long)nmo, nw, nb, lc, Cs, (long)nw * lc};
-  const HalfArgs h{nb, nw, nmo, (long)na * nb, b, C, bh, cs};
+  const HalfArgs h{nb, nw, nmo, (long)na * nb, b, C, bh, cs, Planes{}, nullptr, half_dma_ok(nb, nmo, nw, b, C)};
   const MoArgs m{nb, na, nw, nmo, bh, C, bmo, d, cs};
   RIF_PREC_SWITCH(prec, run_transform<P>(c, ps, h, m))
 }
 
 rif_status op_half_slabs_f64(rif_ctx* c, int nb, long nslab, int nw, int nmo, const double* slabs, const double* C,
                              double* out) {
-  const HalfArgs h{nb, nw, nmo, nslab * nb, slabs, C, out, Planes{}, Planes{}, nullptr};
+  const HalfArgs h{nb, nw, nmo, nslab * nb, slabs, C, out, Planes{}, Planes{}, nullptr,
+                   half_dma_ok(nb, nmo, nw, slabs, C)};
   return step_half<kF64>(c, h);
 }
 
@@ -1498,8 +1563,9 @@ rif_status op_jk_ao(rif_ctx* c, int prec, int nb, int na, int nw, const double* 
   if (st) return st;
   unsigned short* Ds = (unsigned short*)((char*)c->ws + o_ds);
   const PSplitArgs ps{d, (long)nw, nw, na, ldd, Ds, (long)nw * ldd};
-  const JaoArgs j{nb, na, nw, b, d, Jn, Planes{Ds, (long)nw * ldd, ldd}};
-  const KaoArgs k{nb, na, nw, bh, Kn};
+  const JaoArgs j{nb, na, nw, b, d, Jn, Planes{Ds, (long)nw * ldd, ldd}, Planes{nullptr, 0, 0},
+                  nb % 2 == 0 && nw % 2 == 0 && ((uintptr_t)b | (uintptr_t)d) % 16 == 0};
+  const KaoArgs k{nb, na, nw, bh, Kn, nb % 2 == 0 && (uintptr_t)bh % 16 == 0};
   RIF_PREC_SWITCH(prec, run_jk_ao<P>(c, ps, j, k))
 }
 

@@ -551,6 +551,67 @@ struct PieceDma {
   }
 };
 
+// Zeros read by the direct-staging loader below for k rows past the end.
+static __device__ __attribute__((aligned(16))) double kDmaZeros[128];
+
+// FP64 x-contiguous operand staged by direct global -> LDS loads (16 bytes,
+// two doubles of one k-row per lane).  With 128 columns one wave's load fills
+// one k-row of the stage; with 64 columns each half-wave fills one row (the
+// load's LDS address is the wave's base plus 16 bytes per lane index).
+// The rows' padding stays untouched.  Rows at or past K read zeros; a column
+// pair that does not exist reads column 0 (its outputs are never stored).
+// Needs 16-byte aligned rows and even column offsets.
+template <int NT, int BK, int PAD, int BX = 128>
+struct XcDma64 {
+  static_assert(BX == 128 || BX == 64, "one row per wave or half-wave");
+  static constexpr int NW = NT / 64, RPI = 128 / BX;   // k-rows per wave instruction pair
+  static constexpr int UPW = BK / (NW * RPI);          // row groups per wave per slice
+  static_assert(BK % (NW * RPI) == 0, "k rows per wave");
+  static constexpr int STRIDE = (BX + PAD) * 8;        // bytes per LDS row
+  const double* col;   // this lane's column pair in k row 0
+  long ld;
+  int K;
+  template <class OffFn>
+  __device__ void init(const double* base, long ld_, int K_, OffFn off) {
+    ld = ld_;
+    K = K_;
+    long o = 0;
+    const bool ok = off(2 * (int)(threadIdx.x & (BX / 2 - 1)), o);
+    col = base + (ok ? o : 0);
+  }
+  __device__ int count() const { return UPW * RPI; }
+  __device__ void issue(int kt, lds_char* S) const {
+    const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+#pragma unroll
+    for (int j = 0; j < UPW; ++j) {
+      const int g = w + j * NW;   // row group
+      if constexpr (BX == 128) {
+        const int k = kt * BK + g;
+        const double* src = k < K ? col + (long)k * ld : kDmaZeros + 2 * lane;
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                         (__attribute__((address_space(3))) void*)(S + g * STRIDE), 16, 0, 0);
+      } else {
+        // rows 2g (lanes 0-31) and 2g+1 (lanes 32-63) from one wave-uniform
+        // LDS base; the upper half's shift to its row goes into the immediate
+        // offset (applied to both addresses, so its global address is set back
+        // by as much), which also keeps the two loads from being merged into
+        // one with a lane-varying base
+        constexpr int kUp = STRIDE - 512;
+        const int h = lane >> 5, kl = 2 * g + h, k = kt * BK + kl;
+        const double* src = k < K ? col + (long)k * ld : kDmaZeros + 2 * (lane & 31);
+        lds_char* dst = S + 2 * g * STRIDE;
+        if (h == 0)
+          __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                           (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+        else
+          __builtin_amdgcn_global_load_lds(
+              (const __attribute__((address_space(1))) void*)((const char*)src - kUp),
+              (__attribute__((address_space(3))) void*)dst, 16, kUp, 0);
+      }
+    }
+  }
+};
+
 template <class L, class = void>
 struct is_presplit : std::false_type {};
 template <class L>
@@ -848,8 +909,9 @@ constexpr int smem_bytes_dma() {
   return dma_stages<E, Cfg>() * (E::template stage_bytes<Cfg::BM>() + E::template stage_bytes<Cfg::BN>());
 }
 
-// Main loop for two PieceDma operands: S = dma_stages() LDS stages, S-1
-// slices of loads in flight.  Per slice kt: wait for this wave's loads of
+// Main loop for two direct-staged operands (PieceDma, XcDma64): S = S_ (or
+// dma_stages()) LDS stages, S-1 slices of loads in flight; with b_is_a one
+// panel is staged and read as both operands.  mma(SA, SB, acc) does a slice.  Per slice kt: wait for this wave's loads of
 // slice kt (the loads of the S-2 later slices stay in flight), a plain
 // s_barrier (so every wave's loads of slice kt have landed and every wave is
 // done reading the stage about to be refilled), the loads of slice kt+S-1
@@ -857,22 +919,24 @@ constexpr int smem_bytes_dma() {
 // memory fence: a fence would wait for every load in flight.  Past the last
 // slice the loads re-read slice nk-1 into a stage nobody reads, which keeps
 // the count of loads per slice fixed for the waits.
-template <class E, class Cfg, class LA, class LB>
-__device__ __forceinline__ void gemm_mainloop_dma(const LA& la, const LB& lb, int nk,
-                                                  typename E::template Acc<Cfg>& acc, char* smem_generic) {
-  constexpr int S = dma_stages<E, Cfg>();
+template <class E, class Cfg, int S_ = 0, class LA, class LB, class MMA>
+__device__ __forceinline__ void gemm_mainloop_dma_with(const LA& la, const LB& lb, int nk,
+                                                       typename E::template Acc<Cfg>& acc, char* smem_generic,
+                                                       bool b_is_a, MMA&& mma) {
+  constexpr int S = S_ > 0 ? S_ : dma_stages<E, Cfg>();
   static_assert(S >= 2, "two stages at least");
   constexpr int SA = E::template stage_bytes<Cfg::BM>();
   constexpr int ST = SA + E::template stage_bytes<Cfg::BN>();
   lds_char* smem = (lds_char*)smem_generic;
   acc.zero();
   if (nk <= 0) return;
-  const int per_slice = la.count() + lb.count();
+  // b_is_a: one panel staged (stage's A part) and read as both operands
+  const int per_slice = la.count() + (b_is_a ? 0 : lb.count());
 #pragma unroll
   for (int j = 0; j < S - 1; ++j) {
     const int k = j < nk ? j : nk - 1;
     la.issue(k, smem + j * ST);
-    lb.issue(k, smem + j * ST + SA);
+    if (!b_is_a) lb.issue(k, smem + j * ST + SA);
   }
   for (int kt = 0; kt < nk; ++kt) {
     wait_vmcnt((S - 2) * per_slice);
@@ -882,9 +946,9 @@ __device__ __forceinline__ void gemm_mainloop_dma(const LA& la, const LB& lb, in
     const int kf = kt + S - 1 < nk ? kt + S - 1 : nk - 1;
     lds_char* sf = smem + ((kt + S - 1) % S) * ST;
     la.issue(kf, sf);
-    lb.issue(kf, sf + SA);
+    if (!b_is_a) lb.issue(kf, sf + SA);
     const lds_char* sc = smem + (kt % S) * ST;
-    E::template mma<Cfg>(sc, sc + SA, acc, regular_plan<Cfg>());
+    mma(sc, b_is_a ? sc : sc + SA, acc);
     if ((kt + 1) % E::CHUNK == 0) acc.flush();
   }
   acc.flush();
@@ -892,6 +956,15 @@ __device__ __forceinline__ void gemm_mainloop_dma(const LA& la, const LB& lb, in
   wait_vmcnt(0);
   asm volatile("" ::: "memory");
   __builtin_amdgcn_s_barrier();
+}
+
+template <class E, class Cfg, int S_ = 0, class LA, class LB>
+__device__ __forceinline__ void gemm_mainloop_dma(const LA& la, const LB& lb, int nk,
+                                                  typename E::template Acc<Cfg>& acc, char* smem_generic) {
+  gemm_mainloop_dma_with<E, Cfg, S_>(la, lb, nk, acc, smem_generic, false,
+                                     [&](const lds_char* SA, const lds_char* SB, typename E::template Acc<Cfg>& c) {
+                                       E::template mma<Cfg>(SA, SB, c, regular_plan<Cfg>());
+                                     });
 }
 
 }  // namespace rif
