@@ -9,7 +9,7 @@
 //   T = diag(T1 - beta e_last e_last^T, T2 - beta e_0 e_0^T) + beta w w^T,
 //   w = (e_last ; sigma e_0).
 // The range [0, n) is halved recursively (block p of level t is
-// [floor(p n / 2^t), floor((p+1) n / 2^t))) down to leaves of at most 32 rows,
+// [floor(p n / 2^t), floor((p+1) n / 2^t))) down to leaves of at most 16 rows,
 // so every split point's two diagonal corrections fall on leaf boundaries.
 //
 // Leaves: implicit symmetric QR steps with the Wilkinson shift, the rotations
@@ -93,7 +93,7 @@ struct TdcArgs {
   double* zh;          // recomputed update vector
   double* invn;        // 1 / |u_i|
   int* colsrc;         // output column c: root i (>= 0) or deflated t (-(t+1))
-  int* err;            // set when a leaf's QR iteration fails to converge
+  int* err;            // set by a non-finite T or a leaf that fails to converge
 };
 
 __device__ __forceinline__ double wave_prod(double x) {
@@ -706,8 +706,8 @@ __global__ __launch_bounds__(256) void k_tdc_zero(long count, double* x, double*
 size_t deflate_lds(int s) { return (size_t)s * (3 * sizeof(double) + 4 * sizeof(int)); }
 }  // namespace
 
-size_t tdc_scratch_bytes(int n) {   // B, then 10 double and 9 int arrays of n
-  return (size_t)n * n * sizeof(double) + 10 * (size_t)n * sizeof(double) + 9 * (size_t)n * sizeof(int);
+size_t tdc_scratch_bytes(int n) {   // B, then 9 double and 8 int arrays of n
+  return (size_t)n * n * sizeof(double) + 9 * (size_t)n * sizeof(double) + 8 * (size_t)n * sizeof(int);
 }
 int tdc_max_n() { return kTdcMaxN; }
 
@@ -734,7 +734,6 @@ rif_status op_tdc(rif_ctx* c, int n, double* d, double* e, double* Z0, double* Z
   a.tau = (double*)take(dn);
   a.zh = (double*)take(dn);
   a.invn = (double*)take(dn);
-  take(dn);   // spare, keeps the int arrays 8-byte aligned
   a.kcnt = (int*)take(in_);
   a.nrot = (int*)take(in_);
   a.ndrow = (int*)take(in_);
@@ -743,7 +742,6 @@ rif_status op_tdc(rif_ctx* c, int n, double* d, double* e, double* Z0, double* Z
   a.rj = (int*)take(in_);
   a.org = (int*)take(in_);
   a.colsrc = (int*)take(in_);
-  take(in_);
   a.err = err;
   const int T = tdc_levels(n);
   double* cur = (T % 2 == 0) ? Z0 : Z1;   // the last level writes Z0
