@@ -86,7 +86,9 @@ def kernel_bytes(nb, na, nw):
 
 
 def build_flops(nb, na, nw, nmo):
-    return sum(kernel_flops(nb, na, nw, nmo).values())
+    """Algorithmic flops of one build (the pre-split kernels' entries are the
+    same work as their split-on-load kernels, so they are not added again)."""
+    return sum(v for k, v in kernel_flops(nb, na, nw, nmo).items() if not k.endswith("_presplit"))
 
 
 def cpu_baseline(inst, Cs, budget_s=20.0):
@@ -389,6 +391,99 @@ def bench_batch(args):
     print(json.dumps(line))
 
 
+def batch_study(ctx, steps=10, warmup=2):
+    """The 64-molecule uneven batch (the batch64 workload, the molecules
+    tests/test_gpu_batch64.py compares with the oracle) inside the default
+    run: FP64 and BF16x6, grouped launches replayed from a hipGraph; FP64
+    also one build call after another."""
+    import torch
+
+    import synth
+
+    items, flops = [], 0.0
+    for inp, npair, ncwo in synth.make_batch_device(64):
+        nb = inp["b"].shape[1]
+        items.append((inp, npair, ncwo, None))
+        flops += build_flops(nb, 3 * nb, npair * (1 + ncwo), nb)
+    res = {"config": "64 molecules, n_bf ~ U{60..400} (seed 3), n_aux = 3 n_bf, pairs = n_bf//12, Ncwo = 2; "
+                     "one step = all 64 builds"}
+    for name in ("fp64", "bf16x6"):
+        batch = ctx.batch(items, prec=MODES[name])
+        for _ in range(warmup):
+            batch.run(use_graph=True)
+        ctx.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            batch.run(use_graph=True)
+        torch.cuda.synchronize()
+        per = (time.perf_counter() - t0) / steps
+        ctx.sync()
+        ent = {"builds_s": round(64 / per, 2), "ms_per_step": round(per * 1e3, 3),
+               "tflops": round(flops / per / 1e12, 2)}
+        if name == "fp64":
+            outs = batch.outs
+            for inp, npair, ncwo, _ in items:   # warm the single-build tiles
+                ctx.build_instance(inp, npair, ncwo, out=None, prec=MODES[name])
+            ctx.sync()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for (inp, npair, ncwo, _), out in zip(items, outs):
+                ctx.build_instance(inp, npair, ncwo, out=out, prec=MODES[name])
+            torch.cuda.synchronize()
+            el_seq = time.perf_counter() - t1
+            ctx.sync()
+            ent["sequential_builds_s"] = round(64 / el_seq, 2)
+            ent["batch_speedup"] = round(el_seq / per, 3)
+        res[name] = ent
+        batch.close()
+    res["bf16x6"]["speedup_vs_fp64"] = round(res["bf16x6"]["builds_s"] / res["fp64"]["builds_s"], 3)
+    del items
+    torch.cuda.empty_cache()
+    return res
+
+
+def largest_study(ctx, steps=3):
+    """The largest workload (n_bf 1000, n_aux 3000, 60 pairs, Ncwo 6; b is 24 GB
+    in FP64, drawn on the GPU) inside the default run: FP64 and BF16x6
+    builds/s, and BF16x6's energy and gradient against the FP64 build (which
+    tests/test_gpu_largest.py holds to the oracle at 1e-10)."""
+    import torch
+
+    import synth
+
+    size, seed = (1000, 3000, 60, 6), 31
+    t, npair, ncwo = synth.make_instance_device(*size, seed)
+    nb, na = size[0], size[1]
+    nw = npair * (1 + ncwo)
+    flops = build_flops(nb, na, nw, nb)
+    res = {"config": f"n_bf={nb} n_aux={na} pairs={npair} ncwo={ncwo} n_omega={nw} n_mo={nb} (seed {seed})"}
+    outs = {}
+    for name in ("fp64", "bf16x6"):
+        pv = MODES[name]
+        out = ctx.build(t["b"], t["C"], t["H"], t["occ"], t["pair_of"], npair, ncwo, prec=pv)   # tiles, warm-up
+        ctx.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.build(t["b"], t["C"], t["H"], t["occ"], t["pair_of"], npair, ncwo, prec=pv, out=out)
+        ctx.sync()
+        torch.cuda.synchronize()
+        per = (time.perf_counter() - t0) / steps
+        res[name] = {"builds_s": round(1 / per, 3), "ms_per_build": round(per * 1e3, 2),
+                     "tflops": round(flops / per / 1e12, 2)}
+        outs[name] = (float(out["energy"].cpu()[0]), out["grad"].cpu().numpy())
+        del out
+    e64, g64 = outs["fp64"]
+    e16, g16 = outs["bf16x6"]
+    res["bf16x6"]["speedup_vs_fp64"] = round(res["bf16x6"]["builds_s"] / res["fp64"]["builds_s"], 3)
+    res["bf16x6"]["dE_vs_fp64"] = e16 - e64
+    res["bf16x6"]["grad_err_vs_fp64"] = float(abs(g16 - g64).max() / abs(g64).max())
+    del t
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_onwarm(args):
     """Learned ON warm start at scale: 2000 training molecules (n_bf ~ U{48..200},
     n_aux = 3 n_bf, pairs = n_bf//12, Ncwo ~ U{1..6}) solved by the plain ON
@@ -684,6 +779,9 @@ def main():
     ap.add_argument("--no-4c", action="store_true", help="skip the RI vs four-centre comparison")
     ap.add_argument("--no-c10h20", action="store_true",
                     help="skip the precision study at the cyclodecane-like size")
+    ap.add_argument("--no-batch64", action="store_true", help="skip the 64-molecule batch sub-record")
+    ap.add_argument("--no-largest", action="store_true",
+                    help="skip the largest workload (n_bf 1000, b 24 GB) sub-record")
     ap.add_argument("--eig", type=int, default=0, choices=[0, 1, 2, 3],
                     help="orbopt eigensolver: 0 automatic (3 where it fits), 1 rocSOLVER dsyevd, "
                          "2 one-launch reduction + rocSOLVER dstedc, 3 one-launch reduction + own divide and conquer")
@@ -844,6 +942,10 @@ def main():
         }
     if not args.no_4c:
         line["four_centre"] = four_centre_study(ctx)
+    if not args.no_batch64:
+        line["batch64"] = batch_study(ctx)
+    if not args.no_largest:
+        line["largest"] = largest_study(ctx)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(inst, Cs, args.cpu_budget)
     ctx.close()
