@@ -105,7 +105,7 @@ def cpu_baseline(inst, Cs, budget_s=20.0):
         ri.build_instance(inst, C=Cs[n % len(Cs)])
         n += 1
         el = time.perf_counter() - t0
-        if el > budget_s or n >= 15:
+        if el > budget_s or n >= 200:
             break
     return {"value": n / el, "unit": "builds/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{n} full FP64 builds of the same workload (numpy oracle, rotated C), {el:.1f} s"}
@@ -485,6 +485,10 @@ def largest_study(ctx, steps=3):
 
 
 def bench_onwarm(args):
+    print(json.dumps(onwarm_study(args)))
+
+
+def onwarm_study(args):
     """Learned ON warm start at scale: 2000 training molecules (n_bf ~ U{48..200},
     n_aux = 3 n_bf, pairs = n_bf//12, Ncwo ~ U{1..6}) solved by the plain ON
     optimiser from the cold start; the MLP trains on their converged ONs on the
@@ -598,7 +602,7 @@ def bench_onwarm(args):
         "held_out": held, "large": big,
     }
     ctx.close()
-    print(json.dumps(line))
+    return line
 
 
 EIG_NAMES = {0: "auto (reduction + divide and conquer)", 1: "rocSOLVER dsyevd",
@@ -662,11 +666,12 @@ def bench_orbopt(args):
     if not args.no_cpu:
         from oracle import orbital as orb
         ts = time.perf_counter()
-        k = orb.inner_loop(inst.b, inst.C, inst.H, inst.occ, inst.pair_of, inst.n_pairs, 3, 1e-14)
+        k = orb.inner_loop(inst.b, inst.C, inst.H, inst.occ, inst.pair_of, inst.n_pairs, 30, 1e-14)
         tc = time.perf_counter() - ts
         cpu = {"value": round(len(k["energies"]) / tc, 3), "unit": "inner iterations/s",
                "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), "kind": "oracle",
-               "sample": f"3 inner iterations of the same workload at fixed ONs (numpy build + eigh), {tc:.1f} s"}
+               "sample": f"{len(k['energies'])} inner iterations of the same workload at fixed ONs "
+                         f"(numpy build + eigh), {tc:.1f} s"}
 
     line = {
         "metric": "orbital-optimisation inner iterations/s (build + F^lambda eigen-decomposition + rotation)",
@@ -767,7 +772,8 @@ def main():
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--lr-final", type=float, default=1e-4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of oracle builds for the CPU baseline (at most 200 builds)")
     ap.add_argument("--no-tune", action="store_true", help="heuristic tile shapes instead of autotuning")
     ap.add_argument("--prec", default="fp64", choices=list(MODES))
     ap.add_argument("--calib", action="store_true",
@@ -780,6 +786,7 @@ def main():
     ap.add_argument("--no-c10h20", action="store_true",
                     help="skip the precision study at the cyclodecane-like size")
     ap.add_argument("--no-batch64", action="store_true", help="skip the 64-molecule batch sub-record")
+    ap.add_argument("--no-onwarm", action="store_true", help="skip the learned ON warm-start sub-record")
     ap.add_argument("--no-largest", action="store_true",
                     help="skip the largest workload (n_bf 1000, b 24 GB) sub-record")
     ap.add_argument("--eig", type=int, default=0, choices=[0, 1, 2, 3],
@@ -946,6 +953,10 @@ def main():
         line["batch64"] = batch_study(ctx)
     if not args.no_largest:
         line["largest"] = largest_study(ctx)
+    if not args.no_onwarm:
+        ow = onwarm_study(args)   # its own context
+        line["onwarm"] = {"metric": ow["metric"], "iter_reduction_held_out": ow["value"], "config": ow["config"],
+                          "train": ow["train"], "held_out": ow["held_out"], "large": ow["large"]}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(inst, Cs, args.cpu_budget)
     ctx.close()
