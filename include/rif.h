@@ -464,6 +464,15 @@ rif_status rif_autotune(rif_ctx *ctx, int mode);
 rif_status rif_set_tile_variant(rif_ctx *ctx, int v);
 /* "kernel shape... -> variant | ms per variant" lines for every tuned shape. */
 rif_status rif_tune_report(rif_ctx *ctx, char *buf, int len);
+/* Tile choices from text in rif_tune_report's format (one line per tuned
+ * shape; blank lines ignored), so that a process can start from choices
+ * measured earlier: under autotuning (mode 1) a later call with a loaded
+ * shape takes the loaded variant without timing (a variant the kernel does
+ * not have is ignored and that shape is timed as usual).  A loaded line
+ * replaces the context's entry for the same shape.  Host-only, no GPU work.
+ * RIF_EINVAL for NULL text or a line that does not parse (nothing is loaded
+ * then; the message names the line). */
+rif_status rif_tune_load(rif_ctx *ctx, const char *text);
 
 /* Per-kernel timing with HIP events on the context's stream.
  * rif_profile_enable(ctx, 1) starts recording an event pair around every

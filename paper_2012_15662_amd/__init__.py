@@ -106,6 +106,7 @@ EXPORTS = {
     "rif_autotune": (_i, [_vp, _i]),
     "rif_set_tile_variant": (_i, [_vp, _i]),
     "rif_tune_report": (_i, [_vp, ctypes.c_char_p, _i]),
+    "rif_tune_load": (_i, [_vp, ctypes.c_char_p]),
     "rif_profile_enable": (_i, [_vp, _i]),
     "rif_profile_report": (_i, [_vp, ctypes.c_char_p, _i]),
     "rif_profile_only": (_i, [_vp, ctypes.c_char_p]),
@@ -577,6 +578,10 @@ class Context:
         buf = ctypes.create_string_buffer(1 << 16)
         self._chk(self.lib.rif_tune_report(self.h, buf, len(buf)))
         return buf.value.decode()
+
+    def tune_load(self, text: str):
+        """rif_tune_load: tile choices from an earlier tune_report()."""
+        self._chk(self.lib.rif_tune_load(self.h, text.encode()))
 
     # ---- per-kernel timing ------------------------------------------------
     def profile(self, on: bool = True, only: str | None = None):

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <string>
+#include <vector>
 
 #include "rif_internal.hpp"
 
@@ -49,7 +50,7 @@ int pick_variant(rif_ctx* c, const char* kernel, std::initializer_list<long> sha
   std::string key = kernel;
   for (long v : shape) key += " " + std::to_string(v);
   for (auto& t : c->tune)
-    if (t.key == key) return t.variant;
+    if (t.key == key && t.variant < nvar) return t.variant;   // (a loaded entry may name too many)
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return -1;
   if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return -1; }
@@ -551,6 +552,51 @@ rif_status rif_tune_report(rif_ctx* c, char* buf, int len) {
   }
   strncpy(buf, s.c_str(), (size_t)len - 1);
   buf[len - 1] = 0;
+  return RIF_OK;
+}
+
+rif_status rif_tune_load(rif_ctx* c, const char* text) {
+  if (!c) return RIF_EINVAL;
+  if (!text) return fail(c, RIF_EINVAL, "rif_tune_load: NULL text");
+  std::vector<rif_ctx::Tune> add;
+  int ln = 0;
+  for (const char* p = text; *p;) {
+    const char* e = strchr(p, '\n');
+    const std::string line(p, e ? (size_t)(e - p) : strlen(p));
+    p = e ? e + 1 : p + line.size();
+    ++ln;
+    if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
+    auto bad = [&]() { return fail(c, RIF_EINVAL, "rif_tune_load: line " + std::to_string(ln) + " does not parse"); };
+    const size_t arrow = line.find(" -> ");
+    if (arrow == std::string::npos || arrow == 0) return bad();
+    const size_t bar = line.find(" |", arrow + 4);
+    if (bar == std::string::npos) return bad();
+    const std::string vs = line.substr(arrow + 4, bar - arrow - 4);
+    char* end = nullptr;
+    const long v = strtol(vs.c_str(), &end, 10);
+    if (vs.empty() || *end != '\0' || v < 0) return bad();
+    rif_ctx::Tune t{line.substr(0, arrow), (int)v, {}};
+    const char* q = line.c_str() + bar + 2;
+    while (*q) {
+      while (*q == ' ' || *q == '\t' || *q == '\r') ++q;
+      if (!*q) break;
+      const float ms = strtof(q, &end);
+      if (end == q) return bad();
+      t.ms.push_back(ms);
+      q = end;
+    }
+    if (t.ms.empty() || (size_t)v >= t.ms.size()) return bad();
+    add.push_back(std::move(t));
+  }
+  for (auto& t : add) {
+    bool found = false;
+    for (auto& u : c->tune)
+      if (u.key == t.key) {
+        u = t;
+        found = true;
+      }
+    if (!found) c->tune.push_back(t);
+  }
   return RIF_OK;
 }
 

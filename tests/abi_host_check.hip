@@ -172,6 +172,23 @@ int main() {
   expect("rif_autotune(c, 5)", rif_autotune(c, 5), RIF_EINVAL, nullptr);
   expect("rif_tune_report(c, NULL, 10)", rif_tune_report(c, nullptr, 10), RIF_EINVAL, nullptr);
   expect("rif_set_workspace_limit", rif_set_workspace_limit(c, 1ull << 40), RIF_OK, nullptr);
+  // tile choices loaded from a report: parse errors load nothing; a good text
+  // round-trips through rif_tune_report, and a later line replaces its shape
+  EXPECT(rif_tune_load(c, nullptr), RIF_EINVAL);
+  EXPECT(rif_tune_load(c, "half 1 2 -> x | 0.1"), RIF_EINVAL);
+  EXPECT(rif_tune_load(c, "half 1 2 -> 3 | 0.1 0.2"), RIF_EINVAL);       // no variant 3 among two
+  EXPECT(rif_tune_load(c, "mo 3 -> 0 | 0.1\nhalf 1 2 0.5"), RIF_EINVAL);  // second line has no arrow
+  EXPECT(rif_tune_load(c, "half 1 2 -> 1 | 0.5 0.25\n\nmo 3 -> 0 | 0.1\n"), RIF_OK);
+  EXPECT(rif_tune_load(c, "half 1 2 -> 0 | 0.5 0.25"), RIF_OK);
+  {
+    char rep[256];
+    ++n_call;
+    if (rif_tune_report(c, rep, sizeof rep) != RIF_OK ||
+        strcmp(rep, "half 1 2 -> 0 | 0.5000 0.2500\nmo 3 -> 0 | 0.1000\n") != 0) {
+      printf("FAIL rif_tune_load round trip: %s\n", rep);
+      ++n_fail;
+    }
+  }
 
   printf("%d calls, %d failures\n", n_call, n_fail);
   return n_fail ? 1 : 0;
