@@ -99,6 +99,47 @@ class WarmStartMLP:
         self.ctx.mlp_forward(X, M, self.theta, H, Z, P)
         return P
 
+    def save(self, path, mu=None, sigma=None):
+        """The weights, the Adam state and the feature standardisation (mu,
+        sigma; defaults: the ones set on the network) to an .npz file of
+        plain arrays, so a trained warm start can be reused without training."""
+        mu = self.mu if mu is None else mu
+        sigma = self.sigma if sigma is None else sigma
+        arrs = {"layers": np.array([N_IN, N_HID, N_HID, N_HID, N_OUT], dtype=np.int64),
+                "theta": self.theta.detach().cpu().numpy(), "m": self.m.detach().cpu().numpy(),
+                "v": self.v.detach().cpu().numpy(), "step": np.array([self.step], dtype=np.int64)}
+        for k, x in (("mu", mu), ("sigma", sigma)):
+            if x is not None:
+                arrs[k] = (x.detach().cpu().numpy() if hasattr(x, "detach") else np.asarray(x)).astype(np.float32)
+        np.savez(path, **arrs)
+
+    @classmethod
+    def load(cls, ctx: Context, path, device="cuda"):
+        """A network written by save(); mu and sigma come back as attributes
+        (None if they were not saved).  Raises ValueError for another layout."""
+        import torch
+        with np.load(path, allow_pickle=False) as f:
+            missing = [k for k in ("layers", "theta", "m", "v", "step") if k not in f]
+            if missing:
+                raise ValueError(f"{path}: no {', '.join(missing)}")
+            if not np.array_equal(f["layers"], [N_IN, N_HID, N_HID, N_HID, N_OUT]):
+                raise ValueError(f"{path}: layer sizes {f['layers'].tolist()} differ from this network's")
+            net = cls(ctx, device=device)
+            n = ctx.mlp_n_params()
+            for k in ("theta", "m", "v"):
+                a = f[k]
+                if a.shape != (n,):
+                    raise ValueError(f"{path}: {k} has shape {a.shape}, expected ({n},)")
+                setattr(net, k, torch.from_numpy(a.astype(np.float32)).to(device))
+            net.step = int(f["step"][0])
+            for k in ("mu", "sigma"):
+                if k in f:
+                    a = f[k]
+                    if a.shape != (N_IN,):
+                        raise ValueError(f"{path}: {k} has shape {a.shape}, expected ({N_IN},)")
+                    setattr(net, k, torch.from_numpy(a.astype(np.float32)).to(device))
+        return net
+
 
 def features(ctx: Context, onset: OnSet, with_targets=False, mu=None, sigma=None):
     import torch

@@ -180,3 +180,18 @@ def test_trained_warm_start_cuts_iterations(ctx):
     # same minima (the optimiser decides where it ends; a different local minimum would show here)
     Ec, Ew = host(te_cold.energy), host(te_warm.energy)
     assert np.mean(np.abs(Ec - Ew) < 1e-9 * np.abs(Ec)) >= 0.9
+    # the trained network saved and loaded again predicts the same bits; a file
+    # of another layout is refused
+    import os
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "warm.npz")
+        net.save(path, mu=mu, sigma=sd)
+        net2 = ws.WarmStartMLP.load(ctx, path)
+        assert net2.step == net.step
+        Xt2, _, Mt2 = ws.features(ctx, rif.OnSet(ctx, test), mu=net2.mu, sigma=net2.sigma)
+        assert np.array_equal(host(net2.predict(Xt2, Mt2)), host(net.predict(Xt, Mt)))
+        bad = os.path.join(d, "bad.npz")
+        np.savez(bad, layers=np.array([39, 64, 7]), theta=np.zeros(3, np.float32))
+        with pytest.raises(ValueError):
+            ws.WarmStartMLP.load(ctx, bad)
