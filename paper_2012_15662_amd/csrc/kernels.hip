@@ -150,6 +150,38 @@ struct YdzArgs { int na, nw; const double *Ac, *Bc, *d; void *Zt, *Bt; };
 struct YdArgs { int nb, na, nw, nsplit; long kc; const void *bh, *bmo, *Zt, *Bt; double* Yp; };
 struct GradArgs { int nmo, nw, lsplit; const double* lp; double *lam, *G; int* flag; };
 
+// Runs a tile's main loop, main(mma), and stores through store(m, n, v).  With
+// kTrim (the grouped kernels, whose one tile shape serves molecules of every
+// n_omega), in FP64 and FP32 a tile with at most half of its M fragment rows
+// live (fim fragment rows of n_omega left in the last q-tile) trims each
+// wave's fragment rows to the live ones under a balanced wave plan: the rows
+// it computes are bitwise those of the full tile, and the rows it skips hold
+// q >= n_omega, which are never stored.  Single-molecule launches pick their
+// tile shape per molecule and run whole tiles: there trimming measured
+// slower (those tiles stay load-bound with more rows live).
+template <int P, class Cfg, bool kTrim, class Main, class Store>
+__device__ __forceinline__ void run_q_rows(int fim, typename EngineOf<P>::type::template Acc<Cfg>& acc, Main&& main,
+                                           Store&& store) {
+  using E = typename EngineOf<P>::type;
+  if constexpr (kTrim && (P == kF64 || P == kF32)) {
+    if (2 * fim <= Cfg::BM / 16) {
+      const WavePlan w = make_wave_plan<Cfg>([&](int I, int) { return I < fim; });
+      with_rows<Cfg::TM>(w.ni, [&](auto rows) {
+        constexpr int NI = decltype(rows)::value;
+        main([&](const lds_char* SA, const lds_char* SB, typename E::template Acc<Cfg>& c) {
+          E::template mma_rows<Cfg, NI>(SA, SB, c, w);
+        });
+      });
+      acc.for_each(w, store);
+      return;
+    }
+  }
+  main([&](const lds_char* SA, const lds_char* SB, typename E::template Acc<Cfg>& c) {
+    E::template mma<Cfg>(SA, SB, c, regular_plan<Cfg>());
+  });
+  acc.for_each(store);
+}
+
 // Half transform, Eq. (12): bh[q][r] = sum_mu C[mu][q] b[l][mu][nu] with the
 // output column r = l*n_bf + nu flattened over (l, nu).  M = q, N = r (loads of
 // b and stores of b_half both run along nu), K = mu.  Tiles: q-tile fastest.
@@ -157,7 +189,7 @@ template <int P, class Cfg>
 __host__ __device__ inline long half_tiles(const HalfArgs& a) {
   return (long)cdiv(a.nw, Cfg::BM) * cdiv(a.nr, Cfg::BN);
 }
-template <int P, class Cfg, bool kBPre>
+template <int P, class Cfg, bool kBPre, bool kTrim>
 __device__ void half_tile_with(const HalfArgs& a, long t, char* smem) {
   using E = typename EngineOf<P>::type;
   const int nqt = cdiv(a.nw, Cfg::BM);
@@ -172,17 +204,25 @@ __device__ void half_tile_with(const HalfArgs& a, long t, char* smem) {
     o = l * B2 + (r - l * nb);
     return r < nr;
   };
+  auto store = [&](int m, int n, double v) {
+    const int q = q0 + m;
+    const long r = r0 + n;
+    if (q < nw && r < nr) bh[(long)q * nr + r] = (IOT<P>)v;
+  };
+  const int fim = cdiv(nw - q0, 16);   // live fragment rows
   if constexpr (P == kF64 && !kBPre && Cfg::BM == 128 && Cfg::BN == 128) {
     if (a.dma) {
       XcDma64<Cfg::NT, E::BK, E::PAD> la, lb;
       la.init(a.C, a.nmo, nb, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
       lb.init(a.b, nb, nb, slab_off);
-      gemm_mainloop_dma<E, Cfg, 2>(la, lb, cdiv(nb, E::BK), acc, smem);
-      acc.for_each([&](int m, int n, double v) {
-        const int q = q0 + m;
-        const long r = r0 + n;
-        if (q < nw && r < nr) bh[(long)q * nr + r] = (IOT<P>)v;
-      });
+      if constexpr (kTrim) {
+        run_q_rows<P, Cfg, kTrim>(fim, acc, [&](auto mma) {
+          gemm_mainloop_dma_with<E, Cfg, 2>(la, lb, cdiv(nb, E::BK), acc, smem, false, mma);
+        }, store);
+      } else {
+        gemm_mainloop_dma<E, Cfg, 2>(la, lb, cdiv(nb, E::BK), acc, smem);
+        acc.for_each(store);
+      }
       return;
     }
   }
@@ -210,20 +250,27 @@ __device__ void half_tile_with(const HalfArgs& a, long t, char* smem) {
       lb.init(a.bf, nb, nb, slab_off);
     else
       lb.init(a.b, nb, nb, slab_off);
-    gemm_mainloop<E, Cfg>(la, lb, cdiv(nb, E::BK), acc, smem);
+    if constexpr (kTrim && kPieces<P> == 0) {
+      run_q_rows<P, Cfg, kTrim>(fim, acc, [&](auto mma) {
+        gemm_mainloop_with<E, Cfg>(la, lb, cdiv(nb, E::BK), acc, smem, false, mma);
+      }, store);
+      return;
+    } else {
+      gemm_mainloop<E, Cfg>(la, lb, cdiv(nb, E::BK), acc, smem);
+    }
   }
-  acc.for_each([&](int m, int n, double v) {
-    const int q = q0 + m;
-    const long r = r0 + n;
-    if (q < nw && r < nr) bh[(long)q * nr + r] = (IOT<P>)v;
-  });
+  acc.for_each(store);
 }
 // Separate kernels for b split on load (half) and pre-split (halfp), so each
 // keeps its own register budget.
 template <int P, class Cfg>
-__device__ void half_tile(const HalfArgs& a, long t, char* smem) { half_tile_with<P, Cfg, false>(a, t, smem); }
+__device__ void half_tile(const HalfArgs& a, long t, char* smem) { half_tile_with<P, Cfg, false, false>(a, t, smem); }
 template <int P, class Cfg>
-__device__ void halfp_tile(const HalfArgs& a, long t, char* smem) { half_tile_with<P, Cfg, true>(a, t, smem); }
+__device__ void halfp_tile(const HalfArgs& a, long t, char* smem) { half_tile_with<P, Cfg, true, false>(a, t, smem); }
+template <int P, class Cfg>
+__device__ void half_g_tile(const HalfArgs& a, long t, char* smem) { half_tile_with<P, Cfg, false, true>(a, t, smem); }
+template <int P, class Cfg>
+__device__ void halfp_g_tile(const HalfArgs& a, long t, char* smem) { half_tile_with<P, Cfg, true, true>(a, t, smem); }
 template <int P, class Cfg>
 __host__ __device__ inline long halfp_tiles(const HalfArgs& a) { return half_tiles<P, Cfg>(a); }
 template <int P>
@@ -299,7 +346,7 @@ template <int P, class Cfg>
 __host__ __device__ inline long jao_tiles(const JaoArgs& a) {
   return jao_active(a.nb, Cfg::BN / kJaoTNU, kJaoTNU) * cdiv(a.nw, Cfg::BM);
 }
-template <int P, class Cfg>
+template <int P, class Cfg, bool kTrim = false>
 __device__ void jao_tile(const JaoArgs& a, long t, char* smem) {
   using E = typename EngineOf<P>::type;
   constexpr int TNU = kJaoTNU, TMU = Cfg::BN / TNU;
@@ -325,14 +372,31 @@ __device__ void jao_tile(const JaoArgs& a, long t, char* smem) {
     return mu < nb && nu < nb;
   };
   typename E::template Acc<Cfg> acc;
+  IOT<P>* Jn = (IOT<P>*)a.Jn;
+  auto store = [&](int m, int n, double v) {
+    const int q = q0 + m, mu = mu0 + n / TNU, nu = nu0 + n % TNU;
+    if (q < nw && mu < nb && nu < nb) {
+      IOT<P>* J = Jn + (long)q * B2;
+      if (mu <= nu) J[(long)mu * nb + nu] = (IOT<P>)v;
+      if (mu < nu) J[(long)nu * nb + mu] = (IOT<P>)v;
+    }
+  };
+  const int fim = cdiv(nw - q0, 16);   // live fragment rows
   bool staged = false;
   if constexpr (P == kF64 && Cfg::BM == 128 && Cfg::BN == 128) {
     if (a.dma) {   // both operands by direct global -> LDS loads
       XcDma64<Cfg::NT, E::BK, E::PAD> la, lb;
       la.init(a.d, nw, na, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
       lb.init(a.b, B2, na, b_off);
-      gemm_mainloop_dma<E, Cfg, 2>(la, lb, cdiv(na, E::BK), acc, smem);
-      staged = true;
+      if constexpr (kTrim) {
+        run_q_rows<P, Cfg, kTrim>(fim, acc, [&](auto mma) {
+          gemm_mainloop_dma_with<E, Cfg, 2>(la, lb, cdiv(na, E::BK), acc, smem, false, mma);
+        }, store);
+        return;
+      } else {
+        gemm_mainloop_dma<E, Cfg, 2>(la, lb, cdiv(na, E::BK), acc, smem);
+        staged = true;
+      }
     }
   }
   if (!staged) {
@@ -344,18 +408,20 @@ __device__ void jao_tile(const JaoArgs& a, long t, char* smem) {
       la.init(a.d, nw, na, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
     XCS<P, double, Cfg::BN, Cfg::NT> lb;
     lb.init(a.b, B2, na, b_off);
-    gemm_mainloop<E, Cfg>(la, lb, cdiv(na, E::BK), acc, smem);
-  }
-  IOT<P>* Jn = (IOT<P>*)a.Jn;
-  acc.for_each([&](int m, int n, double v) {
-    const int q = q0 + m, mu = mu0 + n / TNU, nu = nu0 + n % TNU;
-    if (q < nw && mu < nb && nu < nb) {
-      IOT<P>* J = Jn + (long)q * B2;
-      if (mu <= nu) J[(long)mu * nb + nu] = (IOT<P>)v;
-      if (mu < nu) J[(long)nu * nb + mu] = (IOT<P>)v;
+    if constexpr (kTrim && kPieces<P> == 0) {
+      run_q_rows<P, Cfg, kTrim>(fim, acc, [&](auto mma) {
+        gemm_mainloop_with<E, Cfg>(la, lb, cdiv(na, E::BK), acc, smem, false, mma);
+      }, store);
+      return;
+    } else {
+      gemm_mainloop<E, Cfg>(la, lb, cdiv(na, E::BK), acc, smem);
     }
-  });
+  }
+  acc.for_each(store);
 }
+
+template <int P, class Cfg>
+__device__ void jao_g_tile(const JaoArgs& a, long t, char* smem) { jao_tile<P, Cfg, true>(a, t, smem); }
 
 // The same J^q tile with b read as pre-split piece planes (split modes):
 // B element (x = (mu, nu) of the block, k = l) at plane row mu*n_bf + nu, and
@@ -1033,7 +1099,7 @@ __device__ __forceinline__ int find_owner(const long* __restrict__ off, int n, l
   return lo;
 }
 
-#define RIF_STEP_KERNELS(NAME, ARGS, SMEM_BYTES, NTHREADS, REMAP, WPE)                             \
+#define RIF_STEP_KERNELS(NAME, ARGS, SMEM_BYTES, NTHREADS, REMAP, WPE, GWPE, GTILE)                \
   template <int P, class Cfg>                                                                      \
   __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(WPE))) void k_##NAME(  \
       ARGS a) {                                                                                    \
@@ -1042,13 +1108,12 @@ __device__ __forceinline__ int find_owner(const long* __restrict__ off, int n, l
     NAME##_tile<P, Cfg>(a, t, smem);                                                               \
   }                                                                                                \
   template <int P, class Cfg>                                                                      \
-  __global__ __launch_bounds__(NTHREADS) void k_##NAME##_g(const ARGS* __restrict__ a,             \
-                                                           const long* __restrict__ off, int n,    \
-                                                           long total) {                           \
+  __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(GWPE))) void k_##NAME##_g( \
+      const ARGS* __restrict__ a, const long* __restrict__ off, int n, long total) {               \
     __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES];                                 \
     for (long t = blockIdx.x; t < total; t += gridDim.x) {                                         \
       const int i = find_owner(off, n, t);                                                         \
-      NAME##_tile<P, Cfg>(a[i], t - off[i], smem);                                                 \
+      GTILE<P, Cfg>(a[i], t - off[i], smem);                                                       \
     }                                                                                              \
   }
 
@@ -1056,34 +1121,36 @@ __device__ __forceinline__ int find_owner(const long* __restrict__ off, int n, l
 // accumulators allow it: FP64 8-wave tiles are held to 128 VGPRs (4 waves per
 // SIMD); FP32 (FP32 partial and FP64 folded accumulators) and split-BF16
 // (three accumulator sets) 8-wave tiles to 256.  The grouped kernels (which
-// also carry the work-list search) are left to the compiler.
+// also carry the work-list search) are left to the compiler (GWPE 1), except
+// the half transform and J^q, whose trimmed q-tiles (GTILE) would otherwise
+// take FP64 past 128 VGPRs and one workgroup per CU.
 template <int P, class Cfg>
 constexpr int gemm_wpe() {
   return Cfg::NT == 1024 ? 4 : Cfg::NT == 512 ? (P == kF64 ? 4 : 2) : 1;
 }
 #define GEMM_SMEM smem_bytes<typename EngineOf<P>::type, Cfg>()
 #define GEMM_WPE (gemm_wpe<P, Cfg>())
-RIF_STEP_KERNELS(half, HalfArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
+RIF_STEP_KERNELS(half, HalfArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE, GEMM_WPE, half_g_tile)
 // the pre-split half transform and J^q stage piece planes directly (split modes)
 #define GEMM_SMEM_DMA \
   (kPieces<P> > 0 ? smem_bytes_dma<typename EngineOf<P>::type, Cfg>() : smem_bytes<typename EngineOf<P>::type, Cfg>())
-RIF_STEP_KERNELS(halfp, HalfArgs, GEMM_SMEM_DMA, Cfg::NT, false, GEMM_WPE)
-RIF_STEP_KERNELS(mo, MoArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
-RIF_STEP_KERNELS(jao, JaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE)
-RIF_STEP_KERNELS(jaop, JaoArgs, GEMM_SMEM_DMA, Cfg::NT, true, GEMM_WPE)
-RIF_STEP_KERNELS(kao, KaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE)
-RIF_STEP_KERNELS(gemm, GemmArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
-RIF_STEP_KERNELS(fock, FockArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
-RIF_STEP_KERNELS(yd, YdArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE)
-RIF_STEP_KERNELS(ydz, YdzArgs, kYdzLds * 8, 256, false, 1)
-RIF_STEP_KERNELS(jkp, JkArgs, 16, 256, false, 1)
-RIF_STEP_KERNELS(jkr, JkArgs, 16, 256, false, 1)
-RIF_STEP_KERNELS(coef, CoefArgs, 256 * 8, 256, false, 1)
-RIF_STEP_KERNELS(energy, EnergyArgs, kEnergySmem, kEnergyThreads, false, 1)
-RIF_STEP_KERNELS(fred, FockRedArgs, 16, 256, false, 1)
-RIF_STEP_KERNELS(grad, GradArgs, 16, 256, false, 1)
-RIF_STEP_KERNELS(psplit, PSplitArgs, 16, 256, false, 1)
-RIF_STEP_KERNELS(bsplit, BSplitArgs, 16, 256, false, 1)
+RIF_STEP_KERNELS(halfp, HalfArgs, GEMM_SMEM_DMA, Cfg::NT, false, GEMM_WPE, GEMM_WPE, halfp_g_tile)
+RIF_STEP_KERNELS(mo, MoArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE, 1, mo_tile)
+RIF_STEP_KERNELS(jao, JaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE, GEMM_WPE, jao_g_tile)
+RIF_STEP_KERNELS(jaop, JaoArgs, GEMM_SMEM_DMA, Cfg::NT, true, GEMM_WPE, 1, jaop_tile)
+RIF_STEP_KERNELS(kao, KaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE, 1, kao_tile)
+RIF_STEP_KERNELS(gemm, GemmArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE, 1, gemm_tile)
+RIF_STEP_KERNELS(fock, FockArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE, 1, fock_tile)
+RIF_STEP_KERNELS(yd, YdArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE, 1, yd_tile)
+RIF_STEP_KERNELS(ydz, YdzArgs, kYdzLds * 8, 256, false, 1, 1, ydz_tile)
+RIF_STEP_KERNELS(jkp, JkArgs, 16, 256, false, 1, 1, jkp_tile)
+RIF_STEP_KERNELS(jkr, JkArgs, 16, 256, false, 1, 1, jkr_tile)
+RIF_STEP_KERNELS(coef, CoefArgs, 256 * 8, 256, false, 1, 1, coef_tile)
+RIF_STEP_KERNELS(energy, EnergyArgs, kEnergySmem, kEnergyThreads, false, 1, 1, energy_tile)
+RIF_STEP_KERNELS(fred, FockRedArgs, 16, 256, false, 1, 1, fred_tile)
+RIF_STEP_KERNELS(grad, GradArgs, 16, 256, false, 1, 1, grad_tile)
+RIF_STEP_KERNELS(psplit, PSplitArgs, 16, 256, false, 1, 1, psplit_tile)
+RIF_STEP_KERNELS(bsplit, BSplitArgs, 16, 256, false, 1, 1, bsplit_tile)
 
 // ---------------------------------------------------------------------------
 // Launchers.  Each GEMM-shaped step exists in four tile variants per mode:
