@@ -1162,7 +1162,7 @@ RIF_STEP_KERNELS(bsplit, BSplitArgs, 16, 256, false, 1, 1, bsplit_tile)
 template <int BK> struct Vars;
 template <> struct Vars<16> {  // FP64 / FP32 engines: 8 waves (measured ~10% over 4 at these shapes)
   using V0 = TileCfg<128, 128, 16, 64, 32>;
-  using V1 = TileCfg<64, 64, 16, 16, 32>;
+  using V1 = TileCfg<64, 64, 16, 32, 16>;
   using V2 = TileCfg<128, 64, 16, 32, 32>;
   using V3 = TileCfg<64, 128, 16, 32, 32>;
 };
