@@ -265,8 +265,46 @@ __device__ void half_tile_with(const HalfArgs& a, long t, char* smem) {
 // keeps its own register budget.
 template <int P, class Cfg>
 __device__ void half_tile(const HalfArgs& a, long t, char* smem) { half_tile_with<P, Cfg, false, false>(a, t, smem); }
+// The single-molecule pre-split half transform in the split modes runs
+// persistent workgroups (one per resident slot, tiles strided by the grid),
+// whose direct loads run ahead into the next tile while a tile's epilogue
+// stores: each workgroup holds all of a CU's LDS, so a workgroup per tile left
+// every tile boundary with the load pipe empty.  Results are bitwise those of
+// one workgroup per tile (the same slices in the same order).
 template <int P, class Cfg>
-__device__ void halfp_tile(const HalfArgs& a, long t, char* smem) { half_tile_with<P, Cfg, true, false>(a, t, smem); }
+__device__ void halfp_persistent(const HalfArgs& a, long first, char* smem) {
+  using E = typename EngineOf<P>::type;
+  using LA = PDMA<P, Cfg::BM, Cfg::NT>;
+  using LB = PDMA<P, Cfg::BN, Cfg::NT>;
+  const int nb = a.nb, nw = a.nw;
+  const long nr = a.nr;
+  const int nqt = cdiv(nw, Cfg::BM);
+  IOT<P>* bh = (IOT<P>*)a.bh;
+  gemm_persistent_dma<E, Cfg, 0, LA, LB>(
+      first, (long)gridDim.x, half_tiles<P, Cfg>(a), cdiv(nb, E::BK), smem,
+      [&](long t, LA& la, LB& lb) {
+        const int q0 = (int)(t % nqt) * Cfg::BM;
+        const long r0 = (t / nqt) * Cfg::BN;
+        la.init(a.Cs.p, a.Cs.ps, a.Cs.ld, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
+        lb.init(a.Bs.p, a.Bs.ps, a.Bs.ld, [&](int x, long& o) { o = r0 + x; return r0 + x < nr; });
+      },
+      [&](long t, const typename E::template Acc<Cfg>& acc) {
+        const int q0 = (int)(t % nqt) * Cfg::BM;
+        const long r0 = (t / nqt) * Cfg::BN;
+        acc.for_each([&](int m, int n, double v) {
+          const int q = q0 + m;
+          const long r = r0 + n;
+          if (q < nw && r < nr) bh[(long)q * nr + r] = (IOT<P>)v;
+        });
+      });
+}
+template <int P, class Cfg>
+__device__ void halfp_tile(const HalfArgs& a, long t, char* smem) {
+  if constexpr (kPieces<P> > 0)
+    halfp_persistent<P, Cfg>(a, t, smem);
+  else
+    half_tile_with<P, Cfg, true, false>(a, t, smem);
+}
 template <int P, class Cfg>
 __device__ void half_g_tile(const HalfArgs& a, long t, char* smem) { half_tile_with<P, Cfg, false, true>(a, t, smem); }
 template <int P, class Cfg>
@@ -1232,6 +1270,37 @@ template <class Cfg> static double useful_fock(const FockArgs& a) {
   return (double)a.nb * a.nw / ((double)cdiv(a.nb, Cfg::BM) * Cfg::BM * cdiv(a.nw, Cfg::BN) * Cfg::BN);
 }
 
+// Launch grid of a single-molecule step: one workgroup per tile, except the
+// persistent pre-split half transform of the split modes (one per resident
+// slot, from the compiled kernel's occupancy).
+#define RIF_TILE_GRID(NAME, ARGS) \
+  template <int P, class Cfg>     \
+  static long NAME##_grid(const ARGS& a) { return NAME##_tiles<P, Cfg>(a); }
+RIF_TILE_GRID(half, HalfArgs)
+RIF_TILE_GRID(mo, MoArgs)
+RIF_TILE_GRID(jao, JaoArgs)
+RIF_TILE_GRID(jaop, JaoArgs)
+RIF_TILE_GRID(kao, KaoArgs)
+RIF_TILE_GRID(fock, FockArgs)
+template <int P, class Cfg>
+static long halfp_grid(const HalfArgs& a) {
+  const long n = halfp_tiles<P, Cfg>(a);
+  if constexpr (kPieces<P> > 0) {
+    static int per_cu = 0;
+    if (per_cu == 0) {
+      int v = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, (const void*)&k_halfp<P, Cfg>, Cfg::NT, 0) != hipSuccess ||
+          v < 1) {
+        (void)hipGetLastError();
+        v = 1;
+      }
+      per_cu = v;
+    }
+    return std::min(n, 256L * per_cu);
+  }
+  return n;
+}
+
 // Single-molecule launch of a GEMM-shaped step with variant selection.
 #define RIF_GEMM_STEP(NAME, ARGS, LABEL, NVAR, ...)                                                     \
   template <int P>                                                                                      \
@@ -1242,7 +1311,7 @@ template <class Cfg> static double useful_fock(const FockArgs& a) {
         if constexpr (NVAR == 2 && Cfg::BM != Cfg::BN) {                                                \
           return fail(c, RIF_ENOTSUP, LABEL ": non-square tile variant");                               \
         } else {                                                                                        \
-          hipLaunchKernelGGL((k_##NAME<P, Cfg>), dim3((unsigned)NAME##_tiles<P, Cfg>(a)), dim3(Cfg::NT), \
+          hipLaunchKernelGGL((k_##NAME<P, Cfg>), dim3((unsigned)NAME##_grid<P, Cfg>(a)), dim3(Cfg::NT),  \
                              0, c->stream, a);                                                          \
           return check_launch(c, LABEL);                                                                \
         }                                                                                               \

@@ -958,6 +958,80 @@ __device__ __forceinline__ void gemm_mainloop_dma_with(const LA& la, const LB& l
   __builtin_amdgcn_s_barrier();
 }
 
+// Persistent form of the direct-staged main loop: one workgroup computes the
+// tiles t = first, first + step, ... below n.  make(t, la, lb) points the
+// loaders at tile t and epi(t, acc) stores its result.  The loads keep running
+// S-1 slices ahead across tile boundaries, so the next tile's first slices are
+// in flight while this tile's epilogue stores, and no tile starts from empty
+// stages.  The first slice of each later tile waits for all memory operations
+// (the epilogue's stores are counted with the loads and need not retire in
+// order with them); within a tile the waits are those of the single-tile loop.
+template <class E, class Cfg, int S_, class LA, class LB, class Make, class Epi>
+__device__ __forceinline__ void gemm_persistent_dma(long first, long step, long n, int nk, char* smem_generic,
+                                                    Make&& make, Epi&& epi) {
+  constexpr int S = S_ > 0 ? S_ : dma_stages<E, Cfg>();
+  static_assert(S >= 2, "two stages at least");
+  constexpr int SA = E::template stage_bytes<Cfg::BM>();
+  constexpr int ST = SA + E::template stage_bytes<Cfg::BN>();
+  lds_char* smem = (lds_char*)smem_generic;
+  if (first >= n) return;
+  typename E::template Acc<Cfg> acc;
+  if (nk <= 0) {
+    for (long t = first; t < n; t += step) {
+      acc.zero();
+      epi(t, acc);
+    }
+    return;
+  }
+  LA la;
+  LB lb;
+  long it = first;   // tile and slice of the next loads
+  int ik = 0;
+  make(it, la, lb);
+  const int per_slice = la.count() + lb.count();
+  // loads of the next slice in order; past the last tile they re-read the
+  // last slice into a stage nobody reads, keeping the count per slice fixed
+  auto issue_next = [&](lds_char* st) {
+    if (it < n) {
+      la.issue(ik, st);
+      lb.issue(ik, st + SA);
+      if (++ik == nk) {
+        ik = 0;
+        it += step;
+        if (it < n) make(it, la, lb);
+      }
+    } else {
+      la.issue(nk - 1, st);
+      lb.issue(nk - 1, st + SA);
+    }
+  };
+#pragma unroll
+  for (int j = 0; j < S - 1; ++j) issue_next(smem + j * ST);
+  long g = 0;   // slices computed so far (the stage ring position)
+  for (long t = first; t < n; t += step) {
+    acc.zero();
+    for (int kt = 0; kt < nk; ++kt, ++g) {
+      if (kt == 0 && t != first)
+        wait_vmcnt(0);
+      else
+        wait_vmcnt((S - 2) * per_slice);
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+      issue_next(smem + (int)((g + S - 1) % S) * ST);
+      const lds_char* sc = smem + (int)(g % S) * ST;
+      E::template mma<Cfg>(sc, sc + SA, acc, regular_plan<Cfg>());
+      if ((kt + 1) % E::CHUNK == 0) acc.flush();
+    }
+    acc.flush();
+    epi(t, acc);
+  }
+  // no load may still write LDS when the workgroup ends
+  wait_vmcnt(0);
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+}
+
 template <class E, class Cfg, int S_ = 0, class LA, class LB>
 __device__ __forceinline__ void gemm_mainloop_dma(const LA& la, const LB& lb, int nk,
                                                   typename E::template Acc<Cfg>& acc, char* smem_generic) {
