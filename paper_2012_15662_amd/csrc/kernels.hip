@@ -469,7 +469,7 @@ __device__ void jao_g_tile(const JaoArgs& a, long t, char* smem) { jao_tile<P, C
 template <int P, class Cfg>
 __host__ __device__ inline long jaop_tiles(const JaoArgs& a) { return jao_tiles<P, Cfg>(a); }
 template <int P, class Cfg>
-__device__ void jaop_tile(const JaoArgs& a, long t, char* smem) {
+__device__ void jaop_one_tile(const JaoArgs& a, long t, char* smem) {
   using E = typename EngineOf<P>::type;
   constexpr int TNU = kJaoTNU, TMU = Cfg::BN / TNU;
   const int nb = a.nb, na = a.na, nw = a.nw;
@@ -509,6 +509,71 @@ __device__ void jaop_tile(const JaoArgs& a, long t, char* smem) {
     }
   });
 }
+
+// The single-molecule J^q from piece planes runs persistent workgroups like
+// the pre-split half transform (one per resident slot, loads running ahead
+// into the next tile).  Workgroups are dispatched round-robin over the 8 XCDs;
+// those of one XCD take a contiguous eighth of the tile list, so tiles that
+// share b blocks run on one L2.  Bitwise the results of jaop_one_tile (the
+// grouped kernel's per-tile form).
+template <int P, class Cfg>
+__device__ void jaop_persistent(const JaoArgs& a, char* smem) {
+  using E = typename EngineOf<P>::type;
+  using LA = PDMA<P, Cfg::BM, Cfg::NT>;
+  using LB = PDMA<P, Cfg::BN, Cfg::NT>;
+  constexpr int TNU = kJaoTNU, TMU = Cfg::BN / TNU;
+  const int nb = a.nb, na = a.na, nw = a.nw;
+  const int nbj = cdiv(nb, TNU), nbi = cdiv(nb, TMU);
+  const long nq = cdiv(nw, Cfg::BM);
+  const long B2 = (long)nb * nb;
+  const long n = jaop_tiles<P, Cfg>(a), G = gridDim.x, w = blockIdx.x;
+  long first = w, step = G, end = n;
+  if (G % 8 == 0 && n >= G) {
+    const long x = w % 8;
+    first = x * n / 8 + w / 8;
+    step = G / 8;
+    end = (x + 1) * n / 8;
+  }
+  auto decode = [&](long t, int& q0, int& mu0, int& nu0) {
+    q0 = (int)(t % nq) * Cfg::BM;
+    long r = t / nq;
+    int bi = 0;
+    for (; bi < nbi; ++bi) {
+      const int m = nbj - jao_first_col(bi, TMU, TNU);
+      if (r < m) break;
+      r -= m;
+    }
+    mu0 = bi * TMU;   // bi == nbi only past the list: then nothing is stored
+    nu0 = (bi < nbi ? jao_first_col(bi, TMU, TNU) + (int)r : 0) * TNU;
+  };
+  IOT<P>* Jn = (IOT<P>*)a.Jn;
+  gemm_persistent_dma<E, Cfg, 0, LA, LB>(
+      first, step, end, cdiv(na, E::BK), smem,
+      [&](long t, LA& la, LB& lb) {
+        int q0, mu0, nu0;
+        decode(t, q0, mu0, nu0);
+        la.init(a.Ds.p, a.Ds.ps, a.Ds.ld, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
+        lb.init(a.Bj.p, a.Bj.ps, a.Bj.ld, [&](int x, long& o) {
+          const int mu = mu0 + x / TNU, nu = nu0 + x % TNU;
+          o = (long)mu * nb + nu;
+          return mu < nb && nu < nb;
+        });
+      },
+      [&](long t, const typename E::template Acc<Cfg>& acc) {
+        int q0, mu0, nu0;
+        decode(t, q0, mu0, nu0);
+        acc.for_each([&](int m, int nn, double v) {
+          const int q = q0 + m, mu = mu0 + nn / TNU, nu = nu0 + nn % TNU;
+          if (q < nw && mu < nb && nu < nb) {
+            IOT<P>* J = Jn + (long)q * B2;
+            if (mu <= nu) J[(long)mu * nb + nu] = (IOT<P>)v;
+            if (mu < nu) J[(long)nu * nb + mu] = (IOT<P>)v;
+          }
+        });
+      });
+}
+template <int P, class Cfg>
+__device__ void jaop_tile(const JaoArgs& a, long, char* smem) { jaop_persistent<P, Cfg>(a, smem); }
 
 // Per-MO AO exchange: Kn[q] = X_q^T X_q with X_q = b_half[q] ([n_aux][n_bf]).
 // Square blocks bi <= bj only (the blocks of one q adjacent), mirrored like J.
@@ -1175,7 +1240,7 @@ RIF_STEP_KERNELS(half, HalfArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE, GEMM_WPE, 
 RIF_STEP_KERNELS(halfp, HalfArgs, GEMM_SMEM_DMA, Cfg::NT, false, GEMM_WPE, GEMM_WPE, halfp_g_tile)
 RIF_STEP_KERNELS(mo, MoArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE, 1, mo_tile)
 RIF_STEP_KERNELS(jao, JaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE, GEMM_WPE, jao_g_tile)
-RIF_STEP_KERNELS(jaop, JaoArgs, GEMM_SMEM_DMA, Cfg::NT, true, GEMM_WPE, 1, jaop_tile)
+RIF_STEP_KERNELS(jaop, JaoArgs, GEMM_SMEM_DMA, Cfg::NT, false, GEMM_WPE, 1, jaop_one_tile)
 RIF_STEP_KERNELS(kao, KaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE, 1, kao_tile)
 RIF_STEP_KERNELS(gemm, GemmArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE, 1, gemm_tile)
 RIF_STEP_KERNELS(fock, FockArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE, 1, fock_tile)
@@ -1271,34 +1336,40 @@ template <class Cfg> static double useful_fock(const FockArgs& a) {
 }
 
 // Launch grid of a single-molecule step: one workgroup per tile, except the
-// persistent pre-split half transform of the split modes (one per resident
-// slot, from the compiled kernel's occupancy).
+// persistent pre-split half transform and J^q of the split modes (one per
+// resident slot, from the compiled kernel's occupancy).
 #define RIF_TILE_GRID(NAME, ARGS) \
   template <int P, class Cfg>     \
   static long NAME##_grid(const ARGS& a) { return NAME##_tiles<P, Cfg>(a); }
 RIF_TILE_GRID(half, HalfArgs)
 RIF_TILE_GRID(mo, MoArgs)
 RIF_TILE_GRID(jao, JaoArgs)
-RIF_TILE_GRID(jaop, JaoArgs)
 RIF_TILE_GRID(kao, KaoArgs)
 RIF_TILE_GRID(fock, FockArgs)
+template <int P, class Cfg, class KernelOf>
+static long resident_grid(long n, KernelOf kernel_of) {
+  static int per_cu = 0;
+  if (per_cu == 0) {
+    int v = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, kernel_of(), Cfg::NT, 0) != hipSuccess || v < 1) {
+      (void)hipGetLastError();
+      v = 1;
+    }
+    per_cu = v;
+  }
+  return std::min(n, 256L * per_cu);
+}
 template <int P, class Cfg>
 static long halfp_grid(const HalfArgs& a) {
   const long n = halfp_tiles<P, Cfg>(a);
-  if constexpr (kPieces<P> > 0) {
-    static int per_cu = 0;
-    if (per_cu == 0) {
-      int v = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, (const void*)&k_halfp<P, Cfg>, Cfg::NT, 0) != hipSuccess ||
-          v < 1) {
-        (void)hipGetLastError();
-        v = 1;
-      }
-      per_cu = v;
-    }
-    return std::min(n, 256L * per_cu);
-  }
+  if constexpr (kPieces<P> > 0)
+    return resident_grid<P, Cfg>(n, [] { return (const void*)&k_halfp<P, Cfg>; });
   return n;
+}
+// every J^q from piece planes is persistent (the kernel exists in the split modes only)
+template <int P, class Cfg>
+static long jaop_grid(const JaoArgs& a) {
+  return resident_grid<P, Cfg>(jaop_tiles<P, Cfg>(a), [] { return (const void*)&k_jaop<P, Cfg>; });
 }
 
 // Single-molecule launch of a GEMM-shaped step with variant selection.
