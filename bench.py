@@ -37,7 +37,7 @@ HBM_GBS = 8000.0
 # were taken on: a figure is reported only while those sources are unchanged.
 # The runs and their command lines are in profiles/.
 TRAFFIC = {
-    ("half_transform", "c6h12", "fp64"): {"src": "5059f52773f7b900", "fetch": 1173758560, "write": 348779520,
+    ("half_transform", "c6h12", "fp64"): {"src": "8b7b856bc376a688", "fetch": 1173748653, "write": 348779520,
                                          "profile": "profiles/fp64_c6h12_counters.md"},
 }
 
