@@ -59,6 +59,28 @@ def test_batch_equals_single_and_oracle(ctx, variant):
         ctx.set_tile_variant(-1)
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_fp32_batch_equals_single(ctx, variant):
+    """FP32 grouped launches (whose q-tiles with few live rows run trimmed)
+    against the single builds of the same variant, bit for bit."""
+    import paper_2012_15662_amd as rif
+    ctx.set_tile_variant(variant)
+    try:
+        insts, items = make_items(rif.FP32)
+        batch = ctx.batch(items, prec=rif.FP32)
+        batch.run(use_graph=False)
+        ctx.sync()
+        for inst, (inp, npair, ncwo, _), out in zip(insts, items, batch.outs):
+            print(f"case fp32 variant={variant} n_bf={inst.n_bf} pairs={npair}", flush=True)
+            single = ctx.build_instance(inp, npair, ncwo, prec=rif.FP32)
+            ctx.sync()
+            for k in KEYS:
+                assert np.array_equal(host(out[k]), host(single[k])), k
+        batch.close()
+    finally:
+        ctx.set_tile_variant(-1)
+
+
 @pytest.mark.parametrize("prec", [0, 3, 4])
 def test_graph_replays(ctx, prec):
     import torch
