@@ -102,7 +102,9 @@ inline int half_dma_ok(int nb, int nmo, int nw, const double* b, const double* C
 // b symmetric) into the mode's pieces, rows zero-filled from n_bf up to ld;
 // FP32 mode: a float copy.
 struct BSplitArgs { const double* b; long nr; int nb, ld; void* out; long ps; };
-struct MoArgs { int nb, na, nw, nmo; const void* bh; const double* C; void* bmo; double* d; Planes Cs; };
+// dma: FP64 128 x 128 tiles stage b_half and C_Omega by direct global -> LDS
+// loads (even n_bf and n_mo, 16-byte aligned b_half and C).
+struct MoArgs { int nb, na, nw, nmo; const void* bh; const double* C; void* bmo; double* d; Planes Cs; int dma; };
 // Bj: b pre-split for J^q (piece planes with rows r = mu*n_bf + nu and
 // k = l contiguous), or unset (split on load).
 // dma: FP64 operands staged by direct global -> LDS loads in the 128 x 128
@@ -322,6 +324,46 @@ template <int P, class Cfg>
 __host__ __device__ inline long mo_tiles(const MoArgs& a) {
   return (long)cdiv(a.nw, Cfg::BN) * cdiv((long)a.na * a.nw, Cfg::BM);
 }
+// FP64 slice of MFMAs with A in the swizzled [x][k] layout of KcDma64 and B in
+// the engine's padded [k][x] layout.  Lane group kr of MFMA step (h, m) takes
+// k = 2(kr + 4h) + m, so each lane reads its two A values of a step pair as
+// one 16-byte chunk (eight lanes of one k group read eight rows' chunks in
+// distinct bank slots); B is read at the same k.  Every k of the slice is
+// summed once per slice, in a fixed order.
+template <class Cfg>
+__device__ __forceinline__ void mma_xk_f64(const lds_char* SA, const lds_char* SB,
+                                           typename EngF64::template Acc<Cfg>& acc) {
+  using E = EngF64;
+  const lds_f64* As = (const lds_f64*)SA;
+  const lds_f64* Bs = (const lds_f64*)SB;
+  const int lane = threadIdx.x & 63, kr = lane >> 4, xc = lane & 15;
+  int wm0, wn0;
+  wave_origin(Cfg::WAVES_N, Cfg::WM, Cfg::WN, wm0, wn0);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c = kr + 4 * h;   // chunk: k = 2c, 2c + 1
+    double a0[Cfg::TM], a1[Cfg::TM];
+#pragma unroll
+    for (int i = 0; i < Cfg::TM; ++i) {
+      const int x = wm0 + i * 16 + xc;
+      const lds_f64* q = As + x * 16 + 2 * (c ^ (x & 7));
+      a0[i] = q[0];
+      a1[i] = q[1];
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      double b[Cfg::TN];
+#pragma unroll
+      for (int j = 0; j < Cfg::TN; ++j) b[j] = Bs[(2 * c + m) * (Cfg::BN + E::PAD) + wn0 + j * 16 + xc];
+#pragma unroll
+      for (int i = 0; i < Cfg::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < Cfg::TN; ++j)
+          acc.v[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(m ? a1[i] : a0[i], b[j], acc.v[i][j], 0, 0, 0);
+    }
+  }
+}
+
 template <int P, class Cfg>
 __device__ void mo_tile(const MoArgs& a, long t, char* smem) {
   using E = typename EngineOf<P>::type;
@@ -334,6 +376,32 @@ __device__ void mo_tile(const MoArgs& a, long t, char* smem) {
   const IOT<P>* bh = (const IOT<P>*)a.bh;
   IOT<P>* bmo = (IOT<P>*)a.bmo;
   double* d = a.d;
+  if constexpr (P == kF64 && Cfg::BM == 128 && Cfg::BN == 128) {
+    if (a.dma) {   // b_half rows into the swizzled [x][k] layout, C_Omega into [k][x], both by direct loads
+      KcDma64<Cfg::NT, E::BK, Cfg::BM> la;
+      la.init([&](int x) -> const double* {
+        const long s = s0 + x;
+        if (s >= ns) return nullptr;
+        const long l = s / nw, p = s - l * nw;
+        return (const double*)bh + p * AB + l * nb;
+      }, (const double*)bh, nb);
+      XcDma64<Cfg::NT, E::BK, E::PAD> lb;
+      lb.init(a.C, a.nmo, nb, [&](int x, long& o) { o = q0 + x; return q0 + x < nw; });
+      typename E::template Acc<Cfg> acc;
+      gemm_mainloop_dma_with<E, Cfg, 2>(la, lb, cdiv(nb, E::BK), acc, smem, false,
+                                        [&](const lds_char* SA, const lds_char* SB,
+                                            typename E::template Acc<Cfg>& c) { mma_xk_f64<Cfg>(SA, SB, c); });
+      acc.for_each([&](int m, int n, double v) {
+        const long s = s0 + m;
+        const int q = q0 + n;
+        if (s < ns && q < nw) {
+          bmo[s * nw + q] = v;
+          if (s % nw == q) d[s] = v;
+        }
+      });
+      return;
+    }
+  }
   KCS<P, IOT<P>, Cfg::BM, Cfg::NT> la;
   la.init([&](int x) -> const IOT<P>* {
     const long s = s0 + x;
@@ -1607,7 +1675,8 @@ static BuildArgs make_build_args(const Plan& pl, const rif_instance& in, int pre
   } else if (in.b_split && prec == RIF_FP32) {
     A.half.bf = (const float*)in.b_split;
   }
-  A.mo = MoArgs{nb, na, nw, nmo, in.b_half, in.C, in.b_mo, in.d, cs};
+  A.mo = MoArgs{nb, na, nw, nmo, in.b_half, in.C, in.b_mo, in.d, cs,
+                nb % 2 == 0 && nmo % 2 == 0 && ((uintptr_t)in.b_half | (uintptr_t)in.C) % 16 == 0};
   A.jk = JkArgs{na, nw, pl.jk_nsplit, in.b_mo, in.d, part, in.J, in.K};
   A.jao = JaoArgs{nb, na, nw, in.b, in.d, in.Jn, ds, Planes{nullptr, 0, 0},
                   nb % 2 == 0 && nw % 2 == 0 && ((uintptr_t)in.b | (uintptr_t)in.d) % 16 == 0};
@@ -1685,7 +1754,8 @@ rif_status op_transform(rif_ctx* c, int prec, int nb, int na, int nw, int nmo, c
   const Planes cs{Cs, (long)nw * lc, lc};
   const PSplitArgs ps{C, (long)nmo, nw, nb, lc, Cs, (long)nw * lc};
   const HalfArgs h{nb, nw, nmo, (long)na * nb, b, C, bh, cs, Planes{}, nullptr, half_dma_ok(nb, nmo, nw, b, C)};
-  const MoArgs m{nb, na, nw, nmo, bh, C, bmo, d, cs};
+  const MoArgs m{nb, na, nw, nmo, bh, C, bmo, d, cs,
+                 nb % 2 == 0 && nmo % 2 == 0 && ((uintptr_t)bh | (uintptr_t)C) % 16 == 0};
   RIF_PREC_SWITCH(prec, run_transform<P>(c, ps, h, m))
 }
 

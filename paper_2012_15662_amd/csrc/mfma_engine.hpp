@@ -958,6 +958,49 @@ __device__ __forceinline__ void gemm_mainloop_dma_with(const LA& la, const LB& l
   __builtin_amdgcn_s_barrier();
 }
 
+// FP64 k-contiguous operand (element (x, k) at row(x)[k]) staged by direct
+// global -> LDS loads into a [x][k] layout of BX rows of BK doubles (128 bytes
+// per row at BK = 16, no padding) whose 16-byte chunks, two k each, are
+// swizzled per row: chunk c of row x sits in slot c ^ (x % 8).  One wave
+// instruction fills eight rows (1 KB); each lane loads the chunk that the
+// swizzle puts in its slot, so eight lanes read one row's 128 contiguous bytes.
+// Chunks at or past K read zeros (K even, so a chunk is all in or all out);
+// a row that does not exist reads row `fallback` (its outputs are never
+// stored).  Needs 16-byte aligned rows.  mma_xk_f64 reads this layout.
+template <int NT, int BK, int BX>
+struct KcDma64 {
+  static_assert(BK == 16, "eight chunks per row");
+  static constexpr int NW = NT / 64, ROWS = 8;            // rows per wave instruction
+  static constexpr int NI = BX / (NW * ROWS);              // instructions per wave per slice
+  static_assert(BX % (NW * ROWS) == 0, "whole row groups per wave");
+  const double* src[NI];   // this lane's row base plus its chunk's first k
+  int kc[NI];              // the chunk's first k within a slice
+  int K;
+  template <class RowPtr>
+  __device__ void init(RowPtr rowptr, const double* fallback, int K_) {
+    K = K_;
+    const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int x = (w + j * NW) * ROWS + lane / 8, slot = lane % 8, c = slot ^ (x & 7);
+      const double* r = rowptr(x);
+      src[j] = (r ? r : fallback) + 2 * c;
+      kc[j] = 2 * c;
+    }
+  }
+  __device__ int count() const { return NI; }
+  __device__ void issue(int kt, lds_char* S) const {
+    const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const double* g = kt * BK + kc[j] < K ? src[j] + kt * BK : kDmaZeros + 2 * (lane & 7);
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)g,
+                                       (__attribute__((address_space(3))) void*)(S + (w + j * NW) * ROWS * BK * 8),
+                                       16, 0, 0);
+    }
+  }
+};
+
 // Persistent form of the direct-staged main loop: one workgroup computes the
 // tiles t = first, first + step, ... below n.  make(t, la, lb) points the
 // loaders at tile t and epi(t, acc) stores its result.  The loads keep running
