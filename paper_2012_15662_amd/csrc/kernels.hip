@@ -124,11 +124,14 @@ struct GemmArgs {
   double* out; long ldo;
   int ksplit, kc; long ostride;
 };
+// dma: FP64 128 x 128 tiles stage J^q/K^q and C by direct global -> LDS loads
+// (even n_bf, n_omega and n_mo, 16-byte aligned Jn, Kn and C).
 struct FockArgs {
   int nb, nw, nmo, nsplit;
   const void *Jn, *Kn;
   const double *Ac, *Bc, *C;
   double* Yp;
+  int dma;
 };
 struct JkArgs { int na, nw, nsplit; const void* bmo; const double* d; double* part; double* J; double* K; };
 struct CoefArgs {
@@ -833,6 +836,34 @@ struct FockB {  // element (q, nu) of slab t: coef_t[q] * C[nu][q]; r[R] holds c
   __device__ double val(const double (&r)[RR], int p, int i) const { return r[R] * r[p * KV + i]; }
 };
 
+// FP64 Fock operands by direct global -> LDS loads (128 x 128 tiles, one
+// 128-column k-row per wave load into the engine's padded [k][x] layout).
+// Slice g of the stacked slabs holds rows nu0 .. nu0+15 of slab t = g / nchunk
+// (nu0 = 16 (g mod nchunk)); rows at or past n_bf read zeros.  A: element
+// (mu, nu) of slab t read as row nu of X_t (J^t or K^t, symmetric); B: row nu
+// of C (x = q), scaled by the slab's coefficient at MFMA time.
+template <int NT>
+struct FockDma {
+  static constexpr int NW = NT / 64, BK = 16, UPW = BK / NW, STRIDE = (128 + EngF64::PAD) * 8;
+  static_assert(BK % NW == 0, "k rows per wave");
+  const double *J, *K, *C;   // A: J, K (slabs of B2); B: C (J == nullptr)
+  long B2, ld;
+  int nb, nw, g0, nchunk, col;
+  __device__ int count() const { return UPW; }
+  __device__ void issue(int kt, lds_char* S) const {
+    const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int g = g0 + kt, t = g / nchunk, nu0 = (g - t * nchunk) * BK;
+    const double* base = J ? (t < nw ? J + (long)t * B2 : K + (long)(t - nw) * B2) : C;
+#pragma unroll
+    for (int j = 0; j < UPW; ++j) {
+      const int r = w + j * NW, nu = nu0 + r;
+      const double* src = nu < nb ? base + (long)nu * ld + col : kDmaZeros + 2 * lane;
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                       (__attribute__((address_space(3))) void*)(S + r * STRIDE), 16, 0, 0);
+    }
+  }
+};
+
 template <int P, class Cfg>
 __host__ __device__ inline long fock_tiles(const FockArgs& a) {
   return (long)cdiv(a.nb, Cfg::BM) * cdiv(a.nw, Cfg::BN) * a.nsplit;
@@ -847,6 +878,54 @@ __device__ void fock_tile(const FockArgs& a, long t, char* smem) {
   const int s = (int)(t / ((long)nmt * nnt));
   const long S = 2L * nw * cdiv(nb, E::BK);   // slices over all slabs
   const int g0 = (int)(S * s / a.nsplit), g1 = (int)(S * (s + 1) / a.nsplit);
+  if constexpr (P == kF64 && Cfg::BM == 128 && Cfg::BN == 128) {
+    if (a.dma) {
+      const int lane = (int)(threadIdx.x & 63), nchunk = cdiv(nb, E::BK);
+      FockDma<Cfg::NT> la{(const double*)a.Jn, (const double*)a.Kn, nullptr, (long)nb * nb, nb,
+                          nb, nw, g0, nchunk, mu0 + 2 * lane < nb ? mu0 + 2 * lane : 0};
+      FockDma<Cfg::NT> lb{nullptr, nullptr, a.C, 0, a.nmo, nb, nw, g0, nchunk, q0 + 2 * lane < nw ? q0 + 2 * lane : 0};
+      typename E::template Acc<Cfg> acc;
+      int kt = 0, tc = -1;
+      double cq[Cfg::TN];
+      int wm0, wn0;
+      wave_origin(Cfg::WAVES_N, Cfg::WM, Cfg::WN, wm0, wn0);
+      const int kr = lane >> 4, xc = lane & 15;
+      // B element (q, nu) = coef_t[q] * C[nu][q], the product the register
+      // path stages; the coefficients change once per slab
+      gemm_mainloop_dma_with<E, Cfg, 2>(la, lb, g1 - g0, acc, smem, false,
+                                        [&](const lds_char* SA, const lds_char* SB, typename E::template Acc<Cfg>& c) {
+        const int t = (g0 + kt++) / nchunk;
+        if (t != tc) {
+          tc = t;
+#pragma unroll
+          for (int j = 0; j < Cfg::TN; ++j) {
+            const int q = q0 + wn0 + j * 16 + xc;
+            cq[j] = q < nw ? (t < nw ? a.Ac[(long)q * nw + t] : a.Bc[(long)q * nw + (t - nw)]) : 0.0;
+          }
+        }
+        const lds_f64* As = (const lds_f64*)SA;
+        const lds_f64* Bs = (const lds_f64*)SB;
+#pragma unroll
+        for (int kk = 0; kk < E::BK; kk += 4) {
+          double av[Cfg::TM], bv[Cfg::TN];
+#pragma unroll
+          for (int i = 0; i < Cfg::TM; ++i) av[i] = As[(kk + kr) * (Cfg::BM + E::PAD) + wm0 + i * 16 + xc];
+#pragma unroll
+          for (int j = 0; j < Cfg::TN; ++j) bv[j] = cq[j] * Bs[(kk + kr) * (Cfg::BN + E::PAD) + wn0 + j * 16 + xc];
+#pragma unroll
+          for (int i = 0; i < Cfg::TM; ++i)
+#pragma unroll
+            for (int j = 0; j < Cfg::TN; ++j)
+              c.v[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], c.v[i][j], 0, 0, 0);
+        }
+      });
+      double* Y = a.Yp + (long)s * nb * nw;
+      acc.for_each([&](int m, int n, double v) {
+        if (mu0 + m < nb && q0 + n < nw) Y[(long)(mu0 + m) * nw + q0 + n] = v;
+      });
+      return;
+    }
+  }
   FockA<P, Cfg> la;
   la.init((const IOT<P>*)a.Jn, (const IOT<P>*)a.Kn, nb, nw, g0, mu0);
   FockB<P, Cfg> lb;
@@ -1294,7 +1373,8 @@ __device__ __forceinline__ int find_owner(const long* __restrict__ off, int n, l
 // (three accumulator sets) 8-wave tiles to 256.  The grouped kernels (which
 // also carry the work-list search) are left to the compiler (GWPE 1), except
 // the half transform and J^q, whose trimmed q-tiles (GTILE) would otherwise
-// take FP64 past 128 VGPRs and one workgroup per CU.
+// take FP64 past 128 VGPRs and one workgroup per CU, and Fock, whose
+// direct-staged path would.
 template <int P, class Cfg>
 constexpr int gemm_wpe() {
   return Cfg::NT == 1024 ? 4 : Cfg::NT == 512 ? (P == kF64 ? 4 : 2) : 1;
@@ -1311,7 +1391,7 @@ RIF_STEP_KERNELS(jao, JaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE, GEMM_WPE, jao
 RIF_STEP_KERNELS(jaop, JaoArgs, GEMM_SMEM_DMA, Cfg::NT, false, GEMM_WPE, 1, jaop_one_tile)
 RIF_STEP_KERNELS(kao, KaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE, 1, kao_tile)
 RIF_STEP_KERNELS(gemm, GemmArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE, 1, gemm_tile)
-RIF_STEP_KERNELS(fock, FockArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE, 1, fock_tile)
+RIF_STEP_KERNELS(fock, FockArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE, GEMM_WPE, fock_tile)
 RIF_STEP_KERNELS(yd, YdArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE, 1, yd_tile)
 RIF_STEP_KERNELS(ydz, YdzArgs, kYdzLds * 8, 256, false, 1, 1, ydz_tile)
 RIF_STEP_KERNELS(jkp, JkArgs, 16, 256, false, 1, 1, jkp_tile)
@@ -1691,7 +1771,9 @@ static BuildArgs make_build_args(const Plan& pl, const rif_instance& in, int pre
   A.coef = CoefArgs{functional, nw, pl.npairs, pl.ncwo, in.pair_of, in.occ, in.J, in.K, Ac, Bc, Ep};
   A.energy = EnergyArgs{nw, pl.npairs, pl.ncwo, nb, nmo, pl.nparts, in.pair_of, in.occ, in.C, HC, Ep, in.energy,
                         flag};
-  A.fock = FockArgs{nb, nw, nmo, pl.fock_nsplit, in.Jn, in.Kn, Ac, Bc, in.C, Yp};
+  A.fock = FockArgs{nb, nw, nmo, pl.fock_nsplit, in.Jn, in.Kn, Ac, Bc, in.C, Yp,
+                    nb % 2 == 0 && nw % 2 == 0 && nmo % 2 == 0 &&
+                        ((uintptr_t)in.Jn | (uintptr_t)in.Kn | (uintptr_t)in.C) % 16 == 0};
   A.fred = FockRedArgs{nb, nw, pl.fock_nsplit, Yp, in.occ, HC, Y};
   A.lam = GemmArgs{nmo, nw, nb, in.C, (long)nmo, Y, (long)nw, Lp, (long)nw, pl.lam_split, pl.small_kc,
                    (long)nmo * nw};
