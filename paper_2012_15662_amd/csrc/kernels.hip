@@ -689,7 +689,33 @@ __device__ void kao_tile(const KaoArgs& a, long t, char* smem) {
   constexpr int FB = Cfg::BM / 16;
   const int fim = min(FB, cdiv(nb - mu0, 16)), fjm = min(FB, cdiv(nb - nu0, 16));
   const bool diag = bi == bj;
-  if constexpr (P == kF64 && (Cfg::BM == 128 || Cfg::BM == 64)) {
+  if constexpr (P == kF64 && Cfg::BM == 64) {
+    if (a.dma) {   // unpadded rows, three stages (two slices in flight), three workgroups per CU
+      using E2 = EngF64T<16, 0>;
+      XcDma64<Cfg::NT, E2::BK, E2::PAD, 64> da, db;
+      da.init((const double*)X, nb, na, [&](int x, long& o) { o = mu0 + x; return mu0 + x < nb; });
+      db.init((const double*)X, nb, na, [&](int x, long& o) { o = nu0 + x; return nu0 + x < nb; });
+      typename E2::template Acc<Cfg> acc2;
+      if (!diag && fim == FB && fjm == FB) {
+        gemm_mainloop_dma<E2, Cfg, 3>(da, db, cdiv(na, E2::BK), acc2, smem);
+        acc2.for_each(store);
+        return;
+      }
+      const WavePlan w =
+          make_wave_plan<Cfg>([&](int I, int J) { return I < fim && J < fjm && (!diag || I <= J); });
+      with_rows<Cfg::TM>(w.ni, [&](auto rows) {
+        constexpr int NI = decltype(rows)::value;
+        gemm_mainloop_dma_with<E2, Cfg, 3>(da, db, cdiv(na, E2::BK), acc2, smem, diag,
+                                           [&](const lds_char* SA, const lds_char* SB,
+                                               typename E2::template Acc<Cfg>& c) {
+                                             E2::template mma_rows<Cfg, NI>(SA, SB, c, w);
+                                           });
+      });
+      acc2.for_each(w, store);
+      return;
+    }
+  }
+  if constexpr (P == kF64 && Cfg::BM == 128) {
     if (a.dma) {   // b_half by direct global -> LDS loads; a diagonal block stages one panel
       XcDma64<Cfg::NT, E::BK, E::PAD, Cfg::BM> da, db;
       da.init((const double*)X, nb, na, [&](int x, long& o) { o = mu0 + x; return mu0 + x < nb; });
@@ -1389,7 +1415,9 @@ RIF_STEP_KERNELS(halfp, HalfArgs, GEMM_SMEM_DMA, Cfg::NT, false, GEMM_WPE, GEMM_
 RIF_STEP_KERNELS(mo, MoArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE, 1, mo_tile)
 RIF_STEP_KERNELS(jao, JaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE, GEMM_WPE, jao_g_tile)
 RIF_STEP_KERNELS(jaop, JaoArgs, GEMM_SMEM_DMA, Cfg::NT, false, GEMM_WPE, 1, jaop_one_tile)
-RIF_STEP_KERNELS(kao, KaoArgs, GEMM_SMEM, Cfg::NT, true, GEMM_WPE, 1, kao_tile)
+// the FP64 64x64 K^q tile: three unpadded direct-load stages
+#define KAO_SMEM (P == kF64 && Cfg::BM == 64 ? 3 * 2 * EngF64T<16, 0>::template stage_bytes<64>() : GEMM_SMEM)
+RIF_STEP_KERNELS(kao, KaoArgs, KAO_SMEM, Cfg::NT, true, GEMM_WPE, 1, kao_tile)
 RIF_STEP_KERNELS(gemm, GemmArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE, 1, gemm_tile)
 RIF_STEP_KERNELS(fock, FockArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE, GEMM_WPE, fock_tile)
 RIF_STEP_KERNELS(yd, YdArgs, GEMM_SMEM, Cfg::NT, false, GEMM_WPE, 1, yd_tile)

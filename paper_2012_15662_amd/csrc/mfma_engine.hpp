@@ -242,9 +242,11 @@ __device__ __forceinline__ void with_rows(int ni, F&& f) {
 
 // ---------------------------------------------------------------------------
 // FP64 engine (BK_ = slice depth)
-template <int BK_ = 16>
+// PAD_: doubles of padding per LDS row (0 only for direct-staged 64-column
+// operands, whose fragment reads touch one row per 16 lanes).
+template <int BK_ = 16, int PAD_ = 16>
 struct EngF64T {
-  static constexpr int BK = BK_, KV = 1, PAD = 16, CHUNK = 1 << 30;
+  static constexpr int BK = BK_, KV = 1, PAD = PAD_, CHUNK = 1 << 30;
   template <int BX>
   static constexpr int stage_bytes() { return BK * (BX + PAD) * 8; }
   template <class Cfg>
@@ -557,7 +559,10 @@ static __device__ __attribute__((aligned(16))) double kDmaZeros[128];
 // FP64 x-contiguous operand staged by direct global -> LDS loads (16 bytes,
 // two doubles of one k-row per lane).  With 128 columns one wave's load fills
 // one k-row of the stage; with 64 columns each half-wave fills one row (the
-// load's LDS address is the wave's base plus 16 bytes per lane index).
+// load's LDS address is the wave's base plus 16 bytes per lane index): one
+// wave load for the row pair when the rows are unpadded (and so adjacent),
+// else two half-wave loads.  count() is the number of loads a wave issues
+// per slice, which the main loop's waits rely on.
 // The rows' padding stays untouched.  Rows at or past K read zeros; a column
 // pair that does not exist reads column 0 (its outputs are never stored).
 // Needs 16-byte aligned rows and even column offsets.
@@ -579,13 +584,21 @@ struct XcDma64 {
     const bool ok = off(2 * (int)(threadIdx.x & (BX / 2 - 1)), o);
     col = base + (ok ? o : 0);
   }
-  __device__ int count() const { return UPW * RPI; }
+  // unpadded 64-column rows: the two rows of a pair are one contiguous 1 KB
+  // destination, filled by one wave load
+  static constexpr bool kPair = BX == 64 && STRIDE == 512;
+  __device__ int count() const { return kPair ? UPW : UPW * RPI; }
   __device__ void issue(int kt, lds_char* S) const {
     const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
 #pragma unroll
     for (int j = 0; j < UPW; ++j) {
       const int g = w + j * NW;   // row group
-      if constexpr (BX == 128) {
+      if constexpr (kPair) {
+        const int k = kt * BK + 2 * g + (lane >> 5);
+        const double* src = k < K ? col + (long)k * ld : kDmaZeros + 2 * (lane & 31);
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                         (__attribute__((address_space(3))) void*)(S + 2 * g * STRIDE), 16, 0, 0);
+      } else if constexpr (BX == 128) {
         const int k = kt * BK + g;
         const double* src = k < K ? col + (long)k * ld : kDmaZeros + 2 * lane;
         __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
