@@ -37,7 +37,7 @@ HBM_GBS = 8000.0
 # were taken on: a figure is reported only while those sources are unchanged.
 # The runs and their command lines are in profiles/.
 TRAFFIC = {
-    ("half_transform", "c6h12", "fp64"): {"src": "7a1d3b129da9b1cb", "fetch": 1173770972, "write": 348779520,
+    ("half_transform", "c6h12", "fp64"): {"src": "427118243d0bc77d", "fetch": 1173752113, "write": 348779520,
                                          "profile": "profiles/fp64_c6h12_counters.md"},
 }
 
