@@ -14,6 +14,7 @@
 // and reduced in a fixed order, so every result is deterministic.
 #include <math.h>
 
+#include <atomic>
 #include <type_traits>
 
 #include "mfma_engine.hpp"
@@ -1524,16 +1525,16 @@ RIF_TILE_GRID(kao, KaoArgs)
 RIF_TILE_GRID(fock, FockArgs)
 template <int P, class Cfg, class KernelOf>
 static long resident_grid(long n, KernelOf kernel_of) {
-  static int per_cu = 0;
-  if (per_cu == 0) {
-    int v = 0;
+  static std::atomic<int> per_cu{0};   // queried once per kernel; threads may race to store the same value
+  int v = per_cu.load(std::memory_order_relaxed);
+  if (v == 0) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, kernel_of(), Cfg::NT, 0) != hipSuccess || v < 1) {
       (void)hipGetLastError();
       v = 1;
     }
-    per_cu = v;
+    per_cu.store(v, std::memory_order_relaxed);
   }
-  return std::min(n, 256L * per_cu);
+  return std::min(n, 256L * v);
 }
 template <int P, class Cfg>
 static long halfp_grid(const HalfArgs& a) {
