@@ -37,7 +37,7 @@ HBM_GBS = 8000.0
 # were taken on: a figure is reported only while those sources are unchanged.
 # The runs and their command lines are in profiles/.
 TRAFFIC = {
-    ("half_transform", "c6h12", "fp64"): {"src": "427118243d0bc77d", "fetch": 1173752113, "write": 348779520,
+    ("half_transform", "c6h12", "fp64"): {"src": "4eaded17099386bb", "fetch": 1173737881, "write": 348779520,
                                          "profile": "profiles/fp64_c6h12_counters.md"},
 }
 
